@@ -1,0 +1,652 @@
+/*
+ * fmo.c -- FP64 CPU oracle for the preconditioned NCG-MLS field-map estimator
+ * (Lin & Fessler, arXiv 2005.08661).  TEST INFRASTRUCTURE ONLY: used by the
+ * tests, the smoke check and the benchmark's CPU baseline; the HIP product
+ * path neither links nor calls it and shares no code with it.
+ *
+ * What is computed, and where the paper defines it:
+ *   - coil combination and the pair weights r_{cdmnj}, collapsed to the
+ *     coil-combined form R_mn = Gamma_mn conj(zhat_m) zhat_n
+ *     (Sec. II eqs. (cost1), (r), (gamma)); the sum over coil pairs (c,d)
+ *     of the paper's cost differs from the coil-combined cost by a constant
+ *     in omega and has the same gradient;
+ *   - per-voxel cost, gradient and Huber curvature over echo pairs m < n
+ *     (the ordered-pair sum counts each unordered pair twice because Gamma
+ *     is Hermitian, hence the weight 2|R_mn|) (Sec. III-B eqs. (ls_grad),
+ *     (ls_huber), (inner_funs));
+ *   - the first-order finite-difference regulariser (Sec. II eq. (cost));
+ *   - IC(0) of H = D + beta C^T C and the two triangular solves
+ *     (Sec. III-B eqs. (precon_hess), (precon));
+ *   - preconditioned NCG with Polak-Ribiere conjugacy and the monotone line
+ *     search (Sec. III Algorithm, Sec. III-C eqs. (ls_cost), (ls_huber2),
+ *     (ls_update));
+ *   - initialisations of Sec. III-A (eqs. (w0), (w0_wf)).
+ *
+ * Readings taken where the paper is silent or garbled:
+ *   R1 f in Hz, t in seconds, phase 2*pi*f*t; beta multiplies (beta/2)||Cf||^2.
+ *   R3 the gradient carries (t_m - t_n), not its square (derivative of 1-cos).
+ *   R4 "mod pi" is read as wrapping the phase to [-pi, pi]; sinc(0) = 1.
+ *   R5 C has rows only for in-mask neighbour pairs; IC(0) in natural
+ *      (lexicographic, z fastest) or red-black order.
+ *   R6 mu = (g - g_prev)^T p / (g_prev^T p_prev), mu = 0 at i = 0 or when the
+ *      denominator is 0.
+ *   R7 z = -p + mu z_prev, reset to -p when z^T g >= 0.
+ *   R8 the step size restarts from 0 at every outer iteration.
+ *   R9 a fixed number nmls of line-search steps.
+ *   R11 water-fat sweep over [-|df|/2, |df|/2], 100 values, first minimum.
+ *   R12 PWLS by plain CG from the voxelwise estimate.
+ *   R14 angle(0) = 0; zero data gives a zero data term.
+ */
+#include "fmo.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define TWO_PI 6.283185307179586476925286766559
+
+typedef struct {
+  int32_t np;     /* number of echo pairs m < n */
+  double *w;      /* [np][n] 2 |R_mn| */
+  double *a;      /* [np][n] angle(R_mn) */
+  double *d;      /* [np] 2 pi (t_m - t_n) */
+} pairs_t;
+
+static int64_t nvox(const fmo_problem *pb) {
+  return (int64_t)pb->nx * pb->ny * pb->nz;
+}
+
+/* In-mask axis neighbours of voxel j; returns how many. */
+static int neighbours(const fmo_problem *pb, const uint8_t *mask, int64_t j, int64_t nb[6]) {
+  const int64_t nz = pb->nz, ny = pb->ny, nx = pb->nx;
+  const int64_t sy = nz, sx = ny * nz;
+  const int64_t z = j % nz, y = (j / nz) % ny, x = j / sx;
+  int c = 0;
+  if (x > 0 && mask[j - sx]) nb[c++] = j - sx;
+  if (x < nx - 1 && mask[j + sx]) nb[c++] = j + sx;
+  if (y > 0 && mask[j - sy]) nb[c++] = j - sy;
+  if (y < ny - 1 && mask[j + sy]) nb[c++] = j + sy;
+  if (z > 0 && mask[j - 1]) nb[c++] = j - 1;
+  if (z < nz - 1 && mask[j + 1]) nb[c++] = j + 1;
+  return c;
+}
+
+/* Position of voxel j in the elimination order. */
+static int64_t rank_of(const fmo_problem *pb, int64_t j) {
+  if (pb->ordering == FMO_ORDER_REDBLACK) {
+    const int64_t nz = pb->nz, ny = pb->ny;
+    const int64_t z = j % nz, y = (j / nz) % ny, x = j / (ny * nz);
+    return ((x + y + z) & 1) * nvox(pb) + j;
+  }
+  return j;
+}
+
+/* Voxels in elimination order (in-mask only); returns the count. */
+static int64_t build_order(const fmo_problem *pb, const uint8_t *mask, int64_t *order) {
+  const int64_t n = nvox(pb);
+  int64_t c = 0;
+  if (pb->ordering == FMO_ORDER_REDBLACK) {
+    for (int colour = 0; colour < 2; ++colour)
+      for (int64_t j = 0; j < n; ++j)
+        if (mask[j] && rank_of(pb, j) / n == colour) order[c++] = j;
+  } else {
+    for (int64_t j = 0; j < n; ++j)
+      if (mask[j]) order[c++] = j;
+  }
+  return c;
+}
+
+static void cmul_conj(const double *zm, const double *zn, double *re, double *im) {
+  /* conj(zm) * zn */
+  *re = zm[0] * zn[0] + zm[1] * zn[1];
+  *im = zm[0] * zn[1] - zm[1] * zn[0];
+}
+
+/* Precompute the coil-combined pair weights and phases (the paper's
+ * "precompute r and t_m - t_n" step of the Algorithm). */
+static int pairs_build(const fmo_problem *pb, const double *zhat, const uint8_t *mask,
+                       pairs_t *pr) {
+  const int64_t n = nvox(pb);
+  const int L = pb->necho;
+  pr->np = L * (L - 1) / 2;
+  pr->w = (double *)calloc((size_t)pr->np * n, sizeof(double));
+  pr->a = (double *)calloc((size_t)pr->np * n, sizeof(double));
+  pr->d = (double *)calloc((size_t)pr->np, sizeof(double));
+  if (!pr->w || !pr->a || !pr->d) return FMO_ERR_ARG;
+  int q = 0;
+  for (int m = 0; m < L; ++m)
+    for (int k = m + 1; k < L; ++k, ++q) {
+      const double gre = pb->gam[2 * (m * L + k)], gim = pb->gam[2 * (m * L + k) + 1];
+      pr->d[q] = TWO_PI * (pb->te[m] - pb->te[k]);
+      for (int64_t j = 0; j < n; ++j) {
+        if (!mask[j]) continue;
+        double cre, cim;
+        cmul_conj(zhat + 2 * ((int64_t)m * n + j), zhat + 2 * ((int64_t)k * n + j), &cre, &cim);
+        const double rre = gre * cre - gim * cim, rim = gre * cim + gim * cre;
+        pr->w[(int64_t)q * n + j] = 2.0 * hypot(rre, rim);
+        pr->a[(int64_t)q * n + j] = atan2(rim, rre);
+      }
+    }
+  return FMO_OK;
+}
+
+static void pairs_free(pairs_t *pr) {
+  free(pr->w);
+  free(pr->a);
+  free(pr->d);
+}
+
+static double sinc(double u) { return u == 0.0 ? 1.0 : sin(u) / u; }
+
+/* phi_j, dphi_j/df_j and Huber curvature of voxel j at field value fj. */
+static void voxel_terms(const pairs_t *pr, int64_t n, int64_t j, double fj, double *phi,
+                        double *dphi, double *curv) {
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0;
+  for (int q = 0; q < pr->np; ++q) {
+    const double w = pr->w[(int64_t)q * n + j];
+    const double d = pr->d[q];
+    const double x = pr->a[(int64_t)q * n + j] + d * fj;
+    const double u = x - TWO_PI * rint(x / TWO_PI);
+    c0 += w * (1.0 - cos(x));
+    c1 += w * d * sin(x);
+    c2 += w * d * d * sinc(u);
+  }
+  *phi = c0;
+  *dphi = c1;
+  *curv = c2;
+}
+
+int fmo_gamma_fieldmap(int32_t L, double *gam) {
+  if (L < 2 || !gam) return FMO_ERR_ARG;
+  for (int i = 0; i < L * L; ++i) {
+    gam[2 * i] = 1.0 / L;
+    gam[2 * i + 1] = 0.0;
+  }
+  return FMO_OK;
+}
+
+int fmo_gamma_waterfat(int32_t L, const double *te, int32_t npeak, const double *fat_hz,
+                       const double *fat_amp, double *gam) {
+  if (L < 2 || !te || npeak < 1 || !fat_hz || !fat_amp || !gam) return FMO_ERR_ARG;
+  /* gamma is L x 2: column 0 all ones, column 1 c_l. */
+  double *cre = (double *)malloc(sizeof(double) * L), *cim = (double *)malloc(sizeof(double) * L);
+  if (!cre || !cim) return FMO_ERR_ARG;
+  for (int l = 0; l < L; ++l) {
+    cre[l] = 0.0;
+    cim[l] = 0.0;
+    for (int p = 0; p < npeak; ++p) {
+      cre[l] += fat_amp[p] * cos(TWO_PI * fat_hz[p] * te[l]);
+      cim[l] += fat_amp[p] * sin(TWO_PI * fat_hz[p] * te[l]);
+    }
+  }
+  /* G = gamma^H gamma = [[L, sum c], [sum conj c, sum |c|^2]]. */
+  double s_re = 0, s_im = 0, cc = 0;
+  for (int l = 0; l < L; ++l) {
+    s_re += cre[l];
+    s_im += cim[l];
+    cc += cre[l] * cre[l] + cim[l] * cim[l];
+  }
+  const double det = L * cc - (s_re * s_re + s_im * s_im);
+  if (!(det > 0)) {
+    free(cre);
+    free(cim);
+    return FMO_ERR_NOT_PD;
+  }
+  /* G^{-1} = (1/det) [[cc, -sum c], [-sum conj c, L]]. */
+  const double i00 = cc / det, i11 = L / det;
+  const double i01re = -s_re / det, i01im = -s_im / det; /* entry (0,1) */
+  const double i10re = -s_re / det, i10im = s_im / det;  /* entry (1,0) = conj */
+  for (int m = 0; m < L; ++m)
+    for (int k = 0; k < L; ++k) {
+      /* Gamma_mk = sum_ab gamma_ma Ginv_ab conj(gamma_kb), gamma_m0 = 1, gamma_m1 = c_m */
+      double re = i00, im = 0.0;
+      /* a=0, b=1: Ginv_01 conj(c_k) */
+      re += i01re * cre[k] + i01im * cim[k];
+      im += i01im * cre[k] - i01re * cim[k];
+      /* a=1, b=0: c_m Ginv_10 */
+      re += cre[m] * i10re - cim[m] * i10im;
+      im += cre[m] * i10im + cim[m] * i10re;
+      /* a=1, b=1: c_m Ginv_11 conj(c_k) */
+      re += i11 * (cre[m] * cre[k] + cim[m] * cim[k]);
+      im += i11 * (cim[m] * cre[k] - cre[m] * cim[k]);
+      gam[2 * (m * L + k)] = re;
+      gam[2 * (m * L + k) + 1] = im;
+    }
+  free(cre);
+  free(cim);
+  return FMO_OK;
+}
+
+int fmo_combine(int64_t n, int32_t ncoil, int32_t L, const double *y, const double *s,
+                double *zhat) {
+  if (n < 0 || ncoil < 1 || L < 1 || !y || !zhat || (!s && ncoil != 1)) return FMO_ERR_ARG;
+  for (int64_t j = 0; j < n; ++j) {
+    double ss = 0.0;
+    for (int c = 0; c < ncoil; ++c) {
+      const double sre = s ? s[2 * ((int64_t)c * n + j)] : 1.0;
+      const double sim = s ? s[2 * ((int64_t)c * n + j) + 1] : 0.0;
+      ss += sre * sre + sim * sim;
+    }
+    for (int l = 0; l < L; ++l) {
+      double re = 0.0, im = 0.0;
+      for (int c = 0; c < ncoil; ++c) {
+        const double sre = s ? s[2 * ((int64_t)c * n + j)] : 1.0;
+        const double sim = s ? s[2 * ((int64_t)c * n + j) + 1] : 0.0;
+        const double *yy = y + 2 * (((int64_t)c * L + l) * n + j);
+        re += sre * yy[0] + sim * yy[1];
+        im += sre * yy[1] - sim * yy[0];
+      }
+      const double sc = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+      zhat[2 * ((int64_t)l * n + j)] = re * sc;
+      zhat[2 * ((int64_t)l * n + j) + 1] = im * sc;
+    }
+  }
+  return FMO_OK;
+}
+
+int fmo_init_fieldmap(int64_t n, int32_t L, const double *zhat, const double *te,
+                      const uint8_t *mask, double *f0) {
+  if (L < 2 || !zhat || !te || !mask || !f0) return FMO_ERR_ARG;
+  if (te[1] == te[0]) return FMO_ERR_ARG;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!mask[j]) {
+      f0[j] = 0.0;
+      continue;
+    }
+    double re, im;
+    cmul_conj(zhat + 2 * j, zhat + 2 * (n + j), &re, &im);
+    f0[j] = atan2(im, re) / (TWO_PI * (te[1] - te[0]));
+  }
+  return FMO_OK;
+}
+
+static int check_pb(const fmo_problem *pb) {
+  if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 1 || pb->necho < 2 || !pb->te || !pb->gam ||
+      !(pb->beta >= 0) || pb->nmls < 1 || pb->niter < 0)
+    return FMO_ERR_ARG;
+  return FMO_OK;
+}
+
+int fmo_data_term(const fmo_problem *pb, const double *zhat, const uint8_t *mask,
+                  const double *f, double *phi, double *dphi, double *curv) {
+  if (check_pb(pb) || !zhat || !mask || !f) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  pairs_t pr;
+  if (pairs_build(pb, zhat, mask, &pr)) return FMO_ERR_ARG;
+  for (int64_t j = 0; j < n; ++j) {
+    double a = 0, b = 0, c = 0;
+    if (mask[j]) voxel_terms(&pr, n, j, f[j], &a, &b, &c);
+    if (phi) phi[j] = a;
+    if (dphi) dphi[j] = b;
+    if (curv) curv[j] = c;
+  }
+  pairs_free(&pr);
+  return FMO_OK;
+}
+
+int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, double *out) {
+  if (check_pb(pb) || !mask || !f || !out) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  int64_t nb[6];
+  for (int64_t j = 0; j < n; ++j) {
+    double s = 0.0;
+    if (mask[j]) {
+      const int c = neighbours(pb, mask, j, nb);
+      for (int k = 0; k < c; ++k) s += f[j] - f[nb[k]];
+    }
+    out[j] = s;
+  }
+  return FMO_OK;
+}
+
+int fmo_factor(const fmo_problem *pb, const uint8_t *mask, const double *curv, double *piv) {
+  if (check_pb(pb) || !mask || !curv || !piv) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  if (!order) return FMO_ERR_ARG;
+  const int64_t cnt = build_order(pb, mask, order);
+  const double b = pb->beta;
+  int64_t nb[6];
+  int st = FMO_OK;
+  for (int64_t j = 0; j < n; ++j) piv[j] = 0.0;
+  for (int64_t q = 0; q < cnt; ++q) {
+    const int64_t j = order[q];
+    const int c = neighbours(pb, mask, j, nb);
+    const int64_t rj = rank_of(pb, j);
+    double s = 0.0;
+    for (int k = 0; k < c; ++k)
+      if (rank_of(pb, nb[k]) < rj) s += 1.0 / piv[nb[k]];
+    piv[j] = curv[j] + b * c - b * b * s;
+    if (!(piv[j] > 0.0)) {
+      st = isfinite(piv[j]) ? FMO_ERR_NOT_PD : FMO_ERR_NONFINITE;
+      break;
+    }
+  }
+  free(order);
+  return st;
+}
+
+int fmo_apply(const fmo_problem *pb, const uint8_t *mask, const double *piv, const double *g,
+              double *p) {
+  if (check_pb(pb) || !mask || !piv || !g || !p) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  double *x = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  if (!order || !x) return FMO_ERR_ARG;
+  const int64_t cnt = build_order(pb, mask, order);
+  const double b = pb->beta;
+  int64_t nb[6];
+  /* forward: (P + E) x = g, E = strictly lower part of H (entries -beta) */
+  for (int64_t q = 0; q < cnt; ++q) {
+    const int64_t j = order[q];
+    const int c = neighbours(pb, mask, j, nb);
+    const int64_t rj = rank_of(pb, j);
+    double s = g[j];
+    for (int k = 0; k < c; ++k)
+      if (rank_of(pb, nb[k]) < rj) s += b * x[nb[k]];
+    x[j] = s / piv[j];
+  }
+  /* backward: (P + E^T) p = P x */
+  for (int64_t j = 0; j < n; ++j) p[j] = 0.0;
+  for (int64_t q = cnt - 1; q >= 0; --q) {
+    const int64_t j = order[q];
+    const int c = neighbours(pb, mask, j, nb);
+    const int64_t rj = rank_of(pb, j);
+    double s = 0.0;
+    for (int k = 0; k < c; ++k)
+      if (rank_of(pb, nb[k]) > rj) s += p[nb[k]];
+    p[j] = x[j] + b * s / piv[j];
+  }
+  free(order);
+  free(x);
+  return FMO_OK;
+}
+
+static double dot_mask(const uint8_t *mask, int64_t n, const double *a, const double *b) {
+  double s = 0.0;
+  for (int64_t j = 0; j < n; ++j)
+    if (mask[j]) s += a[j] * b[j];
+  return s;
+}
+
+/* Psi at f + alpha z using precomputed pairs (z may be NULL). */
+static double cost_at(const fmo_problem *pb, const pairs_t *pr, const uint8_t *mask,
+                      const double *f, const double *z, double alpha, double *tmp, double *lap) {
+  const int64_t n = nvox(pb);
+  double phi_sum = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    tmp[j] = mask[j] ? f[j] + (z ? alpha * z[j] : 0.0) : 0.0;
+    if (mask[j]) {
+      double a, b, c;
+      voxel_terms(pr, n, j, tmp[j], &a, &b, &c);
+      phi_sum += a;
+    }
+  }
+  fmo_laplacian(pb, mask, tmp, lap);
+  return phi_sum + 0.5 * pb->beta * dot_mask(mask, n, tmp, lap);
+}
+
+int fmo_cost(const fmo_problem *pb, const double *zhat, const uint8_t *mask, const double *f,
+             double *psi) {
+  if (check_pb(pb) || !zhat || !mask || !f || !psi) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  pairs_t pr;
+  if (pairs_build(pb, zhat, mask, &pr)) return FMO_ERR_ARG;
+  double *tmp = (double *)malloc(sizeof(double) * (size_t)n);
+  double *lap = (double *)malloc(sizeof(double) * (size_t)n);
+  *psi = cost_at(pb, &pr, mask, f, NULL, 0.0, tmp, lap);
+  free(tmp);
+  free(lap);
+  pairs_free(&pr);
+  return FMO_OK;
+}
+
+int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, const double *f0,
+              double *f, double *trace, double *mls) {
+  if (check_pb(pb) || !zhat || !mask || !f0 || !f) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  const double beta = pb->beta;
+  pairs_t pr;
+  if (pairs_build(pb, zhat, mask, &pr)) return FMO_ERR_ARG;
+  const size_t nb = sizeof(double) * (size_t)(n ? n : 1);
+  double *dphi = (double *)malloc(nb), *curv = (double *)malloc(nb), *g = (double *)malloc(nb);
+  double *gprev = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  double *zprev = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  double *p = (double *)malloc(nb), *z = (double *)malloc(nb), *piv = (double *)malloc(nb);
+  double *lap = (double *)malloc(nb), *lapz = (double *)malloc(nb), *tmp = (double *)malloc(nb);
+  double *tmp2 = (double *)malloc(nb);
+  int st = FMO_OK;
+  for (int64_t j = 0; j < n; ++j) f[j] = mask[j] ? f0[j] : 0.0;
+  double gtp_prev = 0.0;
+  int64_t nbr[6];
+
+  for (int it = 0; it < pb->niter; ++it) {
+    /* gradient g = grad Phi + beta C^T C f, and the Huber curvature D */
+    double phi_sum = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+      double a = 0, b = 0, c = 0;
+      if (mask[j]) voxel_terms(&pr, n, j, f[j], &a, &b, &c);
+      phi_sum += a;
+      dphi[j] = b;
+      curv[j] = c;
+    }
+    fmo_laplacian(pb, mask, f, lap);
+    for (int64_t j = 0; j < n; ++j) g[j] = mask[j] ? dphi[j] + beta * lap[j] : 0.0;
+    const double cost = phi_sum + 0.5 * beta * dot_mask(mask, n, f, lap);
+
+    /* precondition p = P^{-1} g */
+    if (pb->precond == FMO_PRECOND_IC0) {
+      st = fmo_factor(pb, mask, curv, piv);
+      if (st) break;
+      fmo_apply(pb, mask, piv, g, p);
+    } else if (pb->precond == FMO_PRECOND_DIAG) {
+      for (int64_t j = 0; j < n; ++j) {
+        if (!mask[j]) {
+          p[j] = 0.0;
+          continue;
+        }
+        const double h = curv[j] + beta * neighbours(pb, mask, j, nbr);
+        if (!(h > 0.0)) {
+          st = FMO_ERR_NOT_PD;
+          break;
+        }
+        p[j] = g[j] / h;
+      }
+      if (st) break;
+    } else {
+      for (int64_t j = 0; j < n; ++j) p[j] = g[j];
+    }
+
+    /* Polak-Ribiere conjugacy and the search direction */
+    const double gtp = dot_mask(mask, n, g, p);
+    double mu = 0.0;
+    if (it > 0 && gtp_prev != 0.0) mu = (gtp - dot_mask(mask, n, gprev, p)) / gtp_prev;
+    double ztg = -gtp + mu * dot_mask(mask, n, zprev, g);
+    int restart = 0;
+    if (ztg >= 0.0) {
+      mu = 0.0;
+      ztg = -gtp;
+      restart = 1;
+    }
+    for (int64_t j = 0; j < n; ++j) z[j] = mask[j] ? -p[j] + mu * zprev[j] : 0.0;
+
+    /* monotone line search on f(alpha) = Psi(f + alpha z) */
+    fmo_laplacian(pb, mask, z, lapz);
+    const double A = dot_mask(mask, n, z, lap);   /* z^T C^T C f */
+    const double B = dot_mask(mask, n, z, lapz);  /* ||C z||^2   */
+    double alpha = 0.0;
+    if (mls) mls[(int64_t)it * (pb->nmls + 1)] = cost;
+    for (int k = 0; k < pb->nmls; ++k) {
+      double s1 = 0.0, s2 = 0.0;
+      if (k == 0) {
+        for (int64_t j = 0; j < n; ++j)
+          if (mask[j]) {
+            s1 += z[j] * dphi[j];
+            s2 += z[j] * z[j] * curv[j];
+          }
+      } else {
+        for (int64_t j = 0; j < n; ++j)
+          if (mask[j]) {
+            double a, b, c;
+            voxel_terms(&pr, n, j, f[j] + alpha * z[j], &a, &b, &c);
+            s1 += z[j] * b;
+            s2 += z[j] * z[j] * c;
+          }
+      }
+      const double den = s2 + beta * B;
+      if (!(den > 0.0)) {
+        if (mls)
+          for (int kk = k; kk < pb->nmls; ++kk)
+            mls[(int64_t)it * (pb->nmls + 1) + kk + 1] =
+                mls[(int64_t)it * (pb->nmls + 1) + kk];
+        break;
+      }
+      alpha = alpha - (s1 + beta * A + alpha * beta * B) / den;
+      if (mls) mls[(int64_t)it * (pb->nmls + 1) + k + 1] = cost_at(pb, &pr, mask, f, z, alpha, tmp, tmp2);
+    }
+    if (!isfinite(alpha)) {
+      st = FMO_ERR_NONFINITE;
+      break;
+    }
+    if (trace) {
+      double *t = trace + (int64_t)it * FMO_TR_W;
+      t[FMO_TR_COST] = cost;
+      t[FMO_TR_GTP] = gtp;
+      t[FMO_TR_MU] = mu;
+      t[FMO_TR_RESTART] = restart;
+      t[FMO_TR_ALPHA] = alpha;
+      t[FMO_TR_ZTG] = ztg;
+      t[FMO_TR_B] = B;
+      t[FMO_TR_GNORM2] = dot_mask(mask, n, g, g);
+    }
+    for (int64_t j = 0; j < n; ++j) {
+      if (mask[j]) f[j] += alpha * z[j];
+      gprev[j] = g[j];
+      zprev[j] = z[j];
+    }
+    gtp_prev = gtp;
+  }
+  if (trace && st == FMO_OK) {
+    double *t = trace + (int64_t)pb->niter * FMO_TR_W;
+    for (int c = 0; c < FMO_TR_W; ++c) t[c] = 0.0;
+    t[FMO_TR_COST] = cost_at(pb, &pr, mask, f, NULL, 0.0, tmp, tmp2);
+  }
+  free(dphi);
+  free(curv);
+  free(g);
+  free(gprev);
+  free(zprev);
+  free(p);
+  free(z);
+  free(piv);
+  free(lap);
+  free(lapz);
+  free(tmp);
+  free(tmp2);
+  pairs_free(&pr);
+  return st;
+}
+
+int fmo_init_waterfat_sweep(const fmo_problem *pb, const double *zhat, const uint8_t *mask,
+                            double dfat_hz, int32_t nsweep, double *ftilde) {
+  if (check_pb(pb) || !zhat || !mask || !ftilde || nsweep < 2) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  pairs_t pr;
+  if (pairs_build(pb, zhat, mask, &pr)) return FMO_ERR_ARG;
+  const double h = fabs(dfat_hz) / 2.0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!mask[j]) {
+      ftilde[j] = 0.0;
+      continue;
+    }
+    double best = INFINITY, bestf = 0.0;
+    for (int s = 0; s < nsweep; ++s) {
+      const double fs = -h + 2.0 * h * s / (nsweep - 1);
+      double a, b, c;
+      voxel_terms(&pr, n, j, fs, &a, &b, &c);
+      if (a < best) {
+        best = a;
+        bestf = fs;
+      }
+    }
+    ftilde[j] = bestf;
+  }
+  pairs_free(&pr);
+  return FMO_OK;
+}
+
+int fmo_pwls_weights(int64_t n, int32_t ncoil, int32_t L, const double *y, const double *s,
+                     const double *gam, double *rho) {
+  if (n < 0 || ncoil < 1 || L < 2 || !y || !gam || !rho || (!s && ncoil != 1))
+    return FMO_ERR_ARG;
+  double *a = (double *)malloc(sizeof(double) * L);
+  if (!a) return FMO_ERR_ARG;
+  for (int64_t j = 0; j < n; ++j) {
+    double ss = 0.0;
+    for (int c = 0; c < ncoil; ++c) {
+      const double sre = s ? s[2 * ((int64_t)c * n + j)] : 1.0;
+      const double sim = s ? s[2 * ((int64_t)c * n + j) + 1] : 0.0;
+      ss += sre * sre + sim * sim;
+    }
+    for (int l = 0; l < L; ++l) {
+      a[l] = 0.0;
+      for (int c = 0; c < ncoil; ++c) {
+        const double sm = s ? hypot(s[2 * ((int64_t)c * n + j)], s[2 * ((int64_t)c * n + j) + 1])
+                            : 1.0;
+        const double *yy = y + 2 * (((int64_t)c * L + l) * n + j);
+        a[l] += sm * hypot(yy[0], yy[1]);
+      }
+    }
+    double r = 0.0;
+    for (int m = 0; m < L; ++m)
+      for (int k = 0; k < L; ++k)
+        r += hypot(gam[2 * (m * L + k)], gam[2 * (m * L + k) + 1]) * a[m] * a[k];
+    rho[j] = ss > 0.0 ? r / ss : 0.0;
+  }
+  free(a);
+  return FMO_OK;
+}
+
+/* out = (2 diag(rho) + beta L) v over the mask */
+static void pwls_apply(const fmo_problem *pb, const uint8_t *mask, const double *rho,
+                       const double *v, double *lap, double *out) {
+  const int64_t n = nvox(pb);
+  fmo_laplacian(pb, mask, v, lap);
+  for (int64_t j = 0; j < n; ++j) out[j] = mask[j] ? 2.0 * rho[j] * v[j] + pb->beta * lap[j] : 0.0;
+}
+
+int fmo_pwls_cg(const fmo_problem *pb, const uint8_t *mask, const double *rho,
+                const double *ftilde, int32_t niters, double *f) {
+  if (check_pb(pb) || !mask || !rho || !ftilde || !f || niters < 0) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  const size_t nb = sizeof(double) * (size_t)(n ? n : 1);
+  double *r = (double *)malloc(nb), *d = (double *)malloc(nb), *ad = (double *)malloc(nb);
+  double *lap = (double *)malloc(nb);
+  for (int64_t j = 0; j < n; ++j) f[j] = mask[j] ? ftilde[j] : 0.0;
+  pwls_apply(pb, mask, rho, f, lap, ad);
+  for (int64_t j = 0; j < n; ++j) {
+    r[j] = mask[j] ? 2.0 * rho[j] * ftilde[j] - ad[j] : 0.0;
+    d[j] = r[j];
+  }
+  double rs = dot_mask(mask, n, r, r);
+  for (int it = 0; it < niters; ++it) {
+    pwls_apply(pb, mask, rho, d, lap, ad);
+    const double dad = dot_mask(mask, n, d, ad);
+    if (!(dad > 0.0)) break;
+    const double a = rs / dad;
+    for (int64_t j = 0; j < n; ++j) {
+      f[j] += a * d[j];
+      r[j] -= a * ad[j];
+    }
+    const double rs2 = dot_mask(mask, n, r, r);
+    const double bb = rs2 / rs;
+    for (int64_t j = 0; j < n; ++j) d[j] = r[j] + bb * d[j];
+    rs = rs2;
+    if (rs == 0.0) break;
+  }
+  free(r);
+  free(d);
+  free(ad);
+  free(lap);
+  return FMO_OK;
+}

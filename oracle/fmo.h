@@ -1,0 +1,132 @@
+/*
+ * fmo.h -- FP64 CPU oracle for the preconditioned NCG-MLS field-map estimator
+ * of Lin & Fessler, "Efficient Regularized Field Map Estimation in 3D MRI"
+ * (arXiv 2005.08661).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, obviously-correct
+ * reference used by the tests, by the smoke check and by the benchmark's CPU
+ * baseline.  The product path (the HIP library) never links, loads or calls
+ * it, and it shares no code, header or table with that path.
+ *
+ * Conventions (all host pointers, all FP64):
+ *   - volumes are nx*ny*nz voxels, z fastest: j = (x*ny + y)*nz + z;
+ *   - complex arrays are interleaved (re, im) doubles;
+ *   - the field map f is in Hz and echo times in seconds, so the phase of
+ *     echo l is 2*pi*f*t_l (Sec. II eq. (model) with omega = 2*pi*f);
+ *   - beta multiplies (beta/2)*||C f||^2 with f in Hz (Sec. II eq. (cost));
+ *   - C is the first-order finite difference over the three axes, with a row
+ *     only for pairs of axis neighbours that are both inside the mask, so
+ *     C^T C is the graph Laplacian of the mask;
+ *   - voxels outside the mask are fixed at f = 0 and excluded everywhere.
+ *
+ * Parity pins and the readings taken where the paper is silent are listed in
+ * the header comment of fmo.c.
+ *
+ * Every function returns FMO_OK (0) or a nonzero error code.
+ */
+#ifndef FMO_H
+#define FMO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { FMO_OK = 0, FMO_ERR_ARG = 1, FMO_ERR_NOT_PD = 5, FMO_ERR_NONFINITE = 6 };
+enum { FMO_ORDER_NATURAL = 0, FMO_ORDER_REDBLACK = 1 };
+enum { FMO_PRECOND_IC0 = 0, FMO_PRECOND_DIAG = 1, FMO_PRECOND_NONE = 2 };
+
+/* Columns of the per-iteration trace written by fmo_solve. */
+enum {
+  FMO_TR_COST = 0,    /* Psi(f^i) before the update of iteration i            */
+  FMO_TR_GTP = 1,     /* g^T p                                                */
+  FMO_TR_MU = 2,      /* Polak-Ribiere mu actually used (0 on restart)        */
+  FMO_TR_RESTART = 3, /* 1 if the direction was reset to -p                   */
+  FMO_TR_ALPHA = 4,   /* final step size of the monotone line search          */
+  FMO_TR_ZTG = 5,     /* z^T g of the direction used                          */
+  FMO_TR_B = 6,       /* ||C z||^2                                            */
+  FMO_TR_GNORM2 = 7,  /* ||g||^2                                              */
+  FMO_TR_W = 8
+};
+
+typedef struct {
+  int32_t nx, ny, nz;   /* grid, z fastest */
+  int32_t necho;        /* L >= 2 */
+  const double *te;     /* [L] echo times, seconds */
+  const double *gam;    /* [L*L] interleaved complex, row-major Gamma_{mn} */
+  double beta;          /* >= 0 */
+  int32_t niter;        /* outer NCG iterations */
+  int32_t nmls;         /* line-search steps per outer iteration, >= 1 */
+  int32_t ordering;     /* FMO_ORDER_* (IC(0) ordering) */
+  int32_t precond;      /* FMO_PRECOND_* */
+} fmo_problem;
+
+/* Gamma = gamma (gamma^H gamma)^{-1} gamma^H, Sec. II eq. (gamma).
+ * Field-map case: gamma = 1 (Gamma_mn = 1/L). */
+int fmo_gamma_fieldmap(int32_t L, double *gam);
+/* Water-fat case: gamma = [1, c], c_l = sum_p amp_p exp(i 2 pi hz_p t_l). */
+int fmo_gamma_waterfat(int32_t L, const double *te, int32_t npeak, const double *fat_hz,
+                       const double *fat_amp, double *gam);
+
+/* Coil combination zhat_l = sum_c conj(s_c) y_cl / sqrt(sum_c |s_c|^2)
+ * (0 where the sum of squares is 0).  y: [ncoil][L][n], s: [ncoil][n] or NULL
+ * for s = 1 (then ncoil must be 1).  zhat: [L][n]. */
+int fmo_combine(int64_t n, int32_t ncoil, int32_t L, const double *y, const double *s,
+                double *zhat);
+
+/* Field-map initialisation, Sec. III-A eq. (w0), in Hz; 0 outside the mask. */
+int fmo_init_fieldmap(int64_t n, int32_t L, const double *zhat, const double *te,
+                      const uint8_t *mask, double *f0);
+
+/* Per-voxel data term at f (Sec. II eq. (cost1), Sec. III-B eqs. (ls_grad),
+ * (ls_huber), (inner_funs)): phi_j, dphi_j/df_j and the Huber curvature d_j.
+ * Any output may be NULL.  Outside the mask all three are 0. */
+int fmo_data_term(const fmo_problem *pb, const double *zhat, const uint8_t *mask,
+                  const double *f, double *phi, double *dphi, double *curv);
+
+/* (C^T C f)_j over the mask graph. */
+int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, double *out);
+
+/* Incomplete Cholesky IC(0) of H = diag(curv) + beta C^T C in the problem's
+ * ordering, sqrt-free form M = (P + E) P^{-1} (P + E^T) (Sec. III-B eq.
+ * (precon)): piv[j] = pivot P_jj (0 outside the mask).  Returns FMO_ERR_NOT_PD
+ * if a pivot is not positive. */
+int fmo_factor(const fmo_problem *pb, const uint8_t *mask, const double *curv, double *piv);
+
+/* p = M^{-1} g by forward then backward substitution with the IC(0) factor. */
+int fmo_apply(const fmo_problem *pb, const uint8_t *mask, const double *piv, const double *g,
+              double *p);
+
+/* Full preconditioned NCG with monotone line search (Sec. III, Algorithm).
+ * f0: initial map (Hz); f: output map.  trace: [niter+1][FMO_TR_W] or NULL
+ * (row niter holds only the final cost).  mls: [niter][nmls+1] or NULL; if
+ * given, the cost f(alpha_k) along the line is recorded for every line-search
+ * step (extra cost evaluations used only for the monotonicity checks). */
+int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, const double *f0,
+              double *f, double *trace, double *mls);
+
+/* Total cost Psi(f) = sum_j phi_j + (beta/2) f^T C^T C f. */
+int fmo_cost(const fmo_problem *pb, const double *zhat, const uint8_t *mask, const double *f,
+             double *psi);
+
+/* Water-fat initialisation (Sec. III-A): per-voxel sweep of nsweep equispaced
+ * values over [-|dfat|/2, |dfat|/2] (ends included), keeping the one of least
+ * per-voxel cost (first on ties). */
+int fmo_init_waterfat_sweep(const fmo_problem *pb, const double *zhat, const uint8_t *mask,
+                            double dfat_hz, int32_t nsweep, double *ftilde);
+
+/* PWLS weights rho_j = sum_{m,n} sum_{c,d} |r_cdmnj| (Sec. III-A, after eq.
+ * (w0_wf)), from the raw images and coil maps. */
+int fmo_pwls_weights(int64_t n, int32_t ncoil, int32_t L, const double *y, const double *s,
+                     const double *gam, double *rho);
+
+/* niters plain CG iterations on (2 diag(rho) + beta C^T C) f = 2 rho ftilde
+ * from f = ftilde (eq. (w0_wf)). */
+int fmo_pwls_cg(const fmo_problem *pb, const uint8_t *mask, const double *rho,
+                const double *ftilde, int32_t niters, double *f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

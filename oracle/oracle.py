@@ -1,0 +1,233 @@
+"""ctypes binding of the FP64 C oracle (fmo.c).
+
+Test infrastructure only (tests, smoke check, benchmark CPU baseline).  Every
+array is converted to contiguous float64 / complex128 / uint8 before the call;
+volumes are (nx, ny, nz) C-ordered, z fastest.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libfmo.so")
+_lib = None
+
+NATURAL, REDBLACK = 0, 1
+IC0, DIAG, NONE = 0, 1, 2
+TR = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)
+TR_W = 8
+ERRORS = {1: "bad argument", 5: "not positive definite", 6: "non-finite value"}
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class _Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("necho", C.c_int32),
+                ("te", C.c_void_p), ("gam", C.c_void_p), ("beta", C.c_double),
+                ("niter", C.c_int32), ("nmls", C.c_int32), ("ordering", C.c_int32),
+                ("precond", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIBPATH):
+            from . import build as _b
+            _b.build()
+        _lib = C.CDLL(_LIBPATH)
+    return _lib
+
+
+def _p(a):
+    return C.c_void_p(a.ctypes.data) if a is not None else C.c_void_p(0)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _c128(a):
+    return np.ascontiguousarray(a, dtype=np.complex128)
+
+
+def _u8(a):
+    return np.ascontiguousarray(a, dtype=np.uint8)
+
+
+def _check(st):
+    if st != 0:
+        raise OracleError("oracle error %d: %s" % (st, ERRORS.get(st, "?")))
+
+
+class Problem:
+    """Geometry and parameters of one solve (mirrors fmo_problem)."""
+
+    def __init__(self, shape, te, gamma, beta, niter=10, nmls=3, ordering=NATURAL, precond=IC0):
+        self.shape = tuple(int(s) for s in shape)
+        self.te = _f64(te)
+        self.gamma = _c128(gamma)
+        self.beta = float(beta)
+        self.niter = int(niter)
+        self.nmls = int(nmls)
+        self.ordering = int(ordering)
+        self.precond = int(precond)
+
+    def c(self):
+        nx, ny, nz = self.shape
+        s = _Problem(nx, ny, nz, len(self.te), _p(self.te).value, _p(self.gamma).value, self.beta,
+                     self.niter, self.nmls, self.ordering, self.precond)
+        return s
+
+
+def gamma_fieldmap(L):
+    g = np.zeros((L, L), np.complex128)
+    _check(lib().fmo_gamma_fieldmap(C.c_int32(L), _p(g)))
+    return g
+
+
+def gamma_waterfat(te, fat_hz, fat_amp):
+    te, fh, fa = _f64(te), _f64(fat_hz), _f64(fat_amp)
+    L = len(te)
+    g = np.zeros((L, L), np.complex128)
+    _check(lib().fmo_gamma_waterfat(C.c_int32(L), _p(te), C.c_int32(len(fh)), _p(fh), _p(fa), _p(g)))
+    return g
+
+
+def combine(y, sens=None):
+    """y: [ncoil, L, X, Y, Z]; sens: [ncoil, X, Y, Z] or None -> zhat [L, X, Y, Z]."""
+    y = _c128(y)
+    ncoil, L = y.shape[:2]
+    shape = y.shape[2:]
+    n = int(np.prod(shape))
+    s = None if sens is None else _c128(sens)
+    zhat = np.zeros((L,) + shape, np.complex128)
+    _check(lib().fmo_combine(C.c_int64(n), C.c_int32(ncoil), C.c_int32(L), _p(y), _p(s), _p(zhat)))
+    return zhat
+
+
+def init_fieldmap(zhat, te, mask):
+    zhat, te, mask = _c128(zhat), _f64(te), _u8(mask)
+    f0 = np.zeros(mask.shape, np.float64)
+    _check(lib().fmo_init_fieldmap(C.c_int64(mask.size), C.c_int32(zhat.shape[0]), _p(zhat), _p(te),
+                                   _p(mask), _p(f0)))
+    return f0
+
+
+def data_term(pb, zhat, mask, f):
+    zhat, mask, f = _c128(zhat), _u8(mask), _f64(f)
+    phi, dphi, curv = (np.zeros(pb.shape) for _ in range(3))
+    c = pb.c()
+    _check(lib().fmo_data_term(C.byref(c), _p(zhat), _p(mask), _p(f), _p(phi), _p(dphi), _p(curv)))
+    return phi, dphi, curv
+
+
+def laplacian(pb, mask, f):
+    mask, f = _u8(mask), _f64(f)
+    out = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_laplacian(C.byref(c), _p(mask), _p(f), _p(out)))
+    return out
+
+
+def factor(pb, mask, curv):
+    mask, curv = _u8(mask), _f64(curv)
+    piv = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_factor(C.byref(c), _p(mask), _p(curv), _p(piv)))
+    return piv
+
+
+def apply(pb, mask, piv, g):
+    mask, piv, g = _u8(mask), _f64(piv), _f64(g)
+    p = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_apply(C.byref(c), _p(mask), _p(piv), _p(g), _p(p)))
+    return p
+
+
+def cost(pb, zhat, mask, f):
+    zhat, mask, f = _c128(zhat), _u8(mask), _f64(f)
+    out = C.c_double(0.0)
+    c = pb.c()
+    _check(lib().fmo_cost(C.byref(c), _p(zhat), _p(mask), _p(f), C.byref(out)))
+    return out.value
+
+
+def solve(pb, zhat, mask, f0, want_mls=False):
+    """Run the NCG-MLS iteration; returns (f, trace[niter+1, TR_W], mls or None)."""
+    zhat, mask, f0 = _c128(zhat), _u8(mask), _f64(f0)
+    f = np.zeros(pb.shape)
+    trace = np.zeros((pb.niter + 1, TR_W))
+    mls = np.zeros((max(pb.niter, 1), pb.nmls + 1)) if want_mls else None
+    c = pb.c()
+    _check(lib().fmo_solve(C.byref(c), _p(zhat), _p(mask), _p(f0), _p(f), _p(trace), _p(mls)))
+    return f, trace, mls
+
+
+def init_waterfat_sweep(pb, zhat, mask, dfat_hz, nsweep=100):
+    zhat, mask = _c128(zhat), _u8(mask)
+    out = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_init_waterfat_sweep(C.byref(c), _p(zhat), _p(mask), C.c_double(dfat_hz),
+                                         C.c_int32(nsweep), _p(out)))
+    return out
+
+
+def pwls_weights(y, sens, gamma):
+    y = _c128(y)
+    ncoil, L = y.shape[:2]
+    shape = y.shape[2:]
+    s = None if sens is None else _c128(sens)
+    g = _c128(gamma)
+    rho = np.zeros(shape)
+    _check(lib().fmo_pwls_weights(C.c_int64(int(np.prod(shape))), C.c_int32(ncoil), C.c_int32(L),
+                                  _p(y), _p(s), _p(g), _p(rho)))
+    return rho
+
+
+def pwls_cg(pb, mask, rho, ftilde, niters=10):
+    mask, rho, ftilde = _u8(mask), _f64(rho), _f64(ftilde)
+    out = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_pwls_cg(C.byref(c), _p(mask), _p(rho), _p(ftilde), C.c_int32(niters), _p(out)))
+    return out
+
+
+# --- whole pipeline for a synthetic volume --------------------------------------
+
+def problem_for(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, beta=None):
+    if vol.model == "waterfat":
+        gam = gamma_waterfat(vol.te, vol.fat_hz, vol.fat_amp)
+    else:
+        gam = gamma_fieldmap(vol.necho)
+    return Problem(vol.shape, vol.te, gam, vol.beta if beta is None else beta,
+                   vol.niter if niter is None else niter, vol.nmls if nmls is None else nmls,
+                   ordering, precond)
+
+
+def largest_fat_offset(vol):
+    return float(vol.fat_hz[int(np.argmax(vol.fat_amp))])
+
+
+def initial_map(vol, pb, zhat, pwls_iters=10, nsweep=100):
+    """Sec. III-A initialisation: eq. (w0) for field maps, sweep + PWLS for water-fat."""
+    if vol.model == "waterfat":
+        ft = init_waterfat_sweep(pb, zhat, vol.mask, largest_fat_offset(vol), nsweep)
+        rho = pwls_weights(vol.y, vol.sens, pb.gamma)
+        return pwls_cg(pb, vol.mask, rho, ft, pwls_iters)
+    return init_fieldmap(zhat, vol.te, vol.mask)
+
+
+def run_volume(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, f0=None, want_mls=False):
+    """Combine, initialise and solve one synthetic volume with the oracle."""
+    pb = problem_for(vol, ordering, precond, niter, nmls)
+    zhat = combine(vol.y, vol.sens)
+    if f0 is None:
+        f0 = initial_map(vol, pb, zhat)
+    f, trace, mls = solve(pb, zhat, vol.mask, f0, want_mls)
+    return dict(f=f, trace=trace, mls=mls, f0=f0, zhat=zhat, pb=pb)

@@ -1,0 +1,489 @@
+"""Pins of the FP64 oracle to what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the
+paper's literal formulas evaluated by brute force, explicit least squares,
+library routines (numpy/scipy), closed forms, invariants or values printed in
+the paper (tests/golden).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_08661_amd import synth
+from tests.helpers import (dense_hessian_model, diff_matrix, elimination_order, in_mask_edges,
+                           textbook_ic0, wrap)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rand_c(rng, *shape):
+    return rng.normal(size=shape) + 1j * rng.normal(size=shape)
+
+
+def _fm_problem(shape, te, beta, L=None, **kw):
+    L = len(te) if L is None else L
+    return O.Problem(shape, te, O.gamma_fieldmap(L), beta, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Sec. II: cost (cost1) with r (eq. r) -- literal coil-pair sum vs the oracle's
+# coil-combined form.  The two must differ by a constant in omega and have
+# identical gradients.
+# ---------------------------------------------------------------------------
+
+def _literal_cost(y, s, te, gam, f):
+    """Sum over voxels, ordered echo pairs (m,n) and coil pairs (c,d) of
+    |r|(1 - cos(angle r + omega (t_m - t_n))), omega = 2 pi f (eq. cost1)."""
+    ncoil, L = y.shape[:2]
+    tot = 0.0
+    S = (np.abs(s) ** 2).sum(0)
+    for j in range(y.shape[2]):
+        for m in range(L):
+            for n in range(L):
+                for c in range(ncoil):
+                    for d in range(ncoil):
+                        r = gam[m, n] / S[j] * s[c, j] * np.conj(s[d, j]) * np.conj(y[c, m, j]) * y[d, n, j]
+                        tot += abs(r) * (1 - np.cos(np.angle(r) + 2 * np.pi * f[j] * (te[m] - te[n])))
+    return tot
+
+
+@pytest.mark.parametrize("model", ["fieldmap", "waterfat"])
+def test_coil_pair_sum_equals_combined_cost_up_to_constant(model):
+    rng = np.random.default_rng(1)
+    ncoil, L, nvox = 3, 4, 3
+    te = np.array([0.0, 1.1e-3, 2.3e-3, 4.0e-3])
+    y = _rand_c(rng, ncoil, L, nvox)
+    s = _rand_c(rng, ncoil, nvox)
+    if model == "fieldmap":
+        gam = O.gamma_fieldmap(L)
+    else:
+        gam = O.gamma_waterfat(te, synth.FAT_PPM * 127.73, synth.FAT_AMP)
+    pb = O.Problem((1, 1, nvox), te, gam, 0.0)
+    zhat = O.combine(y.reshape(ncoil, L, 1, 1, nvox), s.reshape(ncoil, 1, 1, nvox))
+    mask = np.ones((1, 1, nvox), np.uint8)
+    diffs = []
+    for trial in range(6):
+        f = rng.uniform(-300, 300, nvox)
+        lit = _literal_cost(y, s, te, gam, f)
+        phi, dphi, _ = O.data_term(pb, zhat, mask, f.reshape(1, 1, nvox))
+        diffs.append(lit - phi.sum())
+        # gradient of the literal cost by central differences (h in Hz)
+        h = 1e-5
+        for j in range(nvox):
+            fp, fm = f.copy(), f.copy()
+            fp[j] += h
+            fm[j] -= h
+            gnum = (_literal_cost(y, s, te, gam, fp) - _literal_cost(y, s, te, gam, fm)) / (2 * h)
+            assert abs(gnum - dphi.ravel()[j]) <= 1e-6 * max(1.0, abs(gnum))
+    diffs = np.array(diffs)
+    assert np.ptp(diffs) <= 1e-9 * np.abs(diffs).max()
+
+
+# ---------------------------------------------------------------------------
+# Sec. II: the profile cost (cost1) is min over x of the joint cost (cost2),
+# up to a constant in omega.  Explicit complex least squares per voxel.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("model", ["fieldmap", "waterfat"])
+def test_profile_cost_equals_joint_least_squares(model):
+    rng = np.random.default_rng(2)
+    ncoil, L = 4, 6
+    te = 1.2e-3 + 1.0e-3 * np.arange(L)
+    fat_hz = synth.FAT_PPM * synth.GAMMA_MHZ_PER_T * 3.0
+    y = _rand_c(rng, ncoil, L, 1)
+    s = _rand_c(rng, ncoil, 1)
+    if model == "fieldmap":
+        gam = O.gamma_fieldmap(L)
+        basis = np.ones((L, 1), complex)
+    else:
+        gam = O.gamma_waterfat(te, fat_hz, synth.FAT_AMP)
+        cl = np.array([np.sum(synth.FAT_AMP * np.exp(2j * np.pi * fat_hz * t)) for t in te])
+        basis = np.stack([np.ones(L), cl], 1)  # x_l = basis[l] @ (m_w, m_f)
+    zhat = O.combine(y.reshape(ncoil, L, 1, 1, 1), s.reshape(ncoil, 1, 1, 1))
+    pb = O.Problem((1, 1, 1), te, gam, 0.0)
+    mask = np.ones((1, 1, 1), np.uint8)
+    diffs = []
+    for f in np.linspace(-400, 400, 9):
+        # y_cl = exp(i 2 pi f t_l) s_c x_l  -> stacked linear model in the unknowns
+        A = np.zeros((ncoil * L, basis.shape[1]), complex)
+        b = np.zeros(ncoil * L, complex)
+        for c in range(ncoil):
+            for l in range(L):
+                A[c * L + l] = np.exp(2j * np.pi * f * te[l]) * s[c, 0] * basis[l]
+                b[c * L + l] = y[c, l, 0]
+        xhat = np.linalg.lstsq(A, b, rcond=None)[0]
+        joint = np.sum(np.abs(b - A @ xhat) ** 2)
+        phi, _, _ = O.data_term(pb, zhat, mask, np.full((1, 1, 1), f))
+        diffs.append(joint - phi.sum())
+    diffs = np.array(diffs)
+    assert np.ptp(diffs) <= 1e-10 * max(1.0, np.abs(diffs).max())
+
+
+def test_gamma_is_the_projector_onto_gamma():
+    te = 1.2e-3 + 1.0e-3 * np.arange(6)
+    fat_hz = synth.FAT_PPM * synth.GAMMA_MHZ_PER_T * 3.0
+    cl = np.array([np.sum(synth.FAT_AMP * np.exp(2j * np.pi * fat_hz * t)) for t in te])
+    gmat = np.stack([np.ones(6), cl], 1)
+    G = O.gamma_waterfat(te, fat_hz, synth.FAT_AMP)
+    np.testing.assert_allclose(G, gmat @ np.linalg.pinv(gmat), atol=1e-13)
+    np.testing.assert_allclose(G @ G, G, atol=1e-13)
+    np.testing.assert_allclose(G, G.conj().T, atol=1e-14)
+    assert abs(np.trace(G) - 2) < 1e-12
+    Gf = O.gamma_fieldmap(3)
+    np.testing.assert_allclose(Gf, np.full((3, 3), 1 / 3))
+    assert abs(np.trace(Gf) - 1) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Gradient (ls_grad) and regulariser: central differences of the total cost.
+# ---------------------------------------------------------------------------
+
+def test_gradient_matches_central_differences():
+    vol = synth.random_volume((4, 3, 5), 2, 3, seed=11, beta=0.3, mask_frac=0.8)
+    pb = O.problem_for(vol)
+    zhat = O.combine(vol.y, vol.sens)
+    rng = np.random.default_rng(3)
+    f = rng.uniform(-80, 80, vol.shape) * vol.mask
+    _, dphi, _ = O.data_term(pb, zhat, vol.mask, f)
+    g = dphi + pb.beta * O.laplacian(pb, vol.mask, f)
+    h = 1e-5
+    for j in np.flatnonzero(vol.mask)[:25]:
+        fp, fm = f.copy().ravel(), f.copy().ravel()
+        fp[j] += h
+        fm[j] -= h
+        num = (O.cost(pb, zhat, vol.mask, fp.reshape(vol.shape)) -
+               O.cost(pb, zhat, vol.mask, fm.reshape(vol.shape))) / (2 * h)
+        assert abs(num - g.ravel()[j]) <= 1e-6 * max(1.0, abs(num)), (j, num, g.ravel()[j])
+
+
+def test_laplacian_is_CtC_of_in_mask_differences():
+    rng = np.random.default_rng(4)
+    shape = (5, 4, 6)
+    mask = (rng.uniform(size=shape) < 0.7).astype(np.uint8)
+    f = rng.normal(size=shape) * mask
+    pb = _fm_problem(shape, [0, 1e-3], 1.0)
+    Cm = diff_matrix(mask)
+    np.testing.assert_allclose(O.laplacian(pb, mask, f).ravel(), (Cm.T @ (Cm @ f.ravel())) * mask.ravel(),
+                               atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Huber curvature (ls_huber, inner_funs): the quadratic with curvature d_j
+# majorises the per-voxel cost; with u wrapped to [-pi, pi] (reading R4) it
+# touches at the reflected point, while the literal "mod pi" reading does not
+# majorise.
+# ---------------------------------------------------------------------------
+
+def test_huber_curvature_majorises_voxel_cost():
+    rng = np.random.default_rng(5)
+    vol = synth.random_volume((2, 2, 3), 3, 3, seed=12, beta=0.0)
+    pb = O.problem_for(vol)
+    zhat = O.combine(vol.y, vol.sens)
+    fgrid = np.linspace(-600, 600, 4001)
+    for trial in range(5):
+        f0 = rng.uniform(-300, 300, vol.shape)
+        phi0, d0, c0 = O.data_term(pb, zhat, vol.mask, f0)
+        for fv in fgrid[::40]:
+            phi, _, _ = O.data_term(pb, zhat, vol.mask, np.full(vol.shape, fv))
+            q = phi0 + d0 * (fv - f0) + 0.5 * c0 * (fv - f0) ** 2
+            assert np.all(q >= phi - 1e-9 * (1 + np.abs(phi)))
+
+
+def test_huber_curvature_is_tight_single_pair():
+    # one echo pair: the majoriser must touch the cost at the reflected point
+    te = np.array([0.0, 2e-3])
+    pb = _fm_problem((1, 1, 1), te, 0.0)
+    zhat = np.array([1.0 + 0j, np.exp(0.7j)]).reshape(2, 1, 1, 1)
+    mask = np.ones((1, 1, 1), np.uint8)
+    dd = 2 * np.pi * (te[0] - te[1])
+    n_lit = 0
+    for f0 in [-170.0, -40.0, 13.0, 95.0, 210.0, 120.0]:
+        phi0, d0, c0 = (a.item() for a in O.data_term(pb, zhat, mask, np.full((1, 1, 1), f0)))
+        x0 = 0.7 + dd * f0  # angle(R_01) + 2 pi f (t_0 - t_1)
+        u = wrap(x0)
+        f_touch = f0 - 2 * u / dd
+        phi_t, _, _ = O.data_term(pb, zhat, mask, np.full((1, 1, 1), f_touch))
+        q = phi0 + d0 * (f_touch - f0) + 0.5 * c0 * (f_touch - f0) ** 2
+        assert abs(q - phi_t.item()) < 1e-9
+        # the literal "mod pi" curvature is smaller than the wrapped one for
+        # u in (-pi/2, 0), and then fails to majorise
+        um = np.mod(x0, np.pi)
+        if np.sin(um) / um < np.sin(u) / u - 1e-3:
+            c_lit = dd * dd * np.sin(um) / um  # w = 2|R_01| = 1
+            fs = np.linspace(f0 - 400, f0 + 400, 2001)
+            phis = np.array([O.data_term(pb, zhat, mask, np.full((1, 1, 1), v))[0].item() for v in fs])
+            qlit = phi0 + d0 * (fs - f0) + 0.5 * c_lit * (fs - f0) ** 2
+            assert np.any(qlit < phis - 1e-6)
+            n_lit += 1
+    assert n_lit >= 1
+
+
+# ---------------------------------------------------------------------------
+# Sec. III-B: IC(0) of H = D + beta C^T C (precon_hess, precon).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+def test_ic0_matches_textbook_incomplete_cholesky(ordering):
+    rng = np.random.default_rng(6)
+    shape = (4, 5, 3)
+    mask = (rng.uniform(size=shape) < 0.85).astype(np.uint8)
+    curv = rng.uniform(0, 0.1, shape) * mask
+    beta = 0.1
+    pb = _fm_problem(shape, [0, 1e-3], beta, ordering=ordering)
+    piv = O.factor(pb, mask, curv)
+    g = rng.normal(size=shape) * mask
+    p = O.apply(pb, mask, piv, g)
+    # dense H in elimination order
+    Cm = diff_matrix(mask)
+    Hfull = np.diag(curv.ravel()) + beta * Cm.T @ Cm
+    order = elimination_order(shape, mask, ordering)
+    H = Hfull[np.ix_(order, order)]
+    Lt = textbook_ic0(H)
+    np.testing.assert_allclose(piv.ravel()[order], np.diag(Lt) ** 2, rtol=1e-12)
+    # L L^T matches H on H's nonzero pattern (the defining property of IC(0))
+    M = Lt @ Lt.T
+    pat = H != 0
+    np.testing.assert_allclose(M[pat], H[pat], atol=1e-13)
+    # the preconditioner apply solves L L^T p = g
+    pd = np.linalg.solve(M, g.ravel()[order])
+    np.testing.assert_allclose(p.ravel()[order], pd, rtol=1e-10, atol=1e-12)
+    assert np.all(p.ravel()[mask.ravel() == 0] == 0)
+
+
+def test_ic0_on_a_line_is_exact_cholesky():
+    rng = np.random.default_rng(7)
+    shape = (1, 1, 40)
+    mask = np.ones(shape, np.uint8)
+    curv = rng.uniform(0, 0.1, shape)
+    pb = _fm_problem(shape, [0, 1e-3], 0.1)
+    piv = O.factor(pb, mask, curv)
+    H, _ = dense_hessian_model(mask, curv, 0.1)
+    Lc = np.linalg.cholesky(H)
+    np.testing.assert_allclose(piv.ravel(), np.diag(Lc) ** 2, rtol=1e-13)
+    g = rng.normal(size=shape)
+    p = O.apply(pb, mask, piv, g)
+    np.testing.assert_allclose(p.ravel(), np.linalg.solve(H, g.ravel()), rtol=1e-11)
+
+
+def test_table1_toy_factorization_nonzeros():
+    """Table 1 (20x16x8 toy, d ~ U(0, 0.1), beta = 0.1): nonzero counts of H,
+    H^-1, the complete Cholesky factor L_c and the IC(0) factor L_0."""
+    with open(os.path.join(GOLDEN, "table1_toy_factorization.json")) as fh:
+        gold = json.load(fh)
+    nx, ny, nz = gold["grid_xyz"]
+    # the paper's arrays are column-major (x fastest); with z fastest here the
+    # same elimination order is obtained on the transposed grid (z, y, x).
+    shape = (nz, ny, nx)
+    rng = np.random.default_rng(8)
+    mask = np.ones(shape, np.uint8)
+    curv = rng.uniform(0, 0.1, shape)
+    beta = gold["beta"]
+    H, _ = dense_hessian_model(mask, curv, beta)
+    nnz_H = int(np.count_nonzero(H))
+    Hinv = np.linalg.inv(H)
+    Lc = np.linalg.cholesky(H)
+    pb = _fm_problem(shape, [0, 1e-3], beta)
+    piv = O.factor(pb, mask, curv)
+    n_edges = len(in_mask_edges(mask))
+    nnz_L0 = int(np.count_nonzero(piv)) + n_edges  # pivots plus one entry per lower edge
+    printed = gold["nnz_printed"]
+    scale = gold["nnz_scale"]
+    for key, val in (("H", nnz_H), ("Hinv", int(np.count_nonzero(Hinv))),
+                     ("Lc", int(np.count_nonzero(Lc))), ("L0", nnz_L0)):
+        digits = gold["nnz_decimals"][key]
+        assert round(val / scale, digits) == printed[key], (key, val)
+    # bounds stated with the table: nnz(L_c) >= (Nv - NxNy) NxNy, nnz(L_0) <= 4 Nv
+    Nv, NxNy = nx * ny * nz, nx * ny
+    assert int(np.count_nonzero(Lc)) >= (Nv - NxNy) * NxNy
+    assert nnz_L0 <= 4 * Nv
+    # NRMSE of the complete factor ||I - L^-1 H L^-T||_F / sqrt(Nv) at round-off level
+    Li = np.linalg.inv(Lc)
+    nr = np.linalg.norm(np.eye(Nv) - Li @ H @ Li.T) / np.sqrt(Nv)
+    assert nr < gold["nrmse"]["Lc_max"]
+
+
+def test_ic0_not_pd_reported():
+    # an isolated in-mask voxel with zero curvature has a zero pivot
+    shape = (1, 1, 3)
+    mask = np.array([1, 0, 1], np.uint8).reshape(shape)
+    curv = np.array([0.0, 0.0, 1.0]).reshape(shape)
+    pb = _fm_problem(shape, [0, 1e-3], 0.5)
+    with pytest.raises(O.OracleError):
+        O.factor(pb, mask, curv)
+
+
+# ---------------------------------------------------------------------------
+# Sec. III-A: field-map initialisation (w0) is exact for noise-free data.
+# ---------------------------------------------------------------------------
+
+def test_init_w0_exact_on_noise_free_data():
+    rng = np.random.default_rng(9)
+    shape = (3, 4, 5)
+    te = np.array([0.0, 1.5e-3, 4e-3])
+    f_true = rng.uniform(-300, 300, shape)  # |f dt| < 0.5 for dt = 1.5 ms
+    s = _rand_c(rng, 3, *shape)
+    x = _rand_c(rng, *shape)
+    y = np.stack([np.stack([s[c] * x * np.exp(2j * np.pi * f_true * t) for t in te]) for c in range(3)])
+    zhat = O.combine(y, s)
+    f0 = O.init_fieldmap(zhat, te, np.ones(shape, np.uint8))
+    np.testing.assert_allclose(f0, f_true, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Whole iteration (Algorithm): closed forms, invariants and Newton.
+# ---------------------------------------------------------------------------
+
+def test_single_voxel_two_echoes_beta0_converges_to_phase_difference():
+    te = np.array([0.5e-3, 3.0e-3])
+    zhat = np.array([0.8 * np.exp(0.3j), 1.3 * np.exp(-2.1j)]).reshape(2, 1, 1, 1)
+    mask = np.ones((1, 1, 1), np.uint8)
+    f_star = wrap(-2.1 - 0.3) / (2 * np.pi * (te[1] - te[0]))
+    pb = _fm_problem((1, 1, 1), te, 0.0, niter=30)
+    for df in [-60.0, 35.0, 120.0]:
+        f, tr, _ = O.solve(pb, zhat, mask, np.full((1, 1, 1), f_star + df))
+        assert abs(f.item() - f_star) < 1e-8
+
+
+def test_beta0_separates_into_voxelwise_local_minima():
+    vol = synth.random_volume((3, 3, 2), 2, 3, seed=13, beta=0.0)
+    pb = O.problem_for(vol, niter=60, nmls=3)
+    zhat = O.combine(vol.y, vol.sens)
+    f0 = O.init_fieldmap(zhat, vol.te, vol.mask)
+    f, _, _ = O.solve(pb, zhat, vol.mask, f0)
+    _, dphi, _ = O.data_term(pb, zhat, vol.mask, f)
+    assert np.abs(dphi).max() < 1e-8 * max(1.0, np.abs(dphi).max() + 1)
+    # each voxel sits at a local minimum of its own 1-D cost (dense local grid)
+    for dv in np.linspace(-3, 3, 13):
+        phi_s, _, _ = O.data_term(pb, zhat, vol.mask, f + dv)
+        phi_f, _, _ = O.data_term(pb, zhat, vol.mask, f)
+        assert np.all(phi_s >= phi_f - 1e-12)
+
+
+def _noise_free_constant(shape, beta, L=3, ncoil=2, seed=14, fval=37.5):
+    rng = np.random.default_rng(seed)
+    te = np.array([0.0, 1.0e-3, 2.6e-3])[:L]
+    s = _rand_c(rng, ncoil, *shape)
+    x = 0.5 + rng.uniform(size=shape)
+    y = np.stack([np.stack([s[c] * x * np.exp(2j * np.pi * fval * t) for t in te]) for c in range(ncoil)])
+    return y, s, te, fval
+
+
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+def test_noise_free_constant_field_is_recovered(ordering):
+    shape = (5, 4, 6)
+    rng = np.random.default_rng(15)
+    mask = (rng.uniform(size=shape) < 0.9).astype(np.uint8)
+    y, s, te, fval = _noise_free_constant(shape, 0.5)
+    zhat = O.combine(y, s)
+    pb = O.Problem(shape, te, O.gamma_fieldmap(3), 0.5, niter=80, ordering=ordering)
+    f0 = (fval + 20 * np.sin(np.arange(mask.size) * 0.37).reshape(shape)) * mask
+    f, tr, _ = O.solve(pb, zhat, mask, f0)
+    assert np.abs((f - fval)[mask == 1]).max() < 1e-8
+    assert tr[-1, O.TR["cost"]] < 1e-12 * tr[0, O.TR["cost"]] + 1e-20
+
+
+def test_converged_point_is_a_newton_fixed_point():
+    vol = synth.random_volume((6, 5, 4), 2, 3, seed=16, beta=0.05, mask_frac=0.9)
+    pb = O.problem_for(vol, niter=400)
+    zhat = O.combine(vol.y, vol.sens)
+    f0 = O.init_fieldmap(zhat, vol.te, vol.mask)
+    f, tr, _ = O.solve(pb, zhat, vol.mask, f0)
+    sel = vol.mask.ravel().astype(bool)
+    # exact Hessian: second derivative of the data term by central differences
+    # of the oracle's gradient, plus beta C^T C
+    h = 1e-4
+    _, dp, _ = O.data_term(pb, zhat, vol.mask, f + h)
+    _, dm, _ = O.data_term(pb, zhat, vol.mask, f - h)
+    hdiag = ((dp - dm) / (2 * h)).ravel()
+    Cm = diff_matrix(vol.mask)
+    Hx = (np.diag(hdiag) + pb.beta * Cm.T @ Cm)[np.ix_(sel, sel)]
+    _, dphi, _ = O.data_term(pb, zhat, vol.mask, f)
+    g = (dphi + pb.beta * O.laplacian(pb, vol.mask, f)).ravel()[sel]
+    step = np.linalg.solve(Hx, g)
+    assert np.abs(step).max() < 1e-8
+    assert np.linalg.eigvalsh(Hx).min() > 0  # a strict local minimum
+
+
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+def test_cost_is_monotone_per_outer_and_line_search_step(ordering):
+    vol = synth.tiny_fieldmap(mask="paper")
+    out = O.run_volume(vol, ordering=ordering, niter=20, want_mls=True)
+    cost = out["trace"][:, O.TR["cost"]]
+    assert np.all(np.diff(cost) <= 1e-13 * abs(cost[0]))
+    mls = out["mls"]
+    assert np.all(np.diff(mls, axis=1) <= 1e-13 * abs(cost[0]))
+    # the cost after the line search is the next outer cost
+    np.testing.assert_allclose(mls[:, -1], cost[1:], rtol=1e-12)
+
+
+def test_line_majoriser_dominates_line_cost():
+    """q_k(alpha) >= f(alpha) on a dense alpha grid (Sec. III-C)."""
+    vol = synth.random_volume((4, 4, 3), 2, 3, seed=17, beta=0.2)
+    pb = O.problem_for(vol)
+    zhat = O.combine(vol.y, vol.sens)
+    rng = np.random.default_rng(18)
+    f = O.init_fieldmap(zhat, vol.te, vol.mask)
+    z = rng.normal(size=vol.shape) * 30
+    Lz = O.laplacian(pb, vol.mask, z)
+    B = float((z * Lz).sum())
+    alphas = np.linspace(-3, 3, 601)
+    fa = np.array([O.cost(pb, zhat, vol.mask, f + a * z) for a in alphas])
+    reg = np.array([0.5 * pb.beta * float(((f + a * z) * O.laplacian(pb, vol.mask, f + a * z)).sum())
+                    for a in alphas])
+    for ak in [-1.0, 0.0, 0.4, 1.7]:
+        phi, dphi, curv = O.data_term(pb, zhat, vol.mask, f + ak * z)
+        dk = float((z * z * curv).sum())
+        s1 = float((z * dphi).sum())
+        q = phi.sum() + s1 * (alphas - ak) + 0.5 * dk * (alphas - ak) ** 2 + reg
+        assert np.all(q >= fa - 1e-9 * np.abs(fa).max())
+        assert B >= 0
+
+
+def test_quadratic_limit_is_preconditioned_linear_cg():
+    """Near a noise-free solution the cost is quadratic and the Huber curvature
+    is the exact one, so one line-search step is an exact line search and the
+    iteration must reproduce preconditioned linear CG (scipy) on H delta = -g
+    with the same IC(0) preconditioner."""
+    from scipy.sparse.linalg import LinearOperator, cg
+
+    shape = (4, 3, 5)
+    mask = np.ones(shape, np.uint8)
+    y, s, te, fval = _noise_free_constant(shape, 0.0, seed=19)
+    zhat = O.combine(y, s)
+    beta = 0.02
+    eps = 1e-6 * np.cos(np.arange(mask.size) * 1.3).reshape(shape)
+    f0 = fval + eps
+    niter = 6
+    pb = O.Problem(shape, te, O.gamma_fieldmap(3), beta, niter=niter, nmls=1)
+    # quadratic model at the solution
+    _, _, curv = O.data_term(pb, zhat, mask, np.full(shape, fval))
+    Hm, _ = dense_hessian_model(mask, curv, beta)
+    Lt = textbook_ic0(Hm)
+    Mop = LinearOperator(Hm.shape, matvec=lambda v: np.linalg.solve(Lt.T, np.linalg.solve(Lt, v)))
+    iters = []
+    for k in range(1, niter + 1):
+        x, _ = cg(Hm, -Hm @ eps.ravel(), x0=np.zeros(mask.size), rtol=0.0, atol=0.0, maxiter=k, M=Mop)
+        iters.append(x)
+    for k in range(1, niter + 1):
+        pbk = O.Problem(shape, te, O.gamma_fieldmap(3), beta, niter=k, nmls=1)
+        fk, _, _ = O.solve(pbk, zhat, mask, f0)
+        dk = (fk - f0).ravel()
+        ref = iters[k - 1]
+        assert np.linalg.norm(dk - ref) <= 1e-5 * np.linalg.norm(eps), (k, np.linalg.norm(dk - ref))
+
+
+def test_diagonal_and_identity_preconditioners():
+    vol = synth.random_volume((3, 4, 3), 1, 3, seed=20, beta=0.3, mask_frac=0.8)
+    zhat = O.combine(vol.y, vol.sens)
+    f0 = O.init_fieldmap(zhat, vol.te, vol.mask)
+    for pc in (O.DIAG, O.NONE):
+        out = O.run_volume(vol, precond=pc, niter=15, f0=f0)
+        c = out["trace"][:, O.TR["cost"]]
+        assert np.all(np.diff(c) <= 1e-13 * abs(c[0]))
+    # with identity preconditioning the first direction is -g (z^T g = -||g||^2)
+    out = O.run_volume(vol, precond=O.NONE, niter=1, f0=f0)
+    tr = out["trace"]
+    assert abs(tr[0, O.TR["ztg"]] + tr[0, O.TR["gnorm2"]]) <= 1e-12 * tr[0, O.TR["gnorm2"]]
