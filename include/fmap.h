@@ -1,0 +1,194 @@
+/*
+ * fmap.h -- C ABI of the MI355X (gfx950) preconditioned NCG-MLS field-map
+ * estimator of Lin & Fessler, "Efficient Regularized Field Map Estimation in
+ * 3D MRI" (arXiv 2005.08661).
+ *
+ * What the library computes (Sec. II-III of the paper):
+ *   minimise  Psi(f) = Phi(f) + (beta/2) ||C f||^2            (Sec. II eq. (cost))
+ * over the field map f (Hz) inside a support mask, where Phi is the
+ * coil-combined multi-echo data term of Sec. II eqs. (cost1), (r), (gamma),
+ * C the first-order finite difference over x, y and z (one row per pair of
+ * axis neighbours that are both inside the mask), by the preconditioned
+ * nonlinear conjugate gradient of the Algorithm in Sec. III: gradient
+ * (eq. (ls_grad)), IC(0) preconditioner of H = D + beta C^T C
+ * (eqs. (precon_hess), (precon)), Polak-Ribiere conjugacy and the monotone
+ * line search of Sec. III-C (eq. (ls_update)).
+ *
+ * Conventions shared by every entry point:
+ *   - Grid nx*ny*nz, z fastest: voxel j = (x*ny + y)*nz + z.
+ *   - Images y are complex64 (interleaved float re, im) with layout
+ *     [ncoil][necho][nx][ny][nz]; coil maps are complex64 [ncoil][nx][ny][nz].
+ *   - Field maps are float64 in Hz; echo times in seconds; the phase of echo
+ *     l is 2*pi*f*t_l (Sec. II eq. (model) with omega = 2*pi*f); beta
+ *     multiplies (beta/2)||C f||^2 with f in Hz.
+ *   - Voxels outside the mask are held at f = 0 and do not enter the cost.
+ *   - Every pointer argument named "dev" is device memory on the current HIP
+ *     device, owned by the caller and left untouched except for outputs.
+ *     Host pointers are marked "host".
+ *   - Work is enqueued on the given stream (NULL = default stream); argument
+ *     and shape checks run synchronously before anything is enqueued.
+ *   - No entry point throws or aborts; each returns an fm_status and, on
+ *     failure, fm_last_error() (thread-local) describes the cause.
+ *   - A plan may be used by one stream at a time; calls on one plan must not
+ *     overlap.
+ */
+#ifndef FMAP_H
+#define FMAP_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FM_MAX_ECHO 16
+#define FM_MAX_PEAK 16
+
+typedef enum {
+  FM_OK = 0,
+  FM_ERR_ARG = 1,       /* invalid argument (NULL pointer, bad enum, beta < 0, ...) */
+  FM_ERR_SHAPE = 2,     /* bad dimensions (non-positive sizes, necho < 2, too many echoes) */
+  FM_ERR_ALLOC = 3,     /* device allocation failed */
+  FM_ERR_HIP = 4,       /* a HIP runtime call failed */
+  FM_ERR_NOT_PD = 5,    /* an IC(0) pivot was not positive (singular Hessian model) */
+  FM_ERR_NONFINITE = 6, /* NaN/Inf met in the iteration */
+  FM_ERR_STATE = 7      /* call out of order (e.g. fm_eval before fm_setup) */
+} fm_status;
+
+typedef enum { FM_FIELDMAP = 0, FM_WATERFAT = 1 } fm_model;
+/* F64: FP64 storage and arithmetic throughout.  MIX: FP32 per-voxel storage
+ * and arithmetic with FP64 pivots, reductions and scalars. */
+typedef enum { FM_PREC_F64 = 0, FM_PREC_MIX = 1 } fm_precision;
+/* Elimination order of the IC(0) factor: natural (lexicographic, z fastest)
+ * or red-black (voxels with x+y+z even first, each colour in natural order). */
+typedef enum { FM_ORDER_NATURAL = 0, FM_ORDER_REDBLACK = 1 } fm_ordering;
+/* Preconditioner: IC(0) (the paper's), diag(H), or none. */
+typedef enum { FM_PRECOND_IC0 = 0, FM_PRECOND_DIAG = 1, FM_PRECOND_NONE = 2 } fm_precond;
+
+/* Columns of the per-iteration trace (see fm_get_trace). */
+enum {
+  FM_TR_COST = 0,    /* Psi(f^i) at the start of iteration i                 */
+  FM_TR_GTP = 1,     /* g^T p                                                */
+  FM_TR_MU = 2,      /* Polak-Ribiere mu used (0 on restart)                 */
+  FM_TR_RESTART = 3, /* 1 if the direction was reset to -p                   */
+  FM_TR_ALPHA = 4,   /* final line-search step size                          */
+  FM_TR_ZTG = 5,     /* z^T g                                                */
+  FM_TR_B = 6,       /* ||C z||^2                                            */
+  FM_TR_GNORM2 = 7,  /* ||g||^2                                              */
+  FM_TR_W = 8
+};
+
+/* Problem description.  Plain data: the struct owns no memory. */
+typedef struct {
+  int32_t nx, ny, nz;            /* grid, each >= 1 */
+  int32_t ncoil;                 /* >= 1 */
+  int32_t necho;                 /* L, 2 <= L <= FM_MAX_ECHO (Sec. II needs L >= 2) */
+  double te[FM_MAX_ECHO];        /* echo times, seconds (first necho used) */
+  double beta;                   /* regularisation weight, >= 0 */
+  int32_t niter;                 /* outer NCG iterations, >= 0 */
+  int32_t nmls;                  /* line-search steps per iteration, >= 1 */
+  int32_t model;                 /* fm_model */
+  int32_t npeak;                 /* water-fat: number of fat peaks */
+  double fat_hz[FM_MAX_PEAK];    /* water-fat: peak offsets, Hz */
+  double fat_amp[FM_MAX_PEAK];   /* water-fat: relative amplitudes */
+  int32_t nsweep;                /* water-fat init: sweep values (Sec. III-A uses 100) */
+  int32_t pwls_iters;            /* water-fat init: CG iterations of eq. (w0_wf) */
+  int32_t precision;             /* fm_precision */
+  int32_t ordering;              /* fm_ordering */
+  int32_t precond;               /* fm_precond */
+} fm_params;
+
+typedef struct fm_plan fm_plan;
+
+/* Validate the parameters and allocate the plan's device workspace on the
+ * current device (about 70 B per voxel in MIX, 140 B in F64, plus the
+ * reduction buffers).  *plan is set to NULL on failure. */
+fm_status fm_plan_create(const fm_params *prm, fm_plan **plan);
+
+/* Free the plan and its workspace.  NULL is accepted. */
+fm_status fm_plan_destroy(fm_plan *plan);
+
+/* Setup (Sec. II eq. (r) and the Algorithm's precompute step): coil-combine
+ * the images into zhat_l = sum_c conj(s_c) y_cl / sqrt(sum_c |s_c|^2) and keep
+ * the per-echo magnitude and phase in the plan; also records the mask.
+ *   y    dev complex64 [ncoil][necho][nx][ny][nz]
+ *   sens dev complex64 [ncoil][nx][ny][nz], or NULL for s = 1 (needs ncoil == 1)
+ *   mask dev uint8 [nx][ny][nz], nonzero = unknown voxel */
+fm_status fm_setup(fm_plan *plan, const void *y, const void *sens, const uint8_t *mask,
+                   hipStream_t stream);
+
+/* Initial map of Sec. III-A (eq. (w0) for field maps; sweep plus PWLS,
+ * eq. (w0_wf), for water-fat) from the data given to fm_setup.
+ *   f0 dev float64 [nx][ny][nz], written; 0 outside the mask. */
+fm_status fm_init(fm_plan *plan, double *f0, hipStream_t stream);
+
+/* Evaluate at a given map f (dev float64 [N]): per-voxel data cost phi,
+ * its derivative dphi/df (eq. (ls_grad) without the regulariser), the Huber
+ * curvature d (eq. (ls_huber)) and (C^T C f).  Any output may be NULL; all
+ * are dev float64 [N] and 0 outside the mask.  Needs fm_setup. */
+fm_status fm_eval(fm_plan *plan, const double *f, double *phi, double *dphi, double *curv,
+                  double *lap, hipStream_t stream);
+
+/* Preconditioner step of the Algorithm for a given curvature d and gradient
+ * g (dev float64 [N]): builds the plan's preconditioner for
+ * H = diag(d) + beta C^T C (IC(0) in the plan's ordering, diag(H), or the
+ * identity) and writes p = P^{-1} g (dev float64 [N]).  piv, if not NULL,
+ * receives the IC(0) pivots P_jj (dev float64 [N]).  Needs fm_setup.
+ * Returns FM_ERR_NOT_PD (after synchronising the stream) if a pivot is not
+ * positive. */
+fm_status fm_precondition(fm_plan *plan, const double *curv, const double *g, double *piv,
+                          double *p, hipStream_t stream);
+
+/* Full solve: fm_setup, then fm_init unless f0 is given, then niter
+ * iterations of the Algorithm; writes the final map to f_out.
+ *   f0    dev float64 [N] initial map, or NULL for the paper's initial map
+ *   f_out dev float64 [N]
+ * The iteration loop runs from a HIP graph without host round trips. */
+fm_status fm_solve(fm_plan *plan, const void *y, const void *sens, const uint8_t *mask,
+                   const double *f0, double *f_out, hipStream_t stream);
+
+/* Run niter further iterations from the plan's current state (after fm_solve
+ * or a previous fm_iterate) and write the map to f_out (dev float64 [N]). */
+fm_status fm_iterate(fm_plan *plan, int32_t niter, double *f_out, hipStream_t stream);
+
+/* Copy the trace of the last solve to host memory: trace is host float64
+ * [niter+1][FM_TR_W] (row niter holds the final cost only).  Synchronises
+ * the stream.  Also returns the device status word of the solve (FM_OK,
+ * FM_ERR_NOT_PD or FM_ERR_NONFINITE). */
+fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
+
+/* Number of voxels inside the mask given to the last fm_setup (host int64),
+ * synchronising the stream. */
+fm_status fm_mask_count(fm_plan *plan, int64_t *count, hipStream_t stream);
+
+/* Kernel classes reported by fm_time_kernels. */
+enum {
+  FM_K_GRAD = 0,      /* gradient pass: data term, stencil, f update        */
+  FM_K_PRECOND_A = 1, /* IC(0) forward sweep (natural) / black pass (red-black) / diagonal */
+  FM_K_PRECOND_B = 2, /* IC(0) backward sweep (natural) / red pass (red-black) */
+  FM_K_DOTS = 3,      /* conjugacy dot products                             */
+  FM_K_DIR = 4,       /* direction and line-search setup                    */
+  FM_K_MLS = 5,       /* further line-search passes                         */
+  FM_NK = 6
+};
+
+/* Measurement: run niter further iterations from the plan's current state
+ * (as fm_iterate, but launching kernel by kernel instead of from the graph)
+ * with a HIP event pair around every launch on the given stream, and return
+ * per kernel class the summed duration in milliseconds and the number of
+ * launches (host float64 ms[FM_NK], host int32 launches[FM_NK]).  The map is
+ * not written out.  Synchronises the stream. */
+fm_status fm_time_kernels(fm_plan *plan, int32_t niter, double *ms, int32_t *launches,
+                          hipStream_t stream);
+
+/* Human-readable text for a status code, and the last error message of the
+ * calling thread. */
+const char *fm_status_string(fm_status st);
+const char *fm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

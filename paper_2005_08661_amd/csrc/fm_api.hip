@@ -1,0 +1,775 @@
+// Host side of the C ABI declared in include/fmap.h: parameter validation,
+// plan and workspace management, the kernel chain of one NCG iteration and
+// the HIP graph that replays the whole iteration loop.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fmap.h"
+#include "fm_kernels.hpp"
+#include "fm_stream.hpp"
+
+using fm::kBlock;
+using fm::kMaxGrid;
+using fm::kMaxK;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fm_status fail(fm_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define FM_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(FM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+#define FM_LAUNCH_CHECK()                                                                 \
+  do {                                                                                    \
+    hipError_t e_ = hipGetLastError();                                                    \
+    if (e_ != hipSuccess) return fail(FM_ERR_HIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct fm_plan {
+  fm_params prm;
+  int device = 0;
+  int64_t n = 0;
+  fm::Geo geo{};
+  bool mix = false;
+  int lmax = 4;
+  int npairs = 0;
+  int grid = 1;   // blocks of the kBlock-thread kernels
+  int sgrid = 1;  // blocks of the streaming iteration passes (kNT threads)
+  size_t tsize = 8;  // bytes of the working type
+  // device workspace
+  void *dat = nullptr;
+  uint8_t *code = nullptr;
+  void *F[2] = {nullptr, nullptr};
+  void *Z[2] = {nullptr, nullptr};
+  void *G[2] = {nullptr, nullptr};
+  void *D = nullptr, *X = nullptr, *P = nullptr;
+  double *ipiv = nullptr;
+  double *hinv = nullptr;
+  fm::State *S = nullptr;      // two ping-pong state copies
+  double *part = nullptr;      // two ping-pong partial-sum buffers [kMaxGrid][kMaxK]
+  double *setup_part = nullptr;
+  double *nmask = nullptr;
+  int32_t *status = nullptr;
+  double *trace = nullptr;
+  void *pairs = nullptr;
+  void *pairs_d = nullptr;
+  double *gabs = nullptr;
+  double *rho = nullptr;
+  double *f0buf = nullptr;
+  double *wf_tmp = nullptr;  // water-fat init: swept map and 3 CG vectors
+  bool setup_done = false;
+  bool solved = false;
+  // position in the kernel chain: launch q reads S[q&1], writes S[(q+1)&1]
+  uint64_t q = 0;
+  // device allocations (freed with the plan); stencil-read arrays are
+  // padded by pad elements on both sides
+  std::vector<void *> bases;
+  int64_t pad = 0;
+  // graphs of the iteration loop keyed by (chain parity, iterations)
+  hipStream_t cap_stream = nullptr;
+  std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+};
+
+namespace {
+
+// Gamma = gamma (gamma^H gamma)^{-1} gamma^H (Sec. II eq. (gamma)).
+std::vector<std::complex<double>> make_gamma(const fm_params &p) {
+  const int L = p.necho;
+  std::vector<std::complex<double>> G((size_t)L * L);
+  if (p.model == FM_FIELDMAP) {
+    for (auto &v : G) v = 1.0 / L;
+    return G;
+  }
+  const double two_pi = 6.283185307179586476925286766559;
+  std::vector<std::complex<double>> c(L);
+  for (int l = 0; l < L; ++l) {
+    std::complex<double> s = 0.0;
+    for (int q = 0; q < p.npeak; ++q) s += p.fat_amp[q] * std::polar(1.0, two_pi * p.fat_hz[q] * p.te[l]);
+    c[l] = s;
+  }
+  // normal matrix N = [[L, sum c], [sum conj c, sum |c|^2]] and its inverse
+  std::complex<double> sc = 0.0;
+  double cc = 0.0;
+  for (int l = 0; l < L; ++l) {
+    sc += c[l];
+    cc += std::norm(c[l]);
+  }
+  const double det = L * cc - std::norm(sc);
+  const std::complex<double> i00 = cc / det, i01 = -sc / det, i10 = -std::conj(sc) / det, i11 = (double)L / det;
+  for (int m = 0; m < L; ++m)
+    for (int n = 0; n < L; ++n)
+      G[(size_t)m * L + n] = i00 + i01 * std::conj(c[n]) + c[m] * i10 + c[m] * i11 * std::conj(c[n]);
+  return G;
+}
+
+template <typename T>
+std::vector<fm::PairC<T>> make_pairs(const fm_params &p, const std::vector<std::complex<double>> &G) {
+  std::vector<fm::PairC<T>> out;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int m = 0; m < p.necho; ++m)
+    for (int n = m + 1; n < p.necho; ++n) {
+      fm::PairC<T> q{};
+      const auto g = G[(size_t)m * p.necho + n];
+      q.w = (T)(2.0 * std::abs(g));
+      q.g = (T)(std::arg(g) / two_pi);
+      q.dt = (T)(p.te[m] - p.te[n]);
+      q.d2pi = (T)(two_pi * (p.te[m] - p.te[n]));
+      q.m = m;
+      q.n = n;
+      out.push_back(q);
+    }
+  return out;
+}
+
+// Arguments of chain launch number q (state and partial-sum slots by parity).
+template <typename T>
+fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
+  fm::IterArgs<T> a{};
+  a.geo = p->geo;
+  a.L = p->prm.necho;
+  a.beta = p->prm.beta;
+  a.dat = (const fm::T2<T> *)p->dat;
+  a.code = p->code;
+  a.pairs = (const fm::PairC<T> *)p->pairs;
+  for (int i = 0; i < 2; ++i) {
+    a.F[i] = (T *)p->F[i];
+    a.Z[i] = (T *)p->Z[i];
+    a.G[i] = (T *)p->G[i];
+  }
+  a.D = (T *)p->D;
+  a.X = (T *)p->X;
+  a.P = (T *)p->P;
+  a.ipiv = p->ipiv;
+  a.hinv = p->hinv;
+  a.write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? 1 : 0;
+  a.store_piv = 0;
+  a.sin = p->S + (q & 1);
+  a.sout = p->S + ((q + 1) & 1);
+  a.pin = p->part + (size_t)(q & 1) * kMaxGrid * kMaxK;
+  a.pout = p->part + (size_t)((q + 1) & 1) * kMaxGrid * kMaxK;
+  a.status = p->status;
+  a.trace = p->trace;
+  a.fout = nullptr;
+  a.final_pass = 0;
+  return a;
+}
+
+// Optional per-launch event recorder (measurement path only).
+struct Recorder {
+  hipStream_t s = nullptr;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cls;
+  hipError_t err = hipSuccess;
+  void begin(int c) {
+    hipEvent_t e = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(&e);
+    if (err == hipSuccess) err = hipEventRecord(e, s);
+    ev.push_back(e);
+    cls.push_back(c);
+  }
+  void end() {
+    hipEvent_t e = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(&e);
+    if (err == hipSuccess) err = hipEventRecord(e, s);
+    ev.push_back(e);
+  }
+  ~Recorder() {
+    for (auto e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
+#define FM_REC_BEGIN(c) \
+  if (rec) rec->begin(c)
+#define FM_REC_END() \
+  if (rec) rec->end()
+
+// Preconditioner step p = P^{-1} g (g from gsrc, or G[iter&1] if null),
+// leaving the dot products g^T p and g_prev^T p as partial sums.
+template <typename T>
+fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *rec = nullptr) {
+  auto pargs = [&](fm_plan *pp, uint64_t q) {
+    fm::IterArgs<T> a = iter_args<T>(pp, q);
+    a.store_piv = gsrc ? 1 : 0;  // the standalone call reports the pivots
+    return a;
+  };
+  if (p->prm.precond == FM_PRECOND_IC0) {
+    if (p->prm.ordering == FM_ORDER_NATURAL) {
+      FM_REC_BEGIN(FM_K_PRECOND_A);
+      hipLaunchKernelGGL(fm::k_ic_fwd_onewg<T>, dim3(1), dim3(1024), 0, s, pargs(p, p->q++), gsrc);
+      FM_REC_END();
+      FM_LAUNCH_CHECK();
+      FM_REC_BEGIN(FM_K_PRECOND_B);
+      hipLaunchKernelGGL(fm::k_ic_bwd_onewg<T>, dim3(1), dim3(1024), 0, s, pargs(p, p->q++), gsrc);
+      FM_REC_END();
+      FM_LAUNCH_CHECK();
+    } else {
+      FM_REC_BEGIN(FM_K_PRECOND_A);
+      hipLaunchKernelGGL(fm::k_rb_black<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, pargs(p, p->q++), gsrc);
+      FM_REC_END();
+      FM_LAUNCH_CHECK();
+      FM_REC_BEGIN(FM_K_PRECOND_B);
+      hipLaunchKernelGGL(fm::k_rb_red<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, pargs(p, p->q++), gsrc);
+      FM_REC_END();
+      FM_LAUNCH_CHECK();
+    }
+  } else {
+    FM_REC_BEGIN(FM_K_PRECOND_A);
+    hipLaunchKernelGGL(fm::k_diag<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, pargs(p, p->q++), gsrc,
+                       p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
+    FM_REC_END();
+    FM_LAUNCH_CHECK();
+  }
+  return FM_OK;
+}
+
+// Launches per iteration (must match enqueue_iteration).
+uint64_t launches_per_iteration(const fm_plan *p) {
+  const uint64_t precond = (p->prm.precond == FM_PRECOND_IC0) ? 2 : 1;
+  return 1 + precond + 1 + (uint64_t)(p->prm.nmls - 1);
+}
+
+// One NCG iteration: gradient, preconditioner (+ dots), direction, and the
+// remaining line-search passes; the last pass is consumed by the next
+// iteration's gradient pass (or by the final pass).
+template <typename T, int LMAX>
+fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) {
+  FM_REC_BEGIN(FM_K_GRAD);
+  hipLaunchKernelGGL((fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, iter_args<T>(p, p->q++));
+  FM_REC_END();
+  FM_LAUNCH_CHECK();
+  fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
+  if (st) return st;
+  FM_REC_BEGIN(FM_K_DIR);
+  hipLaunchKernelGGL(fm::k_dir<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, iter_args<T>(p, p->q++));
+  FM_REC_END();
+  FM_LAUNCH_CHECK();
+  for (int k = 1; k < p->prm.nmls; ++k) {
+    FM_REC_BEGIN(FM_K_MLS);
+    hipLaunchKernelGGL((fm::k_mls<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, iter_args<T>(p, p->q++));
+    FM_REC_END();
+    FM_LAUNCH_CHECK();
+  }
+  return FM_OK;
+}
+
+// Final pass: apply the last step, write the map, and record its cost.
+template <typename T, int LMAX>
+fm_status enqueue_final(fm_plan *p, double *f_out, hipStream_t s) {
+  fm::IterArgs<T> a = iter_args<T>(p, p->q++);
+  a.final_pass = 1;
+  a.fout = f_out;
+  hipLaunchKernelGGL((fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
+  FM_LAUNCH_CHECK();
+  const uint64_t q = p->q++;
+  hipLaunchKernelGGL(fm::k_finish, dim3(1), dim3(kBlock), 0, s, (const fm::State *)(p->S + (q & 1)),
+                     p->S + ((q + 1) & 1), (const double *)(p->part + (size_t)(q & 1) * kMaxGrid * kMaxK),
+                     p->prm.beta, p->trace, p->status);
+  FM_LAUNCH_CHECK();
+  return FM_OK;
+}
+
+template <typename T, int LMAX>
+fm_status enqueue_eval(fm_plan *p, const double *f, double *phi, double *dphi, double *curv, double *lap,
+                       hipStream_t s) {
+  fm::IterArgs<T> a = iter_args<T>(p, 0);
+  hipLaunchKernelGGL((fm::k_eval<T, LMAX>), dim3(p->grid), dim3(kBlock), 0, s, a, f, phi, dphi, curv, lap);
+  FM_LAUNCH_CHECK();
+  return FM_OK;
+}
+
+// Dispatch on the working type and the echo-count bucket.
+template <template <typename, int> class Op, typename... Args>
+fm_status dispatch(fm_plan *p, Args... args) {
+  if (p->mix) {
+    switch (p->lmax) {
+      case 4: return Op<float, 4>::run(p, args...);
+      case 8: return Op<float, 8>::run(p, args...);
+      default: return Op<float, 16>::run(p, args...);
+    }
+  }
+  switch (p->lmax) {
+    case 4: return Op<double, 4>::run(p, args...);
+    case 8: return Op<double, 8>::run(p, args...);
+    default: return Op<double, 16>::run(p, args...);
+  }
+}
+
+template <typename T, int LMAX>
+struct OpLoop {
+  static fm_status run(fm_plan *p, int niter, hipStream_t s) {
+    for (int i = 0; i < niter; ++i) {
+      fm_status st = enqueue_iteration<T, LMAX>(p, s);
+      if (st) return st;
+    }
+    return FM_OK;
+  }
+};
+template <typename T, int LMAX>
+struct OpIterationTimed {
+  static fm_status run(fm_plan *p, hipStream_t s, Recorder *rec) { return enqueue_iteration<T, LMAX>(p, s, rec); }
+};
+template <typename T, int LMAX>
+struct OpFinal {
+  static fm_status run(fm_plan *p, double *f, hipStream_t s) { return enqueue_final<T, LMAX>(p, f, s); }
+};
+template <typename T, int LMAX>
+struct OpEval {
+  static fm_status run(fm_plan *p, const double *f, double *a, double *b, double *c, double *d, hipStream_t s) {
+    return enqueue_eval<T, LMAX>(p, f, a, b, c, d, s);
+  }
+};
+
+fm_status validate(const fm_params *p) {
+  if (!p) return fail(FM_ERR_ARG, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(FM_ERR_SHAPE, "grid sizes must be >= 1");
+  if (p->ncoil < 1) return fail(FM_ERR_SHAPE, "ncoil must be >= 1");
+  if (p->necho < 2 || p->necho > FM_MAX_ECHO) return fail(FM_ERR_SHAPE, "necho must be in [2, 16]");
+  for (int l = 0; l < p->necho; ++l)
+    if (!std::isfinite(p->te[l])) return fail(FM_ERR_ARG, "echo times must be finite");
+  if (!(p->beta >= 0.0) || !std::isfinite(p->beta)) return fail(FM_ERR_ARG, "beta must be finite and >= 0");
+  if (p->niter < 0) return fail(FM_ERR_ARG, "niter must be >= 0");
+  if (p->nmls < 1) return fail(FM_ERR_ARG, "nmls must be >= 1");
+  if (p->model != FM_FIELDMAP && p->model != FM_WATERFAT) return fail(FM_ERR_ARG, "bad model");
+  if (p->precision != FM_PREC_F64 && p->precision != FM_PREC_MIX) return fail(FM_ERR_ARG, "bad precision");
+  if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK) return fail(FM_ERR_ARG, "bad ordering");
+  if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_NONE) return fail(FM_ERR_ARG, "bad preconditioner");
+  if (p->model == FM_FIELDMAP && p->te[1] == p->te[0])
+    return fail(FM_ERR_ARG, "field-map initialisation needs t_2 != t_1");
+  if (p->model == FM_WATERFAT) {
+    if (p->npeak < 1 || p->npeak > FM_MAX_PEAK) return fail(FM_ERR_ARG, "water-fat needs 1..16 fat peaks");
+    if (p->nsweep < 2) return fail(FM_ERR_ARG, "water-fat sweep needs >= 2 values");
+    if (p->pwls_iters < 0) return fail(FM_ERR_ARG, "pwls_iters must be >= 0");
+  }
+  const int64_t n = (int64_t)p->nx * p->ny * p->nz;
+  if (n > (int64_t)1 << 34) return fail(FM_ERR_SHAPE, "volume too large");
+  return FM_OK;
+}
+
+bool plan_alloc(fm_plan *p, void **ptr, size_t bytes) {
+  void *b = nullptr;
+  if (hipMalloc(&b, bytes ? bytes : 1) != hipSuccess) return false;
+  p->bases.push_back(b);
+  *ptr = b;
+  return true;
+}
+
+// Per-voxel array of elems entries of esize bytes with p->pad guard entries
+// on each side (readable neighbour slots outside the volume).
+bool plan_alloc_padded(fm_plan *p, void **ptr, size_t elems, size_t esize) {
+  void *b = nullptr;
+  if (!plan_alloc(p, &b, (elems + 2 * (size_t)p->pad) * esize)) return false;
+  *ptr = (char *)b + (size_t)p->pad * esize;
+  return true;
+}
+
+template <typename T>
+fm_status upload_pairs(fm_plan *p, const std::vector<std::complex<double>> &G, void **dst) {
+  auto pr = make_pairs<T>(p->prm, G);
+  p->npairs = (int)pr.size();
+  if (!plan_alloc(p, dst, sizeof(fm::PairC<T>) * pr.size())) return fail(FM_ERR_ALLOC, "hipMalloc of pairs failed");
+  FM_HIP(hipMemcpy(*dst, pr.data(), sizeof(fm::PairC<T>) * pr.size(), hipMemcpyHostToDevice));
+  return FM_OK;
+}
+
+fm_status wf_init(fm_plan *p, double *f0, hipStream_t s);  // fm_waterfat.inc
+
+void free_plan(fm_plan *p) {
+  if (!p) return;
+  for (auto &kv : p->graphs) {
+    if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+    if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+  }
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (void *b : p->bases)
+    if (b) (void)hipFree(b);
+  delete p;
+}
+
+// Run niter iterations as one graph launch.  The graph for the current chain
+// parity and niter is captured on first use and replayed afterwards (its
+// launches occupy the same chain positions modulo 2).
+fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
+  if (niter <= 0) return FM_OK;
+  const auto key = std::make_pair((int)(p->q & 1), niter);
+  auto it = p->graphs.find(key);
+  if (it == p->graphs.end()) {
+    const uint64_t q0 = p->q;
+    FM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    fm_status st = dispatch<OpLoop>(p, niter, p->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      p->q = q0;
+      return st;
+    }
+    if (e != hipSuccess) return fail(FM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t ge = nullptr;
+    hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return fail(FM_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    }
+    it = p->graphs.emplace(key, std::make_pair(g, ge)).first;
+  } else {
+    p->q += launches_per_iteration(p) * (uint64_t)niter;
+  }
+  FM_HIP(hipGraphLaunch(it->second.second, s));
+  return FM_OK;
+}
+
+template <typename T>
+fm_status enqueue_start(fm_plan *p, const double *f0, hipStream_t s) {
+  const uint64_t q = p->q++;
+  hipLaunchKernelGGL(fm::k_start<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, f0, (const uint8_t *)p->code,
+                     (T *)p->F[1], (T *)p->Z[1], (T *)p->G[1], p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls,
+                     (const double *)p->nmask);
+  FM_LAUNCH_CHECK();
+  return FM_OK;
+}
+
+fm_status check_plan(fm_plan *p) {
+  if (!p) return fail(FM_ERR_ARG, "plan is NULL");
+  int cur = 0;
+  FM_HIP(hipGetDevice(&cur));
+  if (cur != p->device) return fail(FM_ERR_STATE, "plan was created on another device");
+  return FM_OK;
+}
+
+fm_status read_status(fm_plan *p, hipStream_t s, int32_t *status) {
+  FM_HIP(hipMemcpyAsync(status, p->status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  FM_HIP(hipStreamSynchronize(s));
+  return FM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fm_status_string(fm_status st) {
+  switch (st) {
+    case FM_OK: return "ok";
+    case FM_ERR_ARG: return "invalid argument";
+    case FM_ERR_SHAPE: return "invalid shape";
+    case FM_ERR_ALLOC: return "device allocation failed";
+    case FM_ERR_HIP: return "HIP runtime error";
+    case FM_ERR_NOT_PD: return "IC(0) pivot not positive";
+    case FM_ERR_NONFINITE: return "non-finite value in the iteration";
+    case FM_ERR_STATE: return "call out of order";
+  }
+  return "unknown status";
+}
+
+const char *fm_last_error(void) { return g_last_error.c_str(); }
+
+fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
+  if (!out) return fail(FM_ERR_ARG, "plan output pointer is NULL");
+  *out = nullptr;
+  fm_status vs = validate(prm);
+  if (vs) return vs;
+  fm_plan *p = new fm_plan();
+  p->prm = *prm;
+  p->n = (int64_t)prm->nx * prm->ny * prm->nz;
+  p->geo.nx = prm->nx;
+  p->geo.ny = prm->ny;
+  p->geo.nz = prm->nz;
+  p->geo.n = p->n;
+  p->geo.sy = prm->nz;
+  p->geo.sx = (int64_t)prm->ny * prm->nz;
+  p->pad = ((p->geo.sx + 63) / 64) * 64;
+  if (p->n + 2 * p->pad >= ((int64_t)1 << 31)) {
+    delete p;
+    return fail(FM_ERR_SHAPE, "volume too large for 32-bit voxel indices");
+  }
+  p->mix = prm->precision == FM_PREC_MIX;
+  p->tsize = p->mix ? sizeof(float) : sizeof(double);
+  p->lmax = prm->necho <= 4 ? 4 : (prm->necho <= 8 ? 8 : 16);
+  const int64_t blocks = (p->n + kBlock - 1) / kBlock;
+  p->grid = (int)(blocks < kMaxGrid ? blocks : kMaxGrid);
+  if (p->grid < 1) p->grid = 1;
+  const int64_t chunk = (int64_t)fm::kNT * (p->mix ? fm::Vpt<float>::v : fm::Vpt<double>::v);
+  const int64_t sblocks = (p->n + chunk - 1) / chunk;
+  p->sgrid = (int)(sblocks < kMaxGrid ? sblocks : kMaxGrid);
+  if (p->sgrid < 1) p->sgrid = 1;
+  auto cleanup = [&](fm_status st) {
+    free_plan(p);
+    return st;
+  };
+  if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(FM_ERR_HIP, "hipGetDevice failed"));
+  const size_t n = (size_t)p->n, ts = p->tsize, L = (size_t)prm->necho;
+  const size_t trace_bytes = sizeof(double) * FM_TR_W * ((size_t)prm->niter + 1);
+#define FM_ALLOC(ptr, bytes)                                                          \
+  if (!plan_alloc(p, (void **)&(ptr), (bytes)))                                       \
+    return cleanup(fail(FM_ERR_ALLOC, "hipMalloc of " #ptr " failed"));
+#define FM_ALLOC_PAD(ptr, esize)                                                      \
+  if (!plan_alloc_padded(p, (void **)&(ptr), n, (esize)))                             \
+    return cleanup(fail(FM_ERR_ALLOC, "hipMalloc of " #ptr " failed"));
+  FM_ALLOC(p->dat, 2 * ts * L * n);
+  FM_ALLOC(p->code, n);
+  for (int i = 0; i < 2; ++i) {
+    FM_ALLOC_PAD(p->F[i], ts);
+    FM_ALLOC_PAD(p->Z[i], ts);
+    FM_ALLOC_PAD(p->G[i], ts);
+  }
+  FM_ALLOC_PAD(p->D, ts);
+  FM_ALLOC_PAD(p->X, ts);
+  FM_ALLOC_PAD(p->P, ts);
+  FM_ALLOC_PAD(p->ipiv, sizeof(double));
+  FM_ALLOC_PAD(p->hinv, sizeof(double));
+  FM_ALLOC(p->S, sizeof(fm::State) * 2);
+  FM_ALLOC(p->part, sizeof(double) * 2 * kMaxGrid * kMaxK);
+  FM_ALLOC(p->setup_part, sizeof(double) * kMaxGrid * kMaxK);
+  FM_ALLOC(p->nmask, sizeof(double));
+  FM_ALLOC(p->status, sizeof(int32_t));
+  FM_ALLOC(p->trace, trace_bytes);
+  FM_ALLOC(p->f0buf, sizeof(double) * n);
+  if (prm->model == FM_WATERFAT) {
+    FM_ALLOC(p->rho, sizeof(double) * n);
+    FM_ALLOC(p->gabs, sizeof(double) * L * L);
+    FM_ALLOC(p->wf_tmp, sizeof(double) * n * 4);
+  }
+#undef FM_ALLOC
+#undef FM_ALLOC_PAD
+  if (hipMemset(p->S, 0, sizeof(fm::State) * 2) != hipSuccess || hipMemset(p->status, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(p->nmask, 0, sizeof(double)) != hipSuccess || hipMemset(p->trace, 0, trace_bytes) != hipSuccess ||
+      hipMemset(p->part, 0, sizeof(double) * 2 * kMaxGrid * kMaxK) != hipSuccess)
+    return cleanup(fail(FM_ERR_HIP, "hipMemset of the plan state failed"));
+  const auto G = make_gamma(*prm);
+  fm_status st = p->mix ? upload_pairs<float>(p, G, &p->pairs) : upload_pairs<double>(p, G, &p->pairs);
+  if (st) return cleanup(st);
+  st = upload_pairs<double>(p, G, &p->pairs_d);
+  if (st) return cleanup(st);
+  if (p->gabs) {
+    std::vector<double> ga((size_t)L * L);
+    for (size_t i = 0; i < ga.size(); ++i) ga[i] = std::abs(G[i]);
+    if (hipMemcpy(p->gabs, ga.data(), sizeof(double) * ga.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(FM_ERR_HIP, "upload of |Gamma| failed"));
+  }
+  if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(fail(FM_ERR_HIP, "hipStreamCreate failed"));
+  *out = p;
+  return FM_OK;
+}
+
+fm_status fm_plan_destroy(fm_plan *p) {
+  if (!p) return FM_OK;
+  free_plan(p);
+  return FM_OK;
+}
+
+fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *mask, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!y || !mask) return fail(FM_ERR_ARG, "y and mask must not be NULL");
+  if (!sens && p->prm.ncoil != 1) return fail(FM_ERR_ARG, "sens may be NULL only when ncoil == 1");
+  const double two_pi = 6.283185307179586476925286766559;
+  auto launch = [&](auto tag) -> fm_status {
+    using T = decltype(tag);
+    fm::SetupArgs<T> a{};
+    a.geo = p->geo;
+    a.ncoil = p->prm.ncoil;
+    a.L = p->prm.necho;
+    a.y = (const float2 *)y;
+    a.sens = (const float2 *)sens;
+    a.mask = mask;
+    a.dat = (fm::T2<T> *)p->dat;
+    a.code = p->code;
+    a.f0 = p->f0buf;
+    a.inv_2pi_dt = 1.0 / (two_pi * (p->prm.te[1] - p->prm.te[0]));
+    a.rho = p->rho;
+    a.gabs = p->gabs;
+    a.pairs_d = (const fm::PairC<double> *)p->pairs_d;
+    a.npairs = p->npairs;
+    if (p->prm.model == FM_WATERFAT) {
+      // sweep over [-|df|/2, |df|/2], df the offset of the largest fat peak
+      int big = 0;
+      for (int q = 1; q < p->prm.npeak; ++q)
+        if (p->prm.fat_amp[q] > p->prm.fat_amp[big]) big = q;
+      a.nsweep = p->prm.nsweep;
+      a.sweep_half = std::fabs(p->prm.fat_hz[big]) / 2.0;
+      a.ftilde = p->wf_tmp;
+    }
+    a.partials = p->setup_part;
+    hipLaunchKernelGGL(fm::k_setup<T>, dim3(p->grid), dim3(kBlock), 0, s, a);
+    FM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(fm::k_count, dim3(1), dim3(kBlock), 0, s, (const double *)p->setup_part, p->grid, p->nmask);
+    FM_LAUNCH_CHECK();
+    return FM_OK;
+  };
+  fm_status st = p->mix ? launch(float{}) : launch(double{});
+  if (st) return st;
+  p->setup_done = true;
+  return FM_OK;
+}
+
+fm_status fm_init(fm_plan *p, double *f0, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!f0) return fail(FM_ERR_ARG, "f0 must not be NULL");
+  if (!p->setup_done) return fail(FM_ERR_STATE, "fm_init needs fm_setup first");
+  if (p->prm.model == FM_WATERFAT) return wf_init(p, f0, s);
+  FM_HIP(hipMemcpyAsync(f0, p->f0buf, sizeof(double) * p->n, hipMemcpyDeviceToDevice, s));
+  return FM_OK;
+}
+
+fm_status fm_eval(fm_plan *p, const double *f, double *phi, double *dphi, double *curv, double *lap,
+                  hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!f) return fail(FM_ERR_ARG, "f must not be NULL");
+  if (!p->setup_done) return fail(FM_ERR_STATE, "fm_eval needs fm_setup first");
+  return dispatch<OpEval>(p, f, phi, dphi, curv, lap, s);
+}
+
+fm_status fm_precondition(fm_plan *p, const double *curv, const double *g, double *piv, double *pout,
+                          hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!curv || !g || !pout) return fail(FM_ERR_ARG, "curv, g and p must not be NULL");
+  if (!p->setup_done) return fail(FM_ERR_STATE, "fm_precondition needs fm_setup first");
+  auto run = [&](auto tag) -> fm_status {
+    using T = decltype(tag);
+    hipLaunchKernelGGL(fm::k_to_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, curv, (T *)p->D);
+    FM_LAUNCH_CHECK();
+    hipLaunchKernelGGL(fm::k_to_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, g, (T *)p->G[0]);
+    FM_LAUNCH_CHECK();
+    FM_HIP(hipMemsetAsync(p->status, 0, sizeof(int32_t), s));
+    const uint64_t q = p->q++;
+    hipLaunchKernelGGL(fm::k_state_init, dim3(1), dim3(1), 0, s, p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls);
+    FM_LAUNCH_CHECK();
+    if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) {
+      hipLaunchKernelGGL(fm::k_hinv<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, p->prm.beta,
+                         (const uint8_t *)p->code, (const T *)p->D, p->hinv, p->status);
+      FM_LAUNCH_CHECK();
+    }
+    fm_status st = enqueue_precond<T>(p, (const T *)p->G[0], s);
+    if (st) return st;
+    hipLaunchKernelGGL(fm::k_from_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const T *)p->P, pout);
+    FM_LAUNCH_CHECK();
+    if (piv) {
+      hipLaunchKernelGGL(fm::k_pivots, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const double *)p->ipiv, piv);
+      FM_LAUNCH_CHECK();
+    }
+    int32_t status = 0;
+    fm_status rs = read_status(p, s, &status);
+    if (rs) return rs;
+    if (status) return fail((fm_status)status, "preconditioner: non-positive pivot");
+    return FM_OK;
+  };
+  p->solved = false;  // the iteration state was overwritten
+  return p->mix ? run(float{}) : run(double{});
+}
+
+fm_status fm_solve(fm_plan *p, const void *y, const void *sens, const uint8_t *mask, const double *f0,
+                   double *f_out, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!f_out) return fail(FM_ERR_ARG, "f_out must not be NULL");
+  fm_status st = fm_setup(p, y, sens, mask, s);
+  if (st) return st;
+  const double *start = f0;
+  if (!start) {
+    if (p->prm.model == FM_WATERFAT) {
+      st = wf_init(p, p->f0buf, s);
+      if (st) return st;
+    }
+    start = p->f0buf;
+  }
+  FM_HIP(hipMemsetAsync(p->status, 0, sizeof(int32_t), s));
+  p->q = 0;
+  st = p->mix ? enqueue_start<float>(p, start, s) : enqueue_start<double>(p, start, s);
+  if (st) return st;
+  st = run_iterations(p, p->prm.niter, s);
+  if (st) return st;
+  st = dispatch<OpFinal>(p, f_out, s);
+  if (st) return st;
+  p->solved = true;
+  return FM_OK;
+}
+
+fm_status fm_iterate(fm_plan *p, int32_t niter, double *f_out, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!p->solved) return fail(FM_ERR_STATE, "fm_iterate needs a previous fm_solve");
+  if (niter < 0 || !f_out) return fail(FM_ERR_ARG, "niter must be >= 0 and f_out not NULL");
+  fm_status st = run_iterations(p, niter, s);
+  if (st) return st;
+  return dispatch<OpFinal>(p, f_out, s);
+}
+
+fm_status fm_time_kernels(fm_plan *p, int32_t niter, double *ms, int32_t *launches, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!ms || !launches || niter < 0) return fail(FM_ERR_ARG, "bad arguments to fm_time_kernels");
+  if (!p->solved) return fail(FM_ERR_STATE, "fm_time_kernels needs a previous fm_solve");
+  for (int k = 0; k < FM_NK; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  Recorder rec;
+  rec.s = s;
+  for (int i = 0; i < niter; ++i) {
+    fm_status st = dispatch<OpIterationTimed>(p, s, &rec);
+    if (st) return st;
+    if (rec.err != hipSuccess) return fail(FM_ERR_HIP, std::string("event record: ") + hipGetErrorString(rec.err));
+  }
+  FM_HIP(hipStreamSynchronize(s));
+  for (size_t k = 0; k < rec.cls.size(); ++k) {
+    float t = 0.f;
+    FM_HIP(hipEventElapsedTime(&t, rec.ev[2 * k], rec.ev[2 * k + 1]));
+    ms[rec.cls[k]] += t;
+    launches[rec.cls[k]] += 1;
+  }
+  return FM_OK;
+}
+
+fm_status fm_get_trace(fm_plan *p, double *trace, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!trace) return fail(FM_ERR_ARG, "trace must not be NULL");
+  FM_HIP(hipMemcpyAsync(trace, p->trace, sizeof(double) * FM_TR_W * ((size_t)p->prm.niter + 1),
+                        hipMemcpyDeviceToHost, s));
+  int32_t status = 0;
+  fm_status rs = read_status(p, s, &status);
+  if (rs) return rs;
+  if (status) return fail((fm_status)status, "the solve reported a device-side error");
+  return FM_OK;
+}
+
+fm_status fm_mask_count(fm_plan *p, int64_t *count, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!count) return fail(FM_ERR_ARG, "count must not be NULL");
+  if (!p->setup_done) return fail(FM_ERR_STATE, "fm_mask_count needs fm_setup first");
+  double v = 0.0;
+  FM_HIP(hipMemcpyAsync(&v, p->nmask, sizeof(double), hipMemcpyDeviceToHost, s));
+  FM_HIP(hipStreamSynchronize(s));
+  *count = (int64_t)v;
+  return FM_OK;
+}
+
+}  // extern "C"
+
+// Water-fat initialisation lives with the rest of the plan internals.
+#include "fm_waterfat.inc"

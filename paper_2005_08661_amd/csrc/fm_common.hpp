@@ -1,0 +1,346 @@
+// Device-side building blocks shared by the field-map kernels: the scalar
+// state carried from kernel to kernel, the mask/neighbour code, deterministic
+// FP64 reductions and the per-voxel echo-pair data term.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fm {
+
+constexpr int kBlock = 256;      // threads per block of the streaming kernels
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kMaxGrid = 512;    // blocks (hence partial sums) of a streaming pass
+constexpr int kMaxK = 4;         // values reduced per kernel
+
+// Neighbour code of a voxel: bit 0 = inside the mask; bits 1..6 = the
+// -x, +x, -y, +y, -z, +z neighbour is inside the volume and the mask (only set
+// for in-mask voxels).  deg = number of in-mask neighbours.
+// Bit 7 marks the black voxels (x+y+z odd) of the red-black ordering.
+enum : uint32_t { NB_SELF = 1u, NB_XM = 2u, NB_XP = 4u, NB_YM = 8u, NB_YP = 16u, NB_ZM = 32u, NB_ZP = 64u,
+                  NB_BLACK = 128u };
+
+__device__ __forceinline__ int nb_deg(uint32_t c) { return __popc((c >> 1) & 63u); }
+
+// What the partial sums handed from one kernel to the next contain.
+enum PartKind : int32_t {
+  PK_NONE = 0,   // nothing to consume
+  PK_GRAD = 1,   // sum phi, f^T C^T C f, ||g||^2, z_prev^T g
+  PK_DOTS_A = 2, // first half of g^T p, g_prev^T p (red-black: black voxels)
+  PK_DOTS = 3,   // (rest of) g^T p, g_prev^T p
+  PK_DIR = 4,    // z^T C^T C f, ||C z||^2, sum z^2 D
+  PK_MLS = 5,    // S1 = z^T dphi(f + alpha z), S2 = sum z^2 d(f + alpha z)
+  PK_COUNT = 6,  // in-mask voxel count
+};
+
+// Scalar state of one solve.  Two copies ping-pong along the kernel chain:
+// a kernel reads copy q&1 (and the partial sums its predecessor wrote), every
+// block derives the same updated scalars, and block 0 writes copy (q+1)&1.
+struct State {
+  double alpha;     // line-search step
+  double mu;        // Polak-Ribiere coefficient
+  double gtp;       // g^T p
+  double gtp_prev;  // g^T p of the previous iteration
+  double gpp;       // g_prev^T p
+  double acc0, acc1;// first halves of g^T p, g_prev^T p (red-black)
+  double zpg;       // z_prev^T g
+  double ztg;       // z^T g
+  double A;         // z^T C^T C f
+  double B;         // ||C z||^2
+  double cost;      // Psi at the start of the iteration
+  double gnorm2;    // ||g||^2
+  double nmask;     // in-mask voxels
+  int32_t iter;     // current iteration
+  int32_t restart;  // direction reset in the current iteration
+  int32_t ls_left;  // line-search steps still to apply in this iteration
+  int32_t kind;     // PartKind of the incoming partial sums
+  int32_t nparts;   // number of incoming partial blocks
+  int32_t nmls;     // line-search steps per iteration
+  int32_t trace_cap;// rows of the trace (iterations recorded)
+  int32_t ls_done;  // line search of this iteration stopped (zero curvature)
+};
+
+// Per echo-pair constants (m < n): weight factor 2|Gamma_mn|, phase of
+// Gamma_mn in turns, dt = t_m - t_n and 2*pi*dt.
+template <typename T>
+struct PairC {
+  T w;
+  T g;
+  T dt;
+  T d2pi;
+  int32_t m, n;
+  int32_t pad[2];
+};
+
+// ---------------------------------------------------------------------------
+// sin(x)/x and cos(x) for |x| <= pi/2 from their Taylor series, truncated
+// where the remainder falls below the type's rounding: FP32 through the x^10
+// (sin) and x^12 (cos) terms (remainder <= 4e-8 at pi/2), FP64 through x^20
+// (remainder <= 2e-17).  The coefficients are (-1)^k / (2k+1)! and
+// (-1)^k / (2k)!.  No division and no special case at x = 0.
+__device__ __forceinline__ void sinx_cos(float x, float &sx, float &c) {
+  const float x2 = x * x;
+  sx = 1.f + x2 * (-1.f / 6.f + x2 * (1.f / 120.f + x2 * (-1.f / 5040.f + x2 * (1.f / 362880.f +
+       x2 * (-1.f / 39916800.f)))));
+  c = 1.f + x2 * (-0.5f + x2 * (1.f / 24.f + x2 * (-1.f / 720.f + x2 * (1.f / 40320.f +
+      x2 * (-1.f / 3628800.f + x2 * (1.f / 479001600.f))))));
+}
+
+__device__ __forceinline__ void sinx_cos(double x, double &sx, double &c) {
+  const double x2 = x * x;
+  sx = 1.0 + x2 * (-1.0 / 6.0 + x2 * (1.0 / 120.0 + x2 * (-1.0 / 5040.0 + x2 * (1.0 / 362880.0 +
+       x2 * (-1.0 / 39916800.0 + x2 * (1.0 / 6227020800.0 + x2 * (-1.0 / 1307674368000.0 +
+       x2 * (1.0 / 355687428096000.0 + x2 * (-1.0 / 121645100408832000.0 +
+       x2 * (1.0 / 51090942171709440000.0))))))))));
+  c = 1.0 + x2 * (-0.5 + x2 * (1.0 / 24.0 + x2 * (-1.0 / 720.0 + x2 * (1.0 / 40320.0 +
+      x2 * (-1.0 / 3628800.0 + x2 * (1.0 / 479001600.0 + x2 * (-1.0 / 87178291200.0 +
+      x2 * (1.0 / 20922789888000.0 + x2 * (-1.0 / 6402373705728000.0 +
+      x2 * (1.0 / 2432902008176640000.0))))))))));
+}
+
+__device__ __forceinline__ float rint_t(float x) { return rintf(x); }
+__device__ __forceinline__ double rint_t(double x) { return rint(x); }
+
+// Per-voxel data term at field value f (Hz) over the echo pairs.  The phase
+// of pair (m,n) is 2 pi xi with xi = angle(Gamma_mn)/2pi + tau_n - tau_m + f dt
+// (turns).  With h = xi - rint(xi) in [-1/2, 1/2] (the wrap of reading R4),
+// x = pi h, sx = sin(x)/x, s = x sx and c = cos(x):
+//   1 - cos(2 pi xi) = 2 s^2,   sin(2 pi xi) = 2 s c,   sinc(2 pi h) = sx c.
+template <typename T, int LMAX>
+__device__ __forceinline__ void voxel_terms(const T (&rho)[LMAX], const T (&tau)[LMAX], int L,
+                                            const PairC<T> *__restrict__ pc, T f, T &phi, T &dphi,
+                                            T &curv) {
+  T c0 = 0, c1 = 0, c2 = 0;
+  int q = 0;
+#pragma unroll
+  for (int m = 0; m < LMAX; ++m) {
+#pragma unroll
+    for (int n = m + 1; n < LMAX; ++n) {
+      if (n < L) {
+        const PairC<T> P = pc[q];
+        const T w = P.w * rho[m] * rho[n];
+        const T xi = P.g + (tau[n] - tau[m]) + f * P.dt;
+        const T x = T(3.14159265358979323846) * (xi - rint_t(xi));
+        T sx, c;
+        sinx_cos(x, sx, c);
+        const T s = x * sx;
+        const T wd = w * P.d2pi;
+        c0 += w * (T(2) * s * s);
+        c1 += wd * (T(2) * s * c);
+        c2 += wd * P.d2pi * (sx * c);
+        ++q;
+      }
+    }
+  }
+  phi = c0;
+  dphi = c1;
+  curv = c2;
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic FP64 reductions without atomics.  A kernel reduces its K
+// values per block and stores one partial per block; the next kernel in the
+// stream has every block sum all partials in the same fixed order, so every
+// block obtains bit-identical totals (kernel boundaries order the accesses).
+// DPP move of a double (both halves) with the given control; lanes whose
+// source is outside the row, or that the masks disable, read 0.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, BANK_MASK, true);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, BANK_MASK, true);
+  return __hiloint2double(hi2, lo2);
+}
+
+// Wavefront sum with DPP row shifts and row broadcasts: lane 15 of each row
+// collects its row, the broadcasts fold rows 0..3 into lane 63, which is then
+// read by every lane.  Fixed order, hence deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+  double t = v + dpp_d<0x111>(v);    // row_shr:1
+  t = t + dpp_d<0x112>(v);           // row_shr:2
+  t = t + dpp_d<0x113>(v);           // row_shr:3
+  t = t + dpp_d<0x114, 0xf, 0xe>(t); // row_shr:4, banks 1-3
+  t = t + dpp_d<0x118, 0xf, 0xc>(t); // row_shr:8, banks 2-3
+  t = t + dpp_d<0x142, 0xa, 0xf>(t); // row_bcast:15 into rows 1 and 3
+  t = t + dpp_d<0x143, 0xc, 0xf>(t); // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(t), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(t), 63);
+  return __hiloint2double(hi, lo);
+}
+
+template <int K>
+__device__ __forceinline__ void wave_reduce(double (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+}
+
+// Block-wide sum (blockDim.x == NT); result valid in every thread.
+template <int K, int NT = kBlock>
+__device__ __forceinline__ void block_sum(double (&v)[K]) {
+  __shared__ double red[K][NT / kWave];
+  wave_reduce<K>(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k][wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / kWave; ++w) s += red[k][w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// Store this block's K partial sums (layout [block][kMaxK], unused slots 0).
+template <int K, int NT = kBlock>
+__device__ __forceinline__ void store_partials(double (&v)[K], double *__restrict__ pout) {
+  static_assert(K <= kMaxK, "too many reduced values");
+  block_sum<K, NT>(v);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) pout[(size_t)blockIdx.x * kMaxK + k] = (k < K) ? v[k] : 0.0;
+  }
+}
+
+// Sum the predecessor's partials; every thread gets the totals.
+template <int NT = kBlock>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ pin, int nparts, double (&tot)[kMaxK]) {
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) tot[k] = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += NT) {
+#pragma unroll
+    for (int k = 0; k < kMaxK; ++k) tot[k] += pin[(size_t)b * kMaxK + k];
+  }
+  block_sum<kMaxK, NT>(tot);
+}
+
+__device__ __forceinline__ void set_status(int32_t *status, int code) { atomicCAS(status, 0, code); }
+
+// Apply the incoming partial sums to the scalar state (identically in every
+// block).  trace (row-major [trace_cap+1][8]) is written by block 0 only.
+__device__ __forceinline__ void consume(State &s, const double (&t)[kMaxK], double beta, double *trace,
+                                        int32_t *status) {
+  const bool w = (blockIdx.x == 0 && threadIdx.x == 0);
+  switch (s.kind) {
+    case PK_GRAD: {
+      s.cost = t[0] + 0.5 * beta * t[1];
+      s.gnorm2 = t[2];
+      s.zpg = t[3];
+      if (w && s.iter <= s.trace_cap) trace[(size_t)s.iter * 8 + 0] = s.cost;
+      if (w && !(isfinite(s.cost) && isfinite(s.gnorm2))) set_status(status, 6);
+      break;
+    }
+    case PK_DOTS_A: {
+      s.acc0 = t[0];
+      s.acc1 = t[1];
+      break;
+    }
+    case PK_DOTS: {
+      // Polak-Ribiere conjugacy with restart (readings R6, R7)
+      const double gtp = s.acc0 + t[0];
+      const double gpp = s.acc1 + t[1];
+      double mu = (s.gtp_prev != 0.0) ? (gtp - gpp) / s.gtp_prev : 0.0;
+      double ztg = -gtp + mu * s.zpg;
+      int restart = 0;
+      if (ztg >= 0.0) {
+        mu = 0.0;
+        ztg = -gtp;
+        restart = 1;
+      }
+      s.gtp = gtp;
+      s.gpp = gpp;
+      s.mu = mu;
+      s.ztg = ztg;
+      s.restart = restart;
+      s.acc0 = 0.0;
+      s.acc1 = 0.0;
+      if (w && s.iter < s.trace_cap) {
+        double *r = trace + (size_t)s.iter * 8;
+        r[1] = gtp;
+        r[2] = mu;
+        r[3] = (double)restart;
+        r[5] = ztg;
+        r[7] = s.gnorm2;
+      }
+      break;
+    }
+    case PK_DIR: {
+      // first line-search step from alpha = 0: alpha = -z^T g / (d0 + beta B)
+      s.A = t[0];
+      s.B = t[1];
+      const double den = t[2] + beta * t[1];
+      s.ls_left = s.nmls - 1;  // line-search passes still to consume
+      s.ls_done = 0;
+      if (den > 0.0) {
+        s.alpha = -s.ztg / den;
+      } else {
+        s.alpha = 0.0;
+        s.ls_done = 1;
+      }
+      if (w && s.iter < s.trace_cap) trace[(size_t)s.iter * 8 + 6] = t[1];
+      break;
+    }
+    case PK_MLS: {
+      // eq. (ls_update): alpha <- alpha - (S1 + beta A + alpha beta B) / (S2 + beta B)
+      if (!s.ls_done) {
+        const double den = t[1] + beta * s.B;
+        if (den > 0.0) {
+          s.alpha = s.alpha - (t[0] + beta * s.A + s.alpha * beta * s.B) / den;
+        } else {
+          s.ls_done = 1;
+        }
+      }
+      s.ls_left -= 1;
+      break;
+    }
+    default:
+      break;
+  }
+  // The iteration ends once its last line-search pass has been consumed.
+  if ((s.kind == PK_DIR || s.kind == PK_MLS) && s.ls_left == 0) {
+    if (w && s.iter < s.trace_cap) trace[(size_t)s.iter * 8 + 4] = s.alpha;
+    if (w && !isfinite(s.alpha)) set_status(status, 6);
+    s.gtp_prev = s.gtp;
+    s.iter += 1;
+  }
+  s.kind = PK_NONE;
+  s.nparts = 0;
+}
+
+// Iteration index after the incoming partials are consumed, known before the
+// partials are summed (lets a kernel issue its loads first).
+__device__ __forceinline__ int iter_after(const State &s) {
+  if (s.kind == PK_DIR) return s.iter + (s.nmls == 1 ? 1 : 0);
+  if (s.kind == PK_MLS) return s.iter + (s.ls_left == 1 ? 1 : 0);
+  return s.iter;
+}
+
+// Common prologue: load the incoming state, sum the incoming partials and
+// apply them.  Returns the updated state (identical in every block).
+template <int NT = kBlock>
+__device__ __forceinline__ State take_state(const State *__restrict__ sin, const double *__restrict__ pin,
+                                            double beta, double *trace, int32_t *status) {
+  State s = *sin;
+  if (s.kind != PK_NONE) {
+    double t[kMaxK];
+    sum_partials<NT>(pin, s.nparts, t);
+    consume(s, t, beta, trace, status);
+  }
+  return s;
+}
+
+// Epilogue: block 0 publishes the state with the kind of partials it leaves.
+__device__ __forceinline__ void put_state(State s, State *__restrict__ sout, int kind, int nparts) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    s.kind = kind;
+    s.nparts = nparts;
+    *sout = s;
+  }
+}
+
+}  // namespace fm

@@ -1,0 +1,417 @@
+// HIP kernels of the preconditioned NCG-MLS field-map iteration for gfx950.
+//
+// Storage: every per-voxel array is z fastest (j = (x*ny + y)*nz + z).
+// T is the per-voxel storage/arithmetic type (double for F64, float for MIX);
+// pivots, reductions and scalars are always FP64.
+//
+// Ping-pong buffers keyed by the iteration index i held on the device:
+//   F[i&1] = f^i, Z[i&1] = z^i, G[i&1] = g^i; index (i+1)&1 holds the
+//   previous iterate (f^{i-1}, z^{i-1}, g^{i-1}).
+#pragma once
+
+#include "fm_common.hpp"
+
+namespace fm {
+
+template <typename T>
+struct T2 {
+  T x, y;
+};
+
+struct Geo {
+  int32_t nx, ny, nz;
+  int64_t n;
+  int64_t sx, sy;  // strides of x and y (z stride is 1)
+};
+
+// ---------------------------------------------------------------------------
+// Setup (Sec. II eq. (r), the Algorithm's precompute): coil combination into
+// per-echo magnitude |zhat_l| and phase angle(zhat_l)/2pi (turns), the
+// neighbour code, the in-mask count, the field-map initial value of eq. (w0)
+// and, for water-fat, the PWLS weight rho_j of Sec. III-A.
+template <typename T>
+struct SetupArgs {
+  Geo geo;
+  int32_t ncoil, L;
+  const float2 *y;     // [ncoil][L][n]
+  const float2 *sens;  // [ncoil][n] or nullptr
+  const uint8_t *mask;
+  T2<T> *dat;          // [L][n] (|zhat|, angle/2pi)
+  uint8_t *code;
+  double *f0;          // field-map init output (double) or nullptr
+  double inv_2pi_dt;   // 1 / (2 pi (t_2 - t_1))
+  double *rho;         // water-fat PWLS weights or nullptr
+  const double *gabs;  // [L*L] |Gamma_mn| (water-fat) or nullptr
+  const PairC<double> *pairs_d;  // FP64 pair table for the water-fat sweep
+  int32_t npairs;
+  int32_t nsweep;      // water-fat sweep values (0 = no sweep)
+  double sweep_half;   // |delta_f| / 2
+  double *ftilde;      // water-fat sweep output or nullptr
+  double *partials;    // [gridDim.x][kMaxK] in-mask counts
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
+  const Geo g = a.geo;
+  double cnt[1] = {0.0};
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
+    const int32_t z = (int32_t)(j % g.nz);
+    const int32_t yy = (int32_t)((j / g.nz) % g.ny);
+    const int32_t x = (int32_t)(j / g.sx);
+    const bool in = a.mask[j] != 0;
+    uint32_t c = 0;
+    if (in) {
+      c = NB_SELF;
+      if ((x + yy + z) & 1) c |= NB_BLACK;
+      if (x > 0 && a.mask[j - g.sx]) c |= NB_XM;
+      if (x < g.nx - 1 && a.mask[j + g.sx]) c |= NB_XP;
+      if (yy > 0 && a.mask[j - g.sy]) c |= NB_YM;
+      if (yy < g.ny - 1 && a.mask[j + g.sy]) c |= NB_YP;
+      if (z > 0 && a.mask[j - 1]) c |= NB_ZM;
+      if (z < g.nz - 1 && a.mask[j + 1]) c |= NB_ZP;
+      cnt[0] += 1.0;
+    }
+    a.code[j] = (uint8_t)c;
+    // sum of squares of the coil maps
+    double ss = 0.0;
+    if (a.sens) {
+      for (int cc = 0; cc < a.ncoil; ++cc) {
+        const float2 s = a.sens[(int64_t)cc * g.n + j];
+        ss += (double)s.x * s.x + (double)s.y * s.y;
+      }
+    } else {
+      ss = 1.0;
+    }
+    const double scale = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
+    double z1r = 0, z1i = 0, z2r = 0, z2i = 0;
+    double mag[16], ph[16];
+    for (int l = 0; l < a.L; ++l) {
+      double re = 0.0, im = 0.0;
+      for (int cc = 0; cc < a.ncoil; ++cc) {
+        const float2 yv = a.y[((int64_t)cc * a.L + l) * g.n + j];
+        if (a.sens) {
+          const float2 s = a.sens[(int64_t)cc * g.n + j];
+          re += (double)s.x * yv.x + (double)s.y * yv.y;
+          im += (double)s.x * yv.y - (double)s.y * yv.x;
+        } else {
+          re += yv.x;
+          im += yv.y;
+        }
+      }
+      re *= scale;
+      im *= scale;
+      if (l == 0) { z1r = re; z1i = im; }
+      if (l == 1) { z2r = re; z2i = im; }
+      mag[l] = sqrt(re * re + im * im);
+      ph[l] = atan2(im, re) * 0.15915494309189533577;
+      T2<T> d;
+      d.x = (T)mag[l];
+      d.y = (T)ph[l];
+      a.dat[(int64_t)l * g.n + j] = d;
+    }
+    if (a.ftilde) {
+      // Sec. III-A water-fat start: the sweep value of least per-voxel cost
+      // (first one on ties), evaluated in FP64 in every precision mode.
+      double best = 1.0 / 0.0, bestf = 0.0;
+      if (in) {
+        for (int q = 0; q < a.nsweep; ++q) {
+          const double fs = -a.sweep_half + 2.0 * a.sweep_half * q / (a.nsweep - 1);
+          double c0 = 0.0;
+          for (int pq = 0; pq < a.npairs; ++pq) {
+            const PairC<double> P = a.pairs_d[pq];
+            const double xi = P.g + (ph[P.n] - ph[P.m]) + fs * P.dt;
+            const double h = xi - rint(xi);
+            const double s = sinpi(h);
+            c0 += P.w * mag[P.m] * mag[P.n] * (2.0 * s * s);
+          }
+          if (c0 < best) {
+            best = c0;
+            bestf = fs;
+          }
+        }
+      }
+      a.ftilde[j] = in ? bestf : 0.0;
+    }
+    if (a.f0) {
+      // eq. (w0): angle(conj(z_1) z_2) / (2 pi (t_2 - t_1))
+      const double pr = z1r * z2r + z1i * z2i, pi = z1r * z2i - z1i * z2r;
+      a.f0[j] = in ? atan2(pi, pr) * a.inv_2pi_dt : 0.0;
+    }
+    if (a.rho) {
+      // rho_j = (1/S_j) sum_{m,n} |Gamma_mn| a_m a_n, a_m = sum_c |s_c| |y_cm|
+      double av[16];
+      for (int m = 0; m < a.L; ++m) {
+        double am = 0.0;
+        for (int cc = 0; cc < a.ncoil; ++cc) {
+          const float2 yv = a.y[((int64_t)cc * a.L + m) * g.n + j];
+          double sm = 1.0;
+          if (a.sens) {
+            const float2 s = a.sens[(int64_t)cc * g.n + j];
+            sm = sqrt((double)s.x * s.x + (double)s.y * s.y);
+          }
+          am += sm * sqrt((double)yv.x * yv.x + (double)yv.y * yv.y);
+        }
+        av[m] = am;
+      }
+      double r = 0.0;
+      for (int m = 0; m < a.L; ++m)
+        for (int n2 = 0; n2 < a.L; ++n2) r += a.gabs[m * a.L + n2] * av[m] * av[n2];
+      a.rho[j] = (in && ss > 0.0) ? r / ss : 0.0;
+    }
+  }
+  store_partials<1>(cnt, a.partials);
+}
+
+// In-mask count from the setup partials (one block).
+__global__ __launch_bounds__(kBlock) void k_count(const double *__restrict__ partials, int nparts, double *nmask) {
+  double t[kMaxK];
+  sum_partials(partials, nparts, t);
+  if (threadIdx.x == 0) *nmask = t[0];
+}
+
+// Fresh scalar state (block 0 writes it).
+__device__ __forceinline__ void init_state(State *sout, int trace_cap, int nmls, const double *nmask) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    State s{};
+    s.iter = 0;
+    s.kind = PK_NONE;
+    s.nparts = 0;
+    s.nmls = nmls;
+    s.trace_cap = trace_cap;
+    s.nmask = nmask ? *nmask : 0.0;
+    *sout = s;
+  }
+}
+
+// Start of a solve: fresh state and the initial map in F[1] (the slot read as
+// the previous iterate by the first gradient pass), zero previous direction
+// and gradient.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_start(Geo g, const double *__restrict__ f0,
+                                                   const uint8_t *__restrict__ code, T *Fprev,
+                                                   T *Zprev, T *Gprev, State *sout, int trace_cap, int nmls,
+                                                   const double *nmask) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
+    Fprev[j] = (code[j] & NB_SELF) ? (T)f0[j] : T(0);
+    Zprev[j] = T(0);
+    Gprev[j] = T(0);
+  }
+  init_state(sout, trace_cap, nmls, nmask);
+}
+
+__global__ void k_state_init(State *sout, int trace_cap, int nmls) { init_state(sout, trace_cap, nmls, nullptr); }
+
+// ---------------------------------------------------------------------------
+// Gradient pass of iteration i (Sec. III eq. (ls_grad), fused with the update
+// f^i = f^{i-1} + alpha z^{i-1} of the previous iteration):
+//   g_j = dphi_j(f_j) + beta (C^T C f)_j,  D_j = Huber curvature (eq. (ls_huber)).
+// Grid totals: sum phi, f^T C^T C f, ||g||^2, z_prev^T g.
+template <typename T>
+struct IterArgs {
+  Geo geo;
+  int32_t L;
+  double beta;
+  const T2<T> *dat;
+  const uint8_t *code;
+  const PairC<T> *pairs;
+  T *F[2];
+  T *Z[2];
+  T *G[2];
+  T *D;
+  T *X;
+  T *P;
+  double *ipiv;  // 1 / pivot
+  double *hinv;  // 1 / (D + beta deg), written by the gradient pass when needed
+  int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0))
+  int32_t store_piv;   // preconditioner passes also store every pivot
+  const State *sin;    // incoming scalar state
+  State *sout;         // outgoing scalar state (block 0)
+  const double *pin;   // incoming partial sums
+  double *pout;        // outgoing partial sums
+  int32_t *status;     // sticky device status word
+  double *trace;       // [trace_cap + 1][8]
+  double *fout;        // final pass: user output (double) or nullptr
+  int32_t final_pass;
+};
+
+template <typename T, int LMAX>
+__device__ __forceinline__ void load_echoes(const T2<T> *__restrict__ dat, int64_t n, int j, int L,
+                                            T (&rho)[LMAX], T (&tau)[LMAX]) {
+#pragma unroll
+  for (int l = 0; l < LMAX; ++l) {
+    if (l < L) {
+      const T2<T> *__restrict__ dl = dat + (size_t)l * (size_t)n;  // uniform per echo
+      const T2<T> d = dl[j];
+      rho[l] = d.x;
+      tau[l] = d.y;
+    } else {
+      rho[l] = T(0);
+      tau[l] = T(0);
+    }
+  }
+}
+
+// End of a solve (one block): consume the final gradient pass (the cost of
+// the final map) and leave a state from which the iteration can continue.
+__global__ __launch_bounds__(kBlock) void k_finish(const State *sin, State *sout, const double *pin, double beta,
+                                                    double *trace, int32_t *status) {
+  const State st = take_state(sin, pin, beta, trace, status);
+  put_state(st, sout, PK_NONE, 0);
+}
+
+// ---------------------------------------------------------------------------
+// IC(0) in natural order (Sec. III-B eq. (precon)).  Sqrt-free factor
+// M = (P + E) P^{-1} (P + E^T), E the strictly lower part of
+// H = diag(D + beta deg) - beta A_mask:
+//   P_j = D_j + beta deg_j - beta^2 sum_{k lower nbr} 1/P_k
+//   forward   x_j = (g_j + beta sum_{k lower} x_k) / P_j
+//   backward  p_j = x_j + (beta / P_j) sum_{k upper} p_k
+// Lower neighbours in natural order are -x, -y, -z.  This version sweeps the
+// hyperplanes x+y+z = const inside one workgroup (every voxel of a plane
+// depends only on the previous plane).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ic_fwd_onewg(IterArgs<T> a, const T *__restrict__ gsrc) {
+  const Geo g = a.geo;
+  const State st = take_state<1024>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const int it = st.iter;
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const double beta = a.beta, b2 = a.beta * a.beta;
+  const int64_t ncol = (int64_t)g.nx * g.ny;
+  const int nlev = g.nx + g.ny + g.nz - 2;
+  int bad = 0;
+  for (int lev = 0; lev < nlev; ++lev) {
+    for (int64_t col = threadIdx.x; col < ncol; col += blockDim.x) {
+      const int32_t x = (int32_t)(col / g.ny), yy = (int32_t)(col % g.ny);
+      const int32_t z = lev - x - yy;
+      if (z < 0 || z >= g.nz) continue;
+      const int64_t j = col * g.nz + z;
+      const uint32_t c = a.code[j];
+      if (!(c & NB_SELF)) {
+        a.ipiv[j] = 0.0;
+        a.X[j] = T(0);
+        continue;
+      }
+      double sp = 0.0, sxv = 0.0;
+      if (c & NB_XM) { sp += a.ipiv[j - g.sx]; sxv += (double)a.X[j - g.sx]; }
+      if (c & NB_YM) { sp += a.ipiv[j - g.sy]; sxv += (double)a.X[j - g.sy]; }
+      if (c & NB_ZM) { sp += a.ipiv[j - 1]; sxv += (double)a.X[j - 1]; }
+      const double piv = (double)a.D[j] + beta * nb_deg(c) - b2 * sp;
+      double ip = 1.0 / piv;
+      if (!(piv > 0.0)) { bad = 1; ip = 0.0; }
+      a.ipiv[j] = ip;
+      a.X[j] = (T)(((double)gg[j] + beta * sxv) * ip);
+    }
+    __syncthreads();
+  }
+  if (bad) set_status(a.status, 5);
+  put_state(st, a.sout, PK_NONE, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ic_bwd_onewg(IterArgs<T> a, const T *__restrict__ gsrc) {
+  const Geo g = a.geo;
+  const State st = take_state<1024>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const int it = st.iter;
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const double beta = a.beta;
+  double acc[2] = {0.0, 0.0};
+  const int64_t ncol = (int64_t)g.nx * g.ny;
+  const int nlev = g.nx + g.ny + g.nz - 2;
+  for (int lev = nlev - 1; lev >= 0; --lev) {
+    for (int64_t col = threadIdx.x; col < ncol; col += blockDim.x) {
+      const int32_t x = (int32_t)(col / g.ny), yy = (int32_t)(col % g.ny);
+      const int32_t z = lev - x - yy;
+      if (z < 0 || z >= g.nz) continue;
+      const int64_t j = col * g.nz + z;
+      const uint32_t c = a.code[j];
+      if (!(c & NB_SELF)) {
+        a.P[j] = T(0);
+        continue;
+      }
+      double s = 0.0;
+      if (c & NB_XP) s += (double)a.P[j + g.sx];
+      if (c & NB_YP) s += (double)a.P[j + g.sy];
+      if (c & NB_ZP) s += (double)a.P[j + 1];
+      const T pj = (T)((double)a.X[j] + beta * s * a.ipiv[j]);
+      a.P[j] = pj;
+      acc[0] += (double)gg[j] * (double)pj;
+      acc[1] += (double)gp[j] * (double)pj;
+    }
+    __syncthreads();
+  }
+  store_partials<2, 1024>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS, 1);
+}
+
+// hinv_j = 1 / (D_j + beta deg_j) for the standalone preconditioner call.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_hinv(Geo g, double beta, const uint8_t *__restrict__ code,
+                                                  const T *__restrict__ D, double *hinv, int32_t *status) {
+  int bad = 0;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
+    const uint32_t c = code[j];
+    double v = 0.0;
+    if (c & NB_SELF) {
+      const double h = (double)D[j] + beta * nb_deg(c);
+      if (h > 0.0) v = 1.0 / h; else bad = 1;
+    }
+    hinv[j] = v;
+  }
+  if (bad) set_status(status, 5);
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation at a user-supplied map (row-level checks and the adjoint).
+template <typename T, int LMAX>
+__global__ __launch_bounds__(kBlock) void k_eval(IterArgs<T> a, const double *__restrict__ fu,
+                                                  double *phi_o, double *dphi_o, double *curv_o,
+                                                  double *lap_o) {
+  const Geo g = a.geo;
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
+    const uint32_t c = a.code[j];
+    if (!(c & NB_SELF)) {
+      if (phi_o) phi_o[j] = 0.0;
+      if (dphi_o) dphi_o[j] = 0.0;
+      if (curv_o) curv_o[j] = 0.0;
+      if (lap_o) lap_o[j] = 0.0;
+      continue;
+    }
+    const T fj = (T)fu[j];
+    T lap = T(0);
+    if (c & NB_XM) lap += fj - (T)fu[j - g.sx];
+    if (c & NB_XP) lap += fj - (T)fu[j + g.sx];
+    if (c & NB_YM) lap += fj - (T)fu[j - g.sy];
+    if (c & NB_YP) lap += fj - (T)fu[j + g.sy];
+    if (c & NB_ZM) lap += fj - (T)fu[j - 1];
+    if (c & NB_ZP) lap += fj - (T)fu[j + 1];
+    T rho[LMAX], tau[LMAX];
+    load_echoes<T, LMAX>(a.dat, g.n, (int)j, a.L, rho, tau);
+    T phi, dphi, curv;
+    voxel_terms<T, LMAX>(rho, tau, a.L, a.pairs, fj, phi, dphi, curv);
+    if (phi_o) phi_o[j] = (double)phi;
+    if (dphi_o) dphi_o[j] = (double)dphi;
+    if (curv_o) curv_o[j] = (double)curv;
+    if (lap_o) lap_o[j] = (double)lap;
+  }
+}
+
+// Conversions between user float64 arrays and the working type.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_work(int64_t n, const double *__restrict__ src, T *dst) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
+    dst[j] = (T)src[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_from_work(int64_t n, const T *__restrict__ src, double *dst) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
+    dst[j] = (double)src[j];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pivots(int64_t n, const double *__restrict__ ipiv, double *piv) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n; j += (int64_t)gridDim.x * kBlock)
+    piv[j] = ipiv[j] > 0.0 ? 1.0 / ipiv[j] : 0.0;
+}
+
+}  // namespace fm

@@ -1,0 +1,451 @@
+// Streaming passes of one NCG iteration (gradient, red-black / diagonal
+// preconditioner, direction, line search).
+//
+// Launch shape: blocks of kNT threads, each thread owning V voxels of a chunk
+// of kNT*V consecutive voxels (V = 2).  Every load of a
+// chunk is issued before any use: neighbour slots are addressed whenever the
+// index lies inside the volume and masked afterwards with the voxel's
+// neighbour code, so no load waits on another.  The first chunk is loaded
+// before the incoming partial sums are reduced, overlapping the two latencies.
+#pragma once
+
+#include "fm_kernels.hpp"
+
+namespace fm {
+
+#ifndef FM_VPT32
+#define FM_VPT32 2
+#endif
+#ifndef FM_VPT64
+#define FM_VPT64 2
+#endif
+
+constexpr int kNT = 512;
+
+template <typename T>
+struct Vpt {
+  static constexpr int v = sizeof(T) == 4 ? FM_VPT32 : FM_VPT64;
+};
+
+// Every array read at neighbour offsets is padded by one x-plane (sx
+// elements) on both sides, so j + off is always a valid address; the code
+// bits decide whether the value is a neighbour.  Indices are 32-bit (the
+// plan checks n + 2 sx < 2^31).
+struct Offs {
+  int o[6];
+  __device__ __forceinline__ explicit Offs(const Geo &g) {
+    o[0] = -(int)g.sx;
+    o[1] = (int)g.sx;
+    o[2] = -(int)g.sy;
+    o[3] = (int)g.sy;
+    o[4] = -1;
+    o[5] = 1;
+  }
+};
+
+__device__ __forceinline__ bool has_nb(uint32_t c, int k) { return (c >> (k + 1)) & 1u; }
+
+// ---------------------------------------------------------------------------
+// Gradient pass of iteration i (Sec. III eq. (ls_grad)), fused with the update
+// f^i = f^{i-1} + alpha z^{i-1} of the previous iteration:
+//   g_j = dphi_j(f_j) + beta (C^T C f)_j,  D_j = Huber curvature (eq. (ls_huber)),
+// hinv_j = 1 / (D_j + beta deg_j) for the red-black preconditioner.
+// Partial sums: sum phi, f^T C^T C f, ||g||^2, z_prev^T g.
+template <typename T, int LMAX>
+__global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
+  constexpr int V = Vpt<T>::v;
+  const Geo g = a.geo;
+  const int it = iter_after(*a.sin);
+  const T *__restrict__ fin = a.F[(it + 1) & 1];
+  const T *__restrict__ zp = a.Z[(it + 1) & 1];
+  T *__restrict__ fo = a.F[it & 1];
+  T *__restrict__ gg = a.G[it & 1];
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  uint32_t c[V];
+  T f0[V], z0[V], fn[V][6], zn[V][6], rho[V][LMAX], tau[V][LMAX];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      f0[v] = fin[jj];
+      z0[v] = zp[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        fn[v][k] = fin[jj + of.o[k]];
+        zn[v][k] = zp[jj + of.o[k]];
+      }
+      load_echoes<T, LMAX>(a.dat, (int64_t)n, jj, a.L, rho[v], tau[v]);
+    }
+  };
+  int base = (int)blockIdx.x * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const T alpha = (T)st.alpha;
+  const T beta = (T)a.beta;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        fo[j] = T(0);
+        if (a.fout) a.fout[j] = 0.0;
+        if (!a.final_pass) {
+          gg[j] = T(0);
+          a.D[j] = T(0);
+          if (a.write_hinv) a.hinv[j] = 0.0;
+        }
+        continue;
+      }
+      const T fj = f0[v] + alpha * z0[v];
+      T lap = T(0);
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (has_nb(cv, k)) lap += fj - (fn[v][k] + alpha * zn[v][k]);
+      T phi, dphi, curv;
+      voxel_terms<T, LMAX>(rho[v], tau[v], a.L, a.pairs, fj, phi, dphi, curv);
+      const T gj = dphi + beta * lap;
+      fo[j] = fj;
+      if (a.fout) a.fout[j] = (double)fj;
+      if (!a.final_pass) {
+        gg[j] = gj;
+        a.D[j] = curv;
+        if (a.write_hinv) {
+          const double h = (double)curv + a.beta * nb_deg(cv);
+          a.hinv[j] = h > 0.0 ? 1.0 / h : 0.0;
+        }
+      }
+      acc[0] += (double)phi;
+      acc[1] += (double)fj * (double)lap;
+      acc[2] += (double)gj * (double)gj;
+      acc[3] += (double)z0[v] * (double)gj;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  store_partials<4, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_GRAD, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// IC(0) in red-black order (Sec. III-B eq. (precon) with the red voxels,
+// x+y+z even, eliminated first).  Red voxels have no earlier neighbour, so
+// their pivot is h_r = D_r + beta deg_r and x_r = g_r / h_r; black voxels come
+// last with every neighbour earlier:
+//   P_b = h_b - beta^2 sum_k 1/h_k,   x_b = (g_b + beta sum_k g_k / h_k) / P_b,
+// and p_b = x_b (no later neighbour); then p_r = x_r + (beta / h_r) sum_k p_k.
+// 1/h is read from hinv (written once per voxel by the gradient pass).
+// Partial sums: g^T p and g_prev^T p over the colour of the pass.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a, const T *__restrict__ gsrc) {
+  constexpr int V = Vpt<T>::v;
+  const Geo g = a.geo;
+  const int it = iter_after(*a.sin);
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const double *__restrict__ hv = a.hinv;
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  uint32_t c[V];
+  T d0[V], g0[V], gp0[V], gn[V][6];
+  double hn[V][6];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      d0[v] = a.D[jj];
+      g0[v] = gg[jj];
+      gp0[v] = gp[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        gn[v][k] = gg[jj + of.o[k]];
+        hn[v][k] = hv[jj + of.o[k]];
+      }
+    }
+  };
+  int base = (int)blockIdx.x * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const double beta = a.beta, b2 = a.beta * a.beta;
+  double acc[2] = {0.0, 0.0};
+  int bad = 0;
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        if (a.store_piv) a.ipiv[j] = 0.0;
+        a.P[j] = T(0);
+        continue;
+      }
+      if (!(cv & NB_BLACK)) continue;
+      const double h = (double)d0[v] + beta * nb_deg(cv);
+      double sp = 0.0, sxv = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (has_nb(cv, k)) {
+          sp += hn[v][k];
+          sxv += (double)gn[v][k] * hn[v][k];
+        }
+      const double piv = h - b2 * sp;
+      double ip = 1.0 / piv;
+      if (!(piv > 0.0)) {
+        bad = 1;
+        ip = 0.0;
+      }
+      if (a.store_piv) a.ipiv[j] = ip;
+      const T pj = (T)(((double)g0[v] + beta * sxv) * ip);
+      a.P[j] = pj;
+      acc[0] += (double)g0[v] * (double)pj;
+      acc[1] += (double)gp0[v] * (double)pj;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS_A, gridDim.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a, const T *__restrict__ gsrc) {
+  constexpr int V = Vpt<T>::v;
+  const Geo g = a.geo;
+  const int it = iter_after(*a.sin);
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  uint32_t c[V];
+  T g0[V], gp0[V], pn[V][6];
+  double h0[V];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      g0[v] = gg[jj];
+      gp0[v] = gp[jj];
+      h0[v] = a.hinv[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) pn[v][k] = a.P[jj + of.o[k]];
+    }
+  };
+  int base = (int)blockIdx.x * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const double beta = a.beta;
+  double acc[2] = {0.0, 0.0};
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF) || (cv & NB_BLACK)) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (has_nb(cv, k)) s += (double)pn[v][k];
+      const double ip = h0[v];  // red pivots are h_r
+      if (a.store_piv) a.ipiv[j] = ip;
+      const T pj = (T)((double)g0[v] * ip + beta * s * ip);
+      a.P[j] = pj;
+      acc[0] += (double)g0[v] * (double)pj;
+      acc[1] += (double)gp0[v] * (double)pj;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS, gridDim.x);
+}
+
+// Diagonal (P = diag H) or identity preconditioner.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict__ gsrc, int identity) {
+  constexpr int V = Vpt<T>::v;
+  const Geo g = a.geo;
+  const int it = iter_after(*a.sin);
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  uint32_t c[V];
+  T d0[V], g0[V], gp0[V];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      d0[v] = a.D[jj];
+      g0[v] = gg[jj];
+      gp0[v] = gp[jj];
+    }
+  };
+  int base = (int)blockIdx.x * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const double beta = a.beta;
+  double acc[2] = {0.0, 0.0};
+  int bad = 0;
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        a.ipiv[j] = 0.0;
+        a.P[j] = T(0);
+        continue;
+      }
+      T pj;
+      if (identity) {
+        a.ipiv[j] = 1.0;
+        pj = g0[v];
+      } else {
+        const double h = (double)d0[v] + beta * nb_deg(cv);
+        double ip = 1.0 / h;
+        if (!(h > 0.0)) {
+          bad = 1;
+          ip = 0.0;
+        }
+        a.ipiv[j] = ip;
+        pj = (T)((double)g0[v] * ip);
+      }
+      a.P[j] = pj;
+      acc[0] += (double)g0[v] * (double)pj;
+      acc[1] += (double)gp0[v] * (double)pj;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Direction and line-search setup (Sec. III Algorithm and Sec. III-C).  The
+// incoming dot products give the Polak-Ribiere mu (readings R6, R7); then
+// z = -p + mu z_prev, A = z^T C^T C f, B = ||C z||^2 (once per outer
+// iteration) and d0 = sum z^2 D, from which the next kernel takes the first
+// step alpha = -z^T g / (d0 + beta B).
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a) {
+  constexpr int V = Vpt<T>::v;
+  const Geo g = a.geo;
+  const int it = iter_after(*a.sin);
+  const T *__restrict__ zp = a.Z[(it + 1) & 1];
+  T *__restrict__ zo = a.Z[it & 1];
+  const T *__restrict__ f = a.F[it & 1];
+  const T *__restrict__ p = a.P;
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  uint32_t c[V];
+  T p0[V], z0[V], f0[V], d0[V], pn[V][6], zn[V][6], fn[V][6];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      p0[v] = p[jj];
+      z0[v] = zp[jj];
+      f0[v] = f[jj];
+      d0[v] = a.D[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        pn[v][k] = p[jj + of.o[k]];
+        zn[v][k] = zp[jj + of.o[k]];
+        fn[v][k] = f[jj + of.o[k]];
+      }
+    }
+  };
+  int base = (int)blockIdx.x * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const T mu = (T)st.mu;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        zo[j] = T(0);
+        continue;
+      }
+      const T zj = -p0[v] + mu * z0[v];
+      T lz = T(0), lf = T(0);
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (has_nb(cv, k)) {
+          lz += zj - (-pn[v][k] + mu * zn[v][k]);
+          lf += f0[v] - fn[v][k];
+        }
+      zo[j] = zj;
+      acc[0] += (double)zj * (double)lf;
+      acc[1] += (double)zj * (double)lz;
+      acc[2] += (double)zj * (double)zj * (double)d0[v];
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  store_partials<3, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DIR, gridDim.x);
+}
+
+// One further line-search pass (Sec. III-C eq. (ls_update)) at the current
+// alpha: S1 = z^T grad Phi(f + alpha z), S2 = sum z^2 d(f + alpha z); the next
+// kernel applies alpha <- alpha - (S1 + beta A + alpha beta B) / (S2 + beta B).
+template <typename T, int LMAX>
+__global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a) {
+  constexpr int V = Vpt<T>::v;
+  const Geo g = a.geo;
+  const int it = iter_after(*a.sin);
+  const T *__restrict__ f = a.F[it & 1];
+  const T *__restrict__ z = a.Z[it & 1];
+  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  uint32_t c[V];
+  T f0[V], z0[V], rho[V][LMAX], tau[V][LMAX];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      f0[v] = f[jj];
+      z0[v] = z[jj];
+      load_echoes<T, LMAX>(a.dat, (int64_t)n, jj, a.L, rho[v], tau[v]);
+    }
+  };
+  int base = (int)blockIdx.x * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const T alpha = (T)st.alpha;
+  double acc[2] = {0.0, 0.0};
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n || !(c[v] & NB_SELF)) continue;
+      T phi, dphi, curv;
+      voxel_terms<T, LMAX>(rho[v], tau[v], a.L, a.pairs, f0[v] + alpha * z0[v], phi, dphi, curv);
+      acc[0] += (double)z0[v] * (double)dphi;
+      acc[1] += (double)z0[v] * (double)z0[v] * (double)curv;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_MLS, gridDim.x);
+}
+
+}  // namespace fm

@@ -1,0 +1,282 @@
+"""Python binding of the C ABI in include/fmap.h (libfmap.so).
+
+Argument marshalling only: every step of the estimator runs in the HIP
+kernels behind the ABI.  Tensors are torch tensors on the current HIP device;
+the work is enqueued on torch's current stream.  The binding refuses to run
+without the compiled library (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.environ.get("FMAP_LIBRARY") or os.path.join(_HERE, "libfmap.so")
+
+FM_MAX_ECHO = 16
+FM_MAX_PEAK = 16
+FIELDMAP, WATERFAT = 0, 1
+F64, MIX = 0, 1
+NATURAL, REDBLACK = 0, 1
+IC0, DIAG, NONE = 0, 1, 2
+TRACE_COLS = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)
+TRACE_W = 8
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "device allocation failed",
+          4: "HIP runtime error", 5: "IC(0) pivot not positive", 6: "non-finite value",
+          7: "call out of order"}
+
+EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval", "fm_precondition",
+            "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
+            "fm_status_string", "fm_last_error"]
+KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls"]
+
+
+class FmapError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("fmap error %d (%s): %s" % (status, STATUS.get(status, "?"), msg))
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("ncoil", C.c_int32),
+                ("necho", C.c_int32), ("te", C.c_double * FM_MAX_ECHO), ("beta", C.c_double),
+                ("niter", C.c_int32), ("nmls", C.c_int32), ("model", C.c_int32), ("npeak", C.c_int32),
+                ("fat_hz", C.c_double * FM_MAX_PEAK), ("fat_amp", C.c_double * FM_MAX_PEAK),
+                ("nsweep", C.c_int32), ("pwls_iters", C.c_int32), ("precision", C.c_int32),
+                ("ordering", C.c_int32), ("precond", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfmap.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError("libfmap.so is not built (%s); run __graft_entry__.build()" % LIBPATH)
+        L = C.CDLL(LIBPATH)
+        vp = C.c_void_p
+        L.fm_plan_create.argtypes = [C.POINTER(Params), C.POINTER(vp)]
+        L.fm_plan_destroy.argtypes = [vp]
+        L.fm_setup.argtypes = [vp, vp, vp, vp, vp]
+        L.fm_init.argtypes = [vp, vp, vp]
+        L.fm_eval.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fm_precondition.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fm_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fm_iterate.argtypes = [vp, C.c_int32, vp, vp]
+        L.fm_get_trace.argtypes = [vp, vp, vp]
+        L.fm_mask_count.argtypes = [vp, C.POINTER(C.c_int64), vp]
+        L.fm_time_kernels.argtypes = [vp, C.c_int32, vp, vp, vp]
+        L.fm_status_string.restype = C.c_char_p
+        L.fm_last_error.restype = C.c_char_p
+        for name in EXPORTED:
+            if name not in ("fm_status_string", "fm_last_error"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        raise FmapError(st, lib().fm_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_params(shape, ncoil, te, beta, niter=100, nmls=3, model=FIELDMAP, fat_hz=None, fat_amp=None,
+                nsweep=100, pwls_iters=10, precision=F64, ordering=NATURAL, precond=IC0):
+    p = Params()
+    p.nx, p.ny, p.nz = (int(s) for s in shape)
+    p.ncoil = int(ncoil)
+    te = np.asarray(te, dtype=np.float64)
+    p.necho = len(te)
+    if len(te) > FM_MAX_ECHO:
+        raise ValueError("at most %d echoes" % FM_MAX_ECHO)
+    for i, t in enumerate(te):
+        p.te[i] = float(t)
+    p.beta = float(beta)
+    p.niter = int(niter)
+    p.nmls = int(nmls)
+    p.model = int(model)
+    if model == WATERFAT:
+        fh = np.asarray(fat_hz, dtype=np.float64)
+        fa = np.asarray(fat_amp, dtype=np.float64)
+        p.npeak = len(fh)
+        for i in range(len(fh)):
+            p.fat_hz[i] = float(fh[i])
+            p.fat_amp[i] = float(fa[i])
+    p.nsweep = int(nsweep)
+    p.pwls_iters = int(pwls_iters)
+    p.precision = int(precision)
+    p.ordering = int(ordering)
+    p.precond = int(precond)
+    return p
+
+
+def params_for(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, nmls=None):
+    """Parameters for a synthetic volume of paper_2005_08661_amd.synth."""
+    return make_params(vol.shape, vol.ncoil, vol.te, vol.beta, vol.niter if niter is None else niter,
+                       vol.nmls if nmls is None else nmls,
+                       WATERFAT if vol.model == "waterfat" else FIELDMAP, vol.fat_hz, vol.fat_amp,
+                       precision=precision, ordering=ordering, precond=precond)
+
+
+class Plan:
+    """One problem geometry and its device workspace (fm_plan)."""
+
+    def __init__(self, params):
+        self.params = params
+        self.shape = (params.nx, params.ny, params.nz)
+        h = C.c_void_p()
+        _check(lib().fm_plan_create(C.byref(params), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- tensors ---------------------------------------------------------------
+    def _vol(self, dtype, device):
+        import torch
+        return torch.zeros(self.shape, dtype=dtype, device=device)
+
+    @staticmethod
+    def _as_c64(t):
+        import torch
+        return t.to(torch.complex64).contiguous()
+
+    def _take_inputs(self, y, sens, mask):
+        """Check shapes and devices on the host before anything is launched."""
+        import torch
+        P = self.params
+        if tuple(y.shape) != (P.ncoil, P.necho) + self.shape:
+            raise ValueError("y must have shape %s, got %s" % ((P.ncoil, P.necho) + self.shape, tuple(y.shape)))
+        if sens is None:
+            if P.ncoil != 1:
+                raise ValueError("sens may be omitted only for one coil")
+        elif tuple(sens.shape) != (P.ncoil,) + self.shape:
+            raise ValueError("sens must have shape %s, got %s" % ((P.ncoil,) + self.shape, tuple(sens.shape)))
+        if tuple(mask.shape) != self.shape:
+            raise ValueError("mask must have shape %s, got %s" % (self.shape, tuple(mask.shape)))
+        for t in (y, sens, mask):
+            if t is not None and not t.is_cuda:
+                raise ValueError("inputs must be device tensors")
+        self._y, self._s = self._as_c64(y), (None if sens is None else self._as_c64(sens))
+        self._m = mask.to(torch.uint8).contiguous()
+
+    def _vec(self, t):
+        import torch
+        if tuple(t.shape) != self.shape or not t.is_cuda:
+            raise ValueError("per-voxel arrays must be device tensors of shape %s" % (self.shape,))
+        return t.to(torch.float64).contiguous()
+
+    def setup(self, y, sens, mask):
+        self._take_inputs(y, sens, mask)
+        _check(lib().fm_setup(self._h, _ptr(self._y), _ptr(self._s), _ptr(self._m), _stream()))
+
+    def init(self):
+        import torch
+        f0 = self._vol(torch.float64, self._m.device)
+        _check(lib().fm_init(self._h, _ptr(f0), _stream()))
+        return f0
+
+    def eval(self, f):
+        import torch
+        f = self._vec(f)
+        outs = [self._vol(torch.float64, f.device) for _ in range(4)]
+        _check(lib().fm_eval(self._h, _ptr(f), *[_ptr(o) for o in outs], _stream()))
+        return outs  # phi, dphi, curv, lap
+
+    def precondition(self, curv, g):
+        import torch
+        curv = self._vec(curv)
+        g = self._vec(g)
+        piv = self._vol(torch.float64, g.device)
+        p = self._vol(torch.float64, g.device)
+        _check(lib().fm_precondition(self._h, _ptr(curv), _ptr(g), _ptr(piv), _ptr(p), _stream()))
+        return piv, p
+
+    def solve(self, y, sens, mask, f0=None, out=None):
+        import torch
+        self._take_inputs(y, sens, mask)
+        f0c = None if f0 is None else self._vec(f0)
+        if out is None:
+            out = self._vol(torch.float64, self._m.device)
+        elif tuple(out.shape) != self.shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of shape %s" % (self.shape,))
+        _check(lib().fm_solve(self._h, _ptr(self._y), _ptr(self._s), _ptr(self._m), _ptr(f0c), _ptr(out),
+                              _stream()))
+        return out
+
+    def iterate(self, niter, out=None):
+        import torch
+        if out is None:
+            out = self._vol(torch.float64, self._m.device)
+        elif tuple(out.shape) != self.shape or out.dtype != torch.float64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor of shape %s" % (self.shape,))
+        _check(lib().fm_iterate(self._h, C.c_int32(int(niter)), _ptr(out), _stream()))
+        return out
+
+    def trace(self):
+        tr = np.zeros((self.params.niter + 1, TRACE_W))
+        _check(lib().fm_get_trace(self._h, C.c_void_p(tr.ctypes.data), _stream()))
+        return tr
+
+    def time_kernels(self, niter):
+        """Per kernel class: (total ms, launches) over niter event-timed iterations."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), np.int32)
+        _check(lib().fm_time_kernels(self._h, C.c_int32(int(niter)), C.c_void_p(ms.ctypes.data),
+                                     C.c_void_p(n.ctypes.data), _stream()))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def mask_count(self):
+        v = C.c_int64(0)
+        _check(lib().fm_mask_count(self._h, C.byref(v), _stream()))
+        return v.value
+
+
+def to_device(vol, device="cuda"):
+    """Copy a synthetic volume's inputs to the GPU."""
+    import torch
+    y = torch.from_numpy(np.ascontiguousarray(vol.y)).to(device)
+    s = None if vol.sens is None else torch.from_numpy(np.ascontiguousarray(vol.sens)).to(device)
+    m = torch.from_numpy(np.ascontiguousarray(vol.mask)).to(device)
+    return y, s, m
+
+
+def solve_volume(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, nmls=None, f0=None,
+                 device="cuda"):
+    """Solve one synthetic volume on the GPU; returns (f as numpy, trace)."""
+    import torch
+    y, s, m = to_device(vol, device)
+    if f0 is not None and not isinstance(f0, torch.Tensor):
+        f0 = torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float64)).to(device)
+    with Plan(params_for(vol, precision, ordering, precond, niter, nmls)) as plan:
+        f = plan.solve(y, s, m, f0)
+        tr = plan.trace()
+        return f.cpu().numpy(), tr

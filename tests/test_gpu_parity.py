@@ -1,0 +1,247 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: F64 mode must match the oracle's field map within 1e-3 Hz RMS
+over the mask with identical restart decisions; in practice it agrees to
+round-off.  MIX mode (FP32 voxel math, FP64 pivots and reductions) is held to
+0.05 Hz RMS against the oracle and 0.01 Hz RMS against the GPU F64 solve.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_08661_amd import fmap, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    fmap.lib()
+
+
+def ragged_volume():
+    return synth.fieldmap_volume((13, 9, 7), 3, [0.0, 1.5e-3, 4.0e-3], 0.2, 12, synth.SEED_BASE + 900, 3,
+                                 120.0, False, 25.0, mask="paper", name="ragged 13x9x7 3 coils")
+
+
+def random_mask_volume():
+    vol = synth.fieldmap_volume((20, 17, 11), 2, [0.0, 1.0e-3, 3.0e-3], 0.1, 15, synth.SEED_BASE + 901, 3,
+                                150.0, False, 25.0, mask="full", name="20x17x11 random mask")
+    rng = np.random.default_rng(5)
+    vol.mask = (rng.uniform(size=vol.shape) < 0.85).astype(np.uint8)
+    return vol
+
+
+VOLUMES = {"tiny": lambda: synth.tiny_fieldmap(mask="paper"), "ragged": ragged_volume,
+           "random_mask": random_mask_volume}
+PREC = {"f64": fmap.F64, "mix": fmap.MIX}
+
+
+def rms(a, m):
+    return float(np.sqrt(np.mean(a[m] ** 2))) if m.any() else 0.0
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", list(VOLUMES))
+def test_setup_and_init_match_oracle(vname, prec):
+    vol = VOLUMES[vname]()
+    say("setup/init %s %s" % (vname, prec))
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec])) as plan:
+        plan.setup(y, s, m)
+        f0 = plan.init().cpu().numpy()
+        assert plan.mask_count() == int(vol.mask.sum())
+    zhat = O.combine(vol.y, vol.sens)
+    ref = O.init_fieldmap(zhat, vol.te, vol.mask)
+    np.testing.assert_allclose(f0, ref, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", list(VOLUMES))
+def test_data_term_and_stencil_match_oracle(vname, prec):
+    vol = VOLUMES[vname]()
+    say("eval %s %s" % (vname, prec))
+    rng = np.random.default_rng(7)
+    f = (synth.smooth_field(rng, vol.shape, 3, 200.0) + rng.normal(size=vol.shape)) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec])) as plan:
+        plan.setup(y, s, m)
+        out = [o.cpu().numpy() for o in plan.eval(torch.from_numpy(f).cuda())]
+    pb = O.problem_for(vol)
+    zhat = O.combine(vol.y, vol.sens)
+    phi, dphi, curv = O.data_term(pb, zhat, vol.mask, f)
+    lap = O.laplacian(pb, vol.mask, f)
+    tol = 1e-10 if prec == "f64" else 2e-5
+    for got, ref in zip(out, (phi, dphi, curv, lap)):
+        scale = max(np.abs(ref).max(), 1e-30)
+        assert np.abs(got - ref).max() <= tol * scale
+
+
+@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", list(VOLUMES))
+def test_preconditioner_matches_oracle(vname, prec, ordering):
+    vol = VOLUMES[vname]()
+    order = fmap.NATURAL if ordering == "natural" else fmap.REDBLACK
+    say("precondition %s %s %s" % (vname, prec, ordering))
+    rng = np.random.default_rng(8)
+    curv = rng.uniform(0, 0.1, vol.shape) * vol.mask
+    g = rng.normal(size=vol.shape) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec], ordering=order)) as plan:
+        plan.setup(y, s, m)
+        piv, p = (t.cpu().numpy() for t in plan.precondition(torch.from_numpy(curv).cuda(),
+                                                            torch.from_numpy(g).cuda()))
+    pb = O.problem_for(vol, ordering=order)
+    cref = curv if prec == "f64" else curv.astype(np.float32).astype(np.float64)
+    ref_piv = O.factor(pb, vol.mask, cref)
+    ref_p = O.apply(pb, vol.mask, ref_piv, g)
+    np.testing.assert_allclose(piv, ref_piv, rtol=1e-12, atol=0)
+    tol = 1e-11 if prec == "f64" else 1e-5
+    assert np.abs(p - ref_p).max() <= tol * np.abs(ref_p).max()
+
+
+@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", list(VOLUMES))
+def test_solve_matches_oracle(vname, prec, ordering):
+    vol = VOLUMES[vname]()
+    order = fmap.NATURAL if ordering == "natural" else fmap.REDBLACK
+    say("solve %s %s %s niter=%d" % (vname, prec, ordering, vol.niter))
+    f, tr = fmap.solve_volume(vol, precision=PREC[prec], ordering=order)
+    ref = O.run_volume(vol, ordering=order)
+    msk = vol.mask.astype(bool)
+    err = rms(f - ref["f"], msk)
+    say("  rms vs oracle %.3e Hz, max %.3e Hz" % (err, np.abs(f - ref["f"])[msk].max()))
+    assert np.all(f[~msk] == 0)
+    rt = ref["trace"]
+    if prec == "f64":
+        assert err < 1e-3
+        assert np.abs(f - ref["f"])[msk].max() < 1e-2
+        np.testing.assert_array_equal(tr[:-1, 3], rt[:-1, O.TR["restart"]])
+        np.testing.assert_allclose(tr[:, 0], rt[:, O.TR["cost"]], rtol=1e-9)
+        np.testing.assert_allclose(tr[:-1, 4], rt[:-1, O.TR["alpha"]], rtol=1e-6)
+    else:
+        assert err < 0.05
+        np.testing.assert_allclose(tr[:, 0], rt[:, O.TR["cost"]], rtol=1e-4)
+
+
+@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+def test_mixed_precision_close_to_f64_on_gpu(ordering):
+    vol = synth.tiny_fieldmap(mask="paper")
+    order = fmap.NATURAL if ordering == "natural" else fmap.REDBLACK
+    say("mix vs f64 tiny %s" % ordering)
+    f64, _ = fmap.solve_volume(vol, precision=fmap.F64, ordering=order)
+    fmx, _ = fmap.solve_volume(vol, precision=fmap.MIX, ordering=order)
+    d = rms(fmx - f64, vol.mask.astype(bool))
+    say("  mix vs f64 rms %.3e Hz" % d)
+    assert d <= 0.01
+
+
+@pytest.mark.parametrize("precond", ["diag", "none"])
+def test_other_preconditioners_match_oracle(precond):
+    vol = ragged_volume()
+    pc = fmap.DIAG if precond == "diag" else fmap.NONE
+    say("solve ragged f64 precond=%s" % precond)
+    f, tr = fmap.solve_volume(vol, precision=fmap.F64, precond=pc)
+    ref = O.run_volume(vol, precond=pc)
+    assert rms(f - ref["f"], vol.mask.astype(bool)) < 1e-6
+
+
+def test_iterate_continues_the_solve():
+    vol = ragged_volume()
+    say("iterate ragged f64 12+8")
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64)) as plan:
+        plan.solve(y, s, m)
+        f2 = plan.iterate(8).cpu().numpy()
+    ref = O.run_volume(vol, niter=vol.niter + 8)
+    assert rms(f2 - ref["f"], vol.mask.astype(bool)) < 1e-6
+
+
+def test_user_initial_map_is_used():
+    vol = ragged_volume()
+    rng = np.random.default_rng(9)
+    f0 = rng.uniform(-50, 50, vol.shape) * vol.mask
+    say("solve ragged f64 with user f0")
+    f, _ = fmap.solve_volume(vol, precision=fmap.F64, f0=f0)
+    ref = O.run_volume(vol, f0=f0)
+    assert rms(f - ref["f"], vol.mask.astype(bool)) < 1e-6
+
+
+def test_edge_cases_empty_mask_single_voxel_and_line():
+    say("edge: empty mask")
+    vol = ragged_volume()
+    vol.mask[:] = 0
+    f, tr = fmap.solve_volume(vol, precision=fmap.F64)
+    assert np.all(f == 0) and np.all(np.isfinite(tr))
+    say("edge: 1x1x1")
+    one = synth.fieldmap_volume((1, 1, 1), 1, [0.0, 2e-3], 0.0, 20, 3, 1, 60.0, False, 60.0)
+    f, tr = fmap.solve_volume(one, precision=fmap.F64)
+    ref = O.run_volume(one)
+    assert abs(f.item() - ref["f"].item()) < 1e-9
+    say("edge: 1x1x37 line")
+    line = synth.fieldmap_volume((1, 1, 37), 2, [0.0, 1e-3, 3e-3], 0.3, 10, 4, 2, 60.0, False, 30.0)
+    for order in (fmap.NATURAL, fmap.REDBLACK):
+        f, tr = fmap.solve_volume(line, precision=fmap.F64, ordering=order)
+        ref = O.run_volume(line, ordering=order)
+        assert rms(f - ref["f"], line.mask.astype(bool)) < 1e-9
+
+
+def test_zero_curvature_isolated_voxel_reports_not_pd():
+    say("edge: isolated voxel with zero data -> NOT_PD")
+    vol = ragged_volume()
+    vol.mask[:] = 0
+    vol.mask[2:6, 2:6, 2:5] = 1
+    vol.mask[10, 7, 5] = 1  # isolated voxel
+    vol.y[:, :, 10, 7, 5] = 0
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64)) as plan:
+        plan.solve(y, s, m)
+        with pytest.raises(fmap.FmapError) as ei:
+            plan.trace()
+        assert ei.value.status == 5
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+def test_waterfat_small_volume_matches_oracle(prec):
+    vol = synth.waterfat_volume((24, 20, 8), 3, 1.2e-3 + 1e-3 * np.arange(6), 2.0 ** -4, 20,
+                                synth.SEED_BASE + 77, 150.0, 40.0, name="water-fat 24x20x8")
+    say("water-fat 24x20x8 %s" % prec)
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec])) as plan:
+        plan.setup(y, s, m)
+        f0 = plan.init().cpu().numpy()
+    ref = O.run_volume(vol)
+    msk = vol.mask.astype(bool)
+    assert rms(f0 - ref["f0"], msk) < 1e-6
+    f, tr = fmap.solve_volume(vol, precision=PREC[prec])
+    err = rms(f - ref["f"], msk)
+    say("  rms vs oracle %.3e Hz" % err)
+    assert err < (1e-3 if prec == "f64" else 0.05)
+
+
+@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+def test_full_size_mid_volume_few_iterations(ordering):
+    """128x128x64, 8 coils at the benchmark's launch configuration, 4
+    iterations elementwise against the oracle (F64) and MIX within 0.05 Hz."""
+    vol = synth.mid_fieldmap(mask="full")
+    order = fmap.NATURAL if ordering == "natural" else fmap.REDBLACK
+    say("full size 128x128x64 %s 4 iterations" % ordering)
+    ref = O.run_volume(vol, ordering=order, niter=4)
+    msk = vol.mask.astype(bool)
+    f, tr = fmap.solve_volume(vol, precision=fmap.F64, ordering=order, niter=4)
+    e64 = rms(f - ref["f"], msk)
+    fm, _ = fmap.solve_volume(vol, precision=fmap.MIX, ordering=order, niter=4)
+    emx = rms(fm - ref["f"], msk)
+    say("  f64 rms %.3e Hz, mix rms %.3e Hz" % (e64, emx))
+    assert e64 < 1e-3
+    assert emx < 0.05
