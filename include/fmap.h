@@ -54,7 +54,8 @@ typedef enum {
   FM_ERR_HIP = 4,       /* a HIP runtime call failed */
   FM_ERR_NOT_PD = 5,    /* an IC(0) pivot was not positive (singular Hessian model) */
   FM_ERR_NONFINITE = 6, /* NaN/Inf met in the iteration */
-  FM_ERR_STATE = 7      /* call out of order (e.g. fm_eval before fm_setup) */
+  FM_ERR_STATE = 7,     /* call out of order (e.g. fm_eval before fm_setup) */
+  FM_ERR_TIMEOUT = 8    /* a device-side wait of the wavefront sweep exceeded its bound */
 } fm_status;
 
 typedef enum { FM_FIELDMAP = 0, FM_WATERFAT = 1 } fm_model;

@@ -15,6 +15,7 @@
 #include "../../include/fmap.h"
 #include "fm_kernels.hpp"
 #include "fm_stream.hpp"
+#include "fm_natural.hpp"
 
 using fm::kBlock;
 using fm::kMaxGrid;
@@ -65,7 +66,9 @@ struct fm_plan {
   double *ipiv = nullptr;
   double *hinv = nullptr;
   fm::State *S = nullptr;      // two ping-pong state copies
-  double *part = nullptr;      // two ping-pong partial-sum buffers [kMaxGrid][kMaxK]
+  double *part = nullptr;      // two ping-pong partial-sum buffers [part_rows][kMaxK]
+  size_t part_rows = kMaxGrid;
+  fm::Wavefront wf{};          // natural-order sweep: tiles, tickets, progress
   double *setup_part = nullptr;
   double *nmask = nullptr;
   int32_t *status = nullptr;
@@ -164,8 +167,8 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.store_piv = 0;
   a.sin = p->S + (q & 1);
   a.sout = p->S + ((q + 1) & 1);
-  a.pin = p->part + (size_t)(q & 1) * kMaxGrid * kMaxK;
-  a.pout = p->part + (size_t)((q + 1) & 1) * kMaxGrid * kMaxK;
+  a.pin = p->part + (size_t)(q & 1) * p->part_rows * kMaxK;
+  a.pout = p->part + (size_t)((q + 1) & 1) * p->part_rows * kMaxK;
   a.status = p->status;
   a.trace = p->trace;
   a.fout = nullptr;
@@ -215,11 +218,11 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
   if (p->prm.precond == FM_PRECOND_IC0) {
     if (p->prm.ordering == FM_ORDER_NATURAL) {
       FM_REC_BEGIN(FM_K_PRECOND_A);
-      hipLaunchKernelGGL(fm::k_ic_fwd_onewg<T>, dim3(1), dim3(1024), 0, s, pargs(p, p->q++), gsrc);
+      hipLaunchKernelGGL(fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), 0, s, pargs(p, p->q++), p->wf, gsrc);
       FM_REC_END();
       FM_LAUNCH_CHECK();
       FM_REC_BEGIN(FM_K_PRECOND_B);
-      hipLaunchKernelGGL(fm::k_ic_bwd_onewg<T>, dim3(1), dim3(1024), 0, s, pargs(p, p->q++), gsrc);
+      hipLaunchKernelGGL(fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), 0, s, pargs(p, p->q++), p->wf, gsrc);
       FM_REC_END();
       FM_LAUNCH_CHECK();
     } else {
@@ -282,7 +285,7 @@ fm_status enqueue_final(fm_plan *p, double *f_out, hipStream_t s) {
   FM_LAUNCH_CHECK();
   const uint64_t q = p->q++;
   hipLaunchKernelGGL(fm::k_finish, dim3(1), dim3(kBlock), 0, s, (const fm::State *)(p->S + (q & 1)),
-                     p->S + ((q + 1) & 1), (const double *)(p->part + (size_t)(q & 1) * kMaxGrid * kMaxK),
+                     p->S + ((q + 1) & 1), (const double *)(p->part + (size_t)(q & 1) * p->part_rows * kMaxK),
                      p->prm.beta, p->trace, p->status);
   FM_LAUNCH_CHECK();
   return FM_OK;
@@ -477,6 +480,7 @@ const char *fm_status_string(fm_status st) {
     case FM_ERR_NOT_PD: return "IC(0) pivot not positive";
     case FM_ERR_NONFINITE: return "non-finite value in the iteration";
     case FM_ERR_STATE: return "call out of order";
+    case FM_ERR_TIMEOUT: return "device-side wait exceeded its bound";
   }
   return "unknown status";
 }
@@ -538,7 +542,33 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   FM_ALLOC_PAD(p->ipiv, sizeof(double));
   FM_ALLOC_PAD(p->hinv, sizeof(double));
   FM_ALLOC(p->S, sizeof(fm::State) * 2);
-  FM_ALLOC(p->part, sizeof(double) * 2 * kMaxGrid * kMaxK);
+  {
+    // natural-order wavefront: 8x8 column tiles in anti-diagonal order
+    fm::Wavefront &w = p->wf;
+    w.ntx = (prm->nx + fm::kTile - 1) / fm::kTile;
+    w.nty = (prm->ny + fm::kTile - 1) / fm::kTile;
+    w.ntiles = w.ntx * w.nty;
+    std::vector<int2> order;
+    order.reserve((size_t)w.ntiles);
+    for (int d = 0; d <= w.ntx + w.nty - 2; ++d)
+      for (int ti = 0; ti < w.ntx; ++ti) {
+        const int tj = d - ti;
+        if (tj >= 0 && tj < w.nty) order.push_back(make_int2(ti, tj));
+      }
+    void *ord = nullptr, *cnt = nullptr;
+    FM_ALLOC(ord, sizeof(int2) * order.size());
+    FM_ALLOC(cnt, sizeof(uint32_t) * 2 + sizeof(int32_t) * 2 * (size_t)w.ntiles);
+    if (hipMemcpy(ord, order.data(), sizeof(int2) * order.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(cnt, 0, sizeof(uint32_t) * 2 + sizeof(int32_t) * 2 * (size_t)w.ntiles) != hipSuccess)
+      return cleanup(fail(FM_ERR_HIP, "wavefront tables upload failed"));
+    w.order = (const int2 *)ord;
+    w.ticket_fwd = (uint32_t *)cnt;
+    w.ticket_bwd = (uint32_t *)cnt + 1;
+    w.prog_fwd = (int32_t *)((uint32_t *)cnt + 2);
+    w.prog_bwd = w.prog_fwd + w.ntiles;
+    p->part_rows = (size_t)(w.ntiles > kMaxGrid ? w.ntiles : kMaxGrid);
+  }
+  FM_ALLOC(p->part, sizeof(double) * 2 * p->part_rows * kMaxK);
   FM_ALLOC(p->setup_part, sizeof(double) * kMaxGrid * kMaxK);
   FM_ALLOC(p->nmask, sizeof(double));
   FM_ALLOC(p->status, sizeof(int32_t));
@@ -553,7 +583,7 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
 #undef FM_ALLOC_PAD
   if (hipMemset(p->S, 0, sizeof(fm::State) * 2) != hipSuccess || hipMemset(p->status, 0, sizeof(int32_t)) != hipSuccess ||
       hipMemset(p->nmask, 0, sizeof(double)) != hipSuccess || hipMemset(p->trace, 0, trace_bytes) != hipSuccess ||
-      hipMemset(p->part, 0, sizeof(double) * 2 * kMaxGrid * kMaxK) != hipSuccess)
+      hipMemset(p->part, 0, sizeof(double) * 2 * p->part_rows * kMaxK) != hipSuccess)
     return cleanup(fail(FM_ERR_HIP, "hipMemset of the plan state failed"));
   const auto G = make_gamma(*prm);
   fm_status st = p->mix ? upload_pairs<float>(p, G, &p->pairs) : upload_pairs<double>(p, G, &p->pairs);

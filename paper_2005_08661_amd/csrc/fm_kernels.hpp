@@ -259,91 +259,6 @@ __global__ __launch_bounds__(kBlock) void k_finish(const State *sin, State *sout
   put_state(st, sout, PK_NONE, 0);
 }
 
-// ---------------------------------------------------------------------------
-// IC(0) in natural order (Sec. III-B eq. (precon)).  Sqrt-free factor
-// M = (P + E) P^{-1} (P + E^T), E the strictly lower part of
-// H = diag(D + beta deg) - beta A_mask:
-//   P_j = D_j + beta deg_j - beta^2 sum_{k lower nbr} 1/P_k
-//   forward   x_j = (g_j + beta sum_{k lower} x_k) / P_j
-//   backward  p_j = x_j + (beta / P_j) sum_{k upper} p_k
-// Lower neighbours in natural order are -x, -y, -z.  This version sweeps the
-// hyperplanes x+y+z = const inside one workgroup (every voxel of a plane
-// depends only on the previous plane).
-template <typename T>
-__global__ __launch_bounds__(1024) void k_ic_fwd_onewg(IterArgs<T> a, const T *__restrict__ gsrc) {
-  const Geo g = a.geo;
-  const State st = take_state<1024>(a.sin, a.pin, a.beta, a.trace, a.status);
-  const int it = st.iter;
-  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
-  const double beta = a.beta, b2 = a.beta * a.beta;
-  const int64_t ncol = (int64_t)g.nx * g.ny;
-  const int nlev = g.nx + g.ny + g.nz - 2;
-  int bad = 0;
-  for (int lev = 0; lev < nlev; ++lev) {
-    for (int64_t col = threadIdx.x; col < ncol; col += blockDim.x) {
-      const int32_t x = (int32_t)(col / g.ny), yy = (int32_t)(col % g.ny);
-      const int32_t z = lev - x - yy;
-      if (z < 0 || z >= g.nz) continue;
-      const int64_t j = col * g.nz + z;
-      const uint32_t c = a.code[j];
-      if (!(c & NB_SELF)) {
-        a.ipiv[j] = 0.0;
-        a.X[j] = T(0);
-        continue;
-      }
-      double sp = 0.0, sxv = 0.0;
-      if (c & NB_XM) { sp += a.ipiv[j - g.sx]; sxv += (double)a.X[j - g.sx]; }
-      if (c & NB_YM) { sp += a.ipiv[j - g.sy]; sxv += (double)a.X[j - g.sy]; }
-      if (c & NB_ZM) { sp += a.ipiv[j - 1]; sxv += (double)a.X[j - 1]; }
-      const double piv = (double)a.D[j] + beta * nb_deg(c) - b2 * sp;
-      double ip = 1.0 / piv;
-      if (!(piv > 0.0)) { bad = 1; ip = 0.0; }
-      a.ipiv[j] = ip;
-      a.X[j] = (T)(((double)gg[j] + beta * sxv) * ip);
-    }
-    __syncthreads();
-  }
-  if (bad) set_status(a.status, 5);
-  put_state(st, a.sout, PK_NONE, 0);
-}
-
-template <typename T>
-__global__ __launch_bounds__(1024) void k_ic_bwd_onewg(IterArgs<T> a, const T *__restrict__ gsrc) {
-  const Geo g = a.geo;
-  const State st = take_state<1024>(a.sin, a.pin, a.beta, a.trace, a.status);
-  const int it = st.iter;
-  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
-  const T *__restrict__ gp = a.G[(it + 1) & 1];
-  const double beta = a.beta;
-  double acc[2] = {0.0, 0.0};
-  const int64_t ncol = (int64_t)g.nx * g.ny;
-  const int nlev = g.nx + g.ny + g.nz - 2;
-  for (int lev = nlev - 1; lev >= 0; --lev) {
-    for (int64_t col = threadIdx.x; col < ncol; col += blockDim.x) {
-      const int32_t x = (int32_t)(col / g.ny), yy = (int32_t)(col % g.ny);
-      const int32_t z = lev - x - yy;
-      if (z < 0 || z >= g.nz) continue;
-      const int64_t j = col * g.nz + z;
-      const uint32_t c = a.code[j];
-      if (!(c & NB_SELF)) {
-        a.P[j] = T(0);
-        continue;
-      }
-      double s = 0.0;
-      if (c & NB_XP) s += (double)a.P[j + g.sx];
-      if (c & NB_YP) s += (double)a.P[j + g.sy];
-      if (c & NB_ZP) s += (double)a.P[j + 1];
-      const T pj = (T)((double)a.X[j] + beta * s * a.ipiv[j]);
-      a.P[j] = pj;
-      acc[0] += (double)gg[j] * (double)pj;
-      acc[1] += (double)gp[j] * (double)pj;
-    }
-    __syncthreads();
-  }
-  store_partials<2, 1024>(acc, a.pout);
-  put_state(st, a.sout, PK_DOTS, 1);
-}
-
 // hinv_j = 1 / (D_j + beta deg_j) for the standalone preconditioner call.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_hinv(Geo g, double beta, const uint8_t *__restrict__ code,

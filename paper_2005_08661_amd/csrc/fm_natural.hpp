@@ -1,0 +1,300 @@
+// IC(0) in natural order (Sec. III-B eq. (precon)) as a pipelined wavefront.
+//
+// The recurrences
+//   forward   P_j = h_j - beta^2 sum_{k lower} 1/P_k,  x_j = (g_j + beta sum_{k lower} x_k) / P_j
+//   backward  p_j = x_j + (beta / P_j) sum_{k upper} p_k
+// (lower = -x, -y, -z neighbours in the mask, upper = +x, +y, +z) have a
+// dependency chain of length nx+ny+nz-2.  The (x, y) plane is cut into 8x8
+// column tiles, one wavefront each: lane (a, b) owns column (8ti+a, 8tj+b) and
+// at step S handles z = S - a - b (backward: the mirror image), so its -x and
+// -y inputs come from lanes t-8 and t-1 of the previous step (cross-lane
+// moves) and its -z input from its own previous step.  Tiles exchange their
+// boundary columns through the stored x, 1/P (forward) and p (backward)
+// arrays, gated by per-tile progress counters (steps completed, published
+// every kStepU steps after the stores have completed).
+//
+// Progress is deadlock-free: a wave takes a ticket from an atomic counter and
+// processes the tile of that rank in anti-diagonal order, so it only waits on
+// tiles held by waves that started earlier.  Every wait is bounded; on
+// expiry the wave records FM_ERR_TIMEOUT and finishes its loop without
+// further waiting.  The forward kernel clears the backward kernel's counters
+// and the backward kernel the forward's (stream order separates them).
+#pragma once
+
+#include "fm_kernels.hpp"
+
+namespace fm {
+
+constexpr int kTile = 8;         // tile edge (8x8 columns = one wavefront)
+constexpr int kStepU = 4;        // steps per unrolled group / prefetch distance
+constexpr int kSpinLimit = 1 << 16;  // polls per wait (each ~1 us): about 0.1 s
+
+struct Wavefront {
+  const int2 *order;     // [ntiles] tile (ti, tj) of each ticket, anti-diagonal order
+  int32_t ntx, nty;      // tiles along x and y
+  int32_t ntiles;
+  uint32_t *ticket_fwd, *ticket_bwd;
+  int32_t *prog_fwd, *prog_bwd;  // [ntiles] steps completed
+};
+
+__device__ __forceinline__ int load_prog(const int32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait (lane 0 polls) until *p >= need; returns the value seen.  Bounded.
+__device__ __forceinline__ int wait_prog(const int32_t *p, int need, int cached, int32_t *status, bool &timed_out) {
+  if (cached >= need || timed_out) return cached;
+  int v = cached;
+  if ((threadIdx.x & 63) == 0) {
+    int spins = 0;
+    v = load_prog(p);
+    while (v < need && spins < kSpinLimit) {
+      __builtin_amdgcn_s_sleep(1);
+      v = load_prog(p);
+      ++spins;
+    }
+    if (v < need) set_status(status, 8);
+  }
+  v = __builtin_amdgcn_readfirstlane(v);
+  if (v < need) timed_out = true;
+  return v;
+}
+
+__device__ __forceinline__ void publish_prog(int32_t *p, int v) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int take_ticket(uint32_t *counter) {
+  int t = 0;
+  if ((threadIdx.x & 63) == 0) t = (int)atomicAdd(counter, 1u);
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_up_t(T v, int d) {
+  return __shfl_up(v, (unsigned)d, 64);
+}
+
+// Agent-coherent loads/stores of the values exchanged between tiles.
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc) {
+  const Geo g = a.geo;
+  const State st = take_state<64>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const int it = st.iter;
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const int ticket = take_ticket(w.ticket_fwd);
+  if (ticket >= w.ntiles) {  // counters not reset: refuse rather than index out of range
+    set_status(a.status, 8);
+    put_state(st, a.sout, PK_NONE, 0);
+    return;
+  }
+  if (ticket == 0 && threadIdx.x == 0) *w.ticket_bwd = 0u;
+  if (ticket == 0)
+    for (int i = threadIdx.x; i < w.ntiles; i += 64) w.prog_bwd[i] = 0;
+  const int2 tile = w.order[ticket];
+  const int lane = threadIdx.x, la = lane >> 3, lb = lane & 7;
+  const int x = tile.x * kTile + la, y = tile.y * kTile + lb;
+  const bool col_ok = x < g.nx && y < g.ny;
+  const int nz = g.nz;
+  const int64_t jcol = col_ok ? ((int64_t)x * g.ny + y) * nz : 0;
+  const int32_t *prog_x = tile.x > 0 ? w.prog_fwd + (tile.x - 1) * w.nty + tile.y : nullptr;
+  const int32_t *prog_y = tile.y > 0 ? w.prog_fwd + tile.x * w.nty + (tile.y - 1) : nullptr;
+  int32_t *my_prog = w.prog_fwd + tile.x * w.nty + tile.y;
+  const double beta = a.beta, b2 = a.beta * a.beta;
+  const int nsteps = nz + 2 * (kTile - 1);
+  int px = prog_x ? 0 : 1 << 30, py = prog_y ? 0 : 1 << 30;
+  bool timed_out = false;
+  int bad = 0;
+  // ring of prefetched inputs, slot = step % kStepU
+  uint32_t rc[kStepU];
+  double rh[kStepU], rbr[kStepU], rbyr[kStepU];
+  T rg[kStepU], rbx[kStepU], rbyx[kStepU];
+  auto prefetch = [&](int S, int u) {
+    const int z = S - la - lb;
+    rc[u] = 0u;
+    if (col_ok && z >= 0 && z < nz) {
+      const int64_t j = jcol + z;
+      const uint32_t c = a.code[j];
+      rc[u] = c;
+      rh[u] = (double)a.D[j] + beta * nb_deg(c);
+      rg[u] = gg[j];
+      if (la == 0 && (c & NB_XM)) {
+        rbr[u] = ld_coh(a.ipiv + (j - g.sx));
+        rbx[u] = ld_coh(a.X + (j - g.sx));
+      }
+      if (lb == 0 && (c & NB_YM)) {
+        rbyr[u] = ld_coh(a.ipiv + (j - g.sy));
+        rbyx[u] = ld_coh(a.X + (j - g.sy));
+      }
+    }
+  };
+  // boundary data of steps [0, kStepU) must be stored by the neighbour tiles
+  if (prog_x) px = wait_prog(prog_x, kStepU + kTile, px, a.status, timed_out);
+  if (prog_y) py = wait_prog(prog_y, kStepU + kTile, py, a.status, timed_out);
+#pragma unroll
+  for (int u = 0; u < kStepU; ++u) prefetch(u, u);
+  double r_prev = 0.0, x_prev = 0.0;  // this lane's previous z (same column)
+  double r_out = 0.0, x_out = 0.0;    // this lane's value of the previous step
+  for (int S0 = 0; S0 < nsteps; S0 += kStepU) {
+    const int need = S0 + 2 * kStepU + kTile;  // covers the prefetches of this group
+    if (prog_x) px = wait_prog(prog_x, need < nsteps ? need : nsteps, px, a.status, timed_out);
+    if (prog_y) py = wait_prog(prog_y, need < nsteps ? need : nsteps, py, a.status, timed_out);
+#pragma unroll
+    for (int u = 0; u < kStepU; ++u) {
+      const int S = S0 + u;
+      // values of lanes (a-1, b) and (a, b-1) from the previous step
+      const double rx_l = shfl_up_t(r_out, kTile), xx_l = shfl_up_t(x_out, kTile);
+      const double ry_l = shfl_up_t(r_out, 1), xy_l = shfl_up_t(x_out, 1);
+      const int z = S - la - lb;
+      const uint32_t c = rc[u];
+      double r_new = 0.0, x_new = 0.0;
+      if (col_ok && z >= 0 && z < nz) {
+        if (c & NB_SELF) {
+          double sr = 0.0, sx = 0.0;
+          if (c & NB_XM) {
+            sr += la ? rx_l : rbr[u];
+            sx += la ? xx_l : (double)rbx[u];
+          }
+          if (c & NB_YM) {
+            sr += lb ? ry_l : rbyr[u];
+            sx += lb ? xy_l : (double)rbyx[u];
+          }
+          if (c & NB_ZM) {
+            sr += r_prev;
+            sx += x_prev;
+          }
+          const double piv = rh[u] - b2 * sr;
+          double ip = 1.0 / piv;
+          if (!(piv > 0.0)) {
+            bad = 1;
+            ip = 0.0;
+          }
+          r_new = ip;
+          x_new = (double)(T)(((double)rg[u] + beta * sx) * ip);
+        }
+        const int64_t j = jcol + z;
+        st_coh(a.ipiv + j, r_new);
+        st_coh(a.X + j, (T)x_new);
+        r_prev = r_new;
+        x_prev = x_new;
+      }
+      r_out = r_new;
+      x_out = x_new;
+      if (S + kStepU < nsteps) prefetch(S + kStepU, u);
+    }
+    publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);
+  }
+  if (bad) set_status(a.status, 5);
+  put_state(st, a.sout, PK_NONE, 0);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc) {
+  const Geo g = a.geo;
+  const State st = take_state<64>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const int it = st.iter;
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
+  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const int ticket = take_ticket(w.ticket_bwd);
+  if (ticket >= w.ntiles) {
+    set_status(a.status, 8);
+    put_state(st, a.sout, PK_DOTS, 0);
+    return;
+  }
+  if (ticket == 0 && threadIdx.x == 0) *w.ticket_fwd = 0u;
+  if (ticket == 0)
+    for (int i = threadIdx.x; i < w.ntiles; i += 64) w.prog_fwd[i] = 0;
+  const int2 tile = w.order[w.ntiles - 1 - ticket];  // reverse anti-diagonal order
+  const int lane = threadIdx.x, la = lane >> 3, lb = lane & 7;
+  const int ra = kTile - 1 - la, rb = kTile - 1 - lb;  // skew of the mirrored sweep
+  const int x = tile.x * kTile + la, y = tile.y * kTile + lb;
+  const bool col_ok = x < g.nx && y < g.ny;
+  const int nz = g.nz;
+  const int64_t jcol = col_ok ? ((int64_t)x * g.ny + y) * nz : 0;
+  const int32_t *prog_x = tile.x + 1 < w.ntx ? w.prog_bwd + (tile.x + 1) * w.nty + tile.y : nullptr;
+  const int32_t *prog_y = tile.y + 1 < w.nty ? w.prog_bwd + tile.x * w.nty + (tile.y + 1) : nullptr;
+  int32_t *my_prog = w.prog_bwd + tile.x * w.nty + tile.y;
+  const double beta = a.beta;
+  const int nsteps = nz + 2 * (kTile - 1);
+  int px = prog_x ? 0 : 1 << 30, py = prog_y ? 0 : 1 << 30;
+  bool timed_out = false;
+  uint32_t rc[kStepU];
+  double rip[kStepU];
+  T rx[kStepU], rg[kStepU], rgp[kStepU], rbx[kStepU], rby[kStepU];
+  auto prefetch = [&](int S, int u) {
+    const int z = nz - 1 - (S - ra - rb);
+    rc[u] = 0u;
+    if (col_ok && z >= 0 && z < nz) {
+      const int64_t j = jcol + z;
+      const uint32_t c = a.code[j];
+      rc[u] = c;
+      rip[u] = ld_coh(a.ipiv + j);
+      rx[u] = ld_coh(a.X + j);
+      rg[u] = gg[j];
+      rgp[u] = gp[j];
+      if (la == kTile - 1 && (c & NB_XP)) rbx[u] = ld_coh(a.P + (j + g.sx));
+      if (lb == kTile - 1 && (c & NB_YP)) rby[u] = ld_coh(a.P + (j + g.sy));
+    }
+  };
+  if (prog_x) px = wait_prog(prog_x, kStepU + kTile, px, a.status, timed_out);
+  if (prog_y) py = wait_prog(prog_y, kStepU + kTile, py, a.status, timed_out);
+#pragma unroll
+  for (int u = 0; u < kStepU; ++u) prefetch(u, u);
+  double p_prev = 0.0, p_out = 0.0;
+  double acc[2] = {0.0, 0.0};
+  for (int S0 = 0; S0 < nsteps; S0 += kStepU) {
+    const int need = S0 + 2 * kStepU + kTile;
+    if (prog_x) px = wait_prog(prog_x, need < nsteps ? need : nsteps, px, a.status, timed_out);
+    if (prog_y) py = wait_prog(prog_y, need < nsteps ? need : nsteps, py, a.status, timed_out);
+#pragma unroll
+    for (int u = 0; u < kStepU; ++u) {
+      const int S = S0 + u;
+      // lanes (a+1, b) and (a, b+1) are lanes t+8 and t+1
+      const double px_l = __shfl_down(p_out, (unsigned)kTile, 64);
+      const double py_l = __shfl_down(p_out, 1u, 64);
+      const int z = nz - 1 - (S - ra - rb);
+      const uint32_t c = rc[u];
+      double p_new = 0.0;
+      if (col_ok && z >= 0 && z < nz) {
+        if (c & NB_SELF) {
+          double s = 0.0;
+          if (c & NB_XP) s += (la < kTile - 1) ? px_l : (double)rbx[u];
+          if (c & NB_YP) s += (lb < kTile - 1) ? py_l : (double)rby[u];
+          if (c & NB_ZP) s += p_prev;
+          p_new = (double)(T)((double)rx[u] + beta * s * rip[u]);
+          acc[0] += (double)rg[u] * p_new;
+          acc[1] += (double)rgp[u] * p_new;
+        }
+        st_coh(a.P + jcol + z, (T)p_new);
+        p_prev = p_new;
+      }
+      p_out = p_new;
+      if (S + kStepU < nsteps) prefetch(S + kStepU, u);
+    }
+    publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);
+  }
+  // per-tile partial sums, indexed by tile so the order is fixed
+  block_sum<2, 64>(acc);
+  if (threadIdx.x == 0) {
+    const int ti = tile.x * w.nty + tile.y;
+    a.pout[(size_t)ti * kMaxK + 0] = acc[0];
+    a.pout[(size_t)ti * kMaxK + 1] = acc[1];
+    a.pout[(size_t)ti * kMaxK + 2] = 0.0;
+    a.pout[(size_t)ti * kMaxK + 3] = 0.0;
+  }
+  put_state(st, a.sout, PK_DOTS, w.ntiles);
+}
+
+}  // namespace fm

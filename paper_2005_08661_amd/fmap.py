@@ -26,7 +26,7 @@ TRACE_W = 8
 
 STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "device allocation failed",
           4: "HIP runtime error", 5: "IC(0) pivot not positive", 6: "non-finite value",
-          7: "call out of order"}
+          7: "call out of order", 8: "device-side wait exceeded its bound"}
 
 EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval", "fm_precondition",
             "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
