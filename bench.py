@@ -26,33 +26,76 @@ def log(msg):
 
 
 def bytes_per_voxel(kclass, precision, L, ordering, precond):
-    """Algorithmic bytes per voxel of one launch of each kernel class: every
-    per-voxel array the kernel must read or write once (neighbour values are
-    re-used from cache and not counted again; the 1-byte neighbour code is
-    counted).  t = working type size, pivots are FP64."""
+    """Algorithmic bytes per voxel of one launch of each kernel class: each
+    per-voxel array the step must read or write, once, for the voxels it
+    concerns (neighbour values come from cache and are not counted again; the
+    1-byte neighbour code is counted).  t = working type size; pivots and
+    1/h are FP64."""
     t = 4 if precision == "mix" else 8
-    code = 1
-    if kclass == "grad":      # read echoes (2L t), f, z; write f, g, D
-        return code + 2 * L * t + 2 * t + 3 * t
-    if kclass == "mls":       # read echoes, f, z
-        return code + 2 * L * t + 2 * t
-    if kclass == "dots":      # read g, g_prev, p
-        return 3 * t
-    if kclass == "dir":       # read p, z_prev, f, D; write z
-        return code + 5 * t
+    rb = precond == "ic0" and ordering == "redblack"
+    if kclass == "grad":       # read code, echoes, f, z_prev; write f, g, D (+ 1/h)
+        return 1 + 2 * L * t + 5 * t + (8 if rb else 0)
+    if kclass == "mls":        # read code, echoes, f, z
+        return 1 + 2 * L * t + 2 * t
+    if kclass == "dir":        # read code, p, z_prev, f, D; write z
+        return 1 + 5 * t
     if precond == "ic0" and ordering == "natural":
-        if kclass == "precond_a":   # read D, g; write 1/pivot (8), x
-            return code + 2 * t + 8 + t
-        if kclass == "precond_b":   # read x, 1/pivot; write p
-            return code + t + 8 + t
-    if precond == "ic0" and ordering == "redblack":
-        if kclass == "precond_a":   # read D, g; write 1/pivot (8), p (black)
-            return code + 2 * t + 8 + t
-        if kclass == "precond_b":   # read g, 1/pivot, p; write p (red)
-            return code + t + 8 + 2 * t
-    if kclass == "precond_a":       # diagonal / identity: read D, g; write 1/pivot, p
-        return code + 2 * t + 8 + t
+        if kclass == "precond_a":  # read code, D, g; write 1/P (8), x
+            return 1 + 3 * t + 8
+        if kclass == "precond_b":  # read code, x, 1/P (8), g, g_prev; write p
+            return 1 + 4 * t + 8
+    if rb:
+        if kclass == "precond_a":  # black: D, g_prev, p of black; g of all; 1/h of red
+            return 1 + 2.5 * t + 4
+        if kclass == "precond_b":  # red: g, g_prev, 1/h, p of red; p of black
+            return 1 + 2.5 * t + 4
+    if kclass == "precond_a":      # diagonal / identity: read code, D, g, g_prev; write 1/h (8), p
+        return 1 + 4 * t + 8
     return 0
+
+
+KERNEL_SYMBOL = {"grad": "k_grad", "mls": "k_mls", "dir": "k_dir", "precond_a": None, "precond_b": None}
+
+
+def kernel_symbol(kclass, ordering, precond):
+    if kclass in ("precond_a", "precond_b"):
+        if precond != "ic0":
+            return "k_diag"
+        if ordering == "natural":
+            return "k_ic_fwd_wave" if kclass == "precond_a" else "k_ic_bwd_wave"
+        return "k_rb_black" if kclass == "precond_a" else "k_rb_red"
+    return KERNEL_SYMBOL[kclass]
+
+
+def measured_traffic(kclass, args):
+    """HBM bytes per launch of the kernel from the committed counter summary,
+    or None if there is none for this workload or the sources changed since."""
+    from paper_2005_08661_amd.prof_summary import source_hash
+    path = os.path.join(ROOT, "profiles", "counters_fieldmap_%s_%s_%s.json" % (
+        args.shape.replace(",", "x"), args.precision, args.ordering if args.precond == "ic0" else args.precond))
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != source_hash():
+        return None
+    sym = kernel_symbol(kclass, args.ordering, args.precond)
+    for name, v in rec["kernels"].items():
+        if sym and ("fm::%s<" % sym) in name:
+            return v["traffic_bytes"]
+    return None
+
+
+def time_solve(plan, fmap, y, s, m, out, steps, torch):
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.solve(y, s, m, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / max(steps, 1)
 
 
 def main():
@@ -61,13 +104,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["mix", "f64"], default="mix")
-    ap.add_argument("--ordering", choices=["natural", "redblack"], default="natural")
+    ap.add_argument("--ordering", choices=["natural", "redblack"], default="redblack")
     ap.add_argument("--precond", choices=["ic0", "diag", "none"], default="ic0")
     ap.add_argument("--mask", choices=["full", "paper"], default="full")
     ap.add_argument("--shape", default="128,128,64")
     ap.add_argument("--kernel-iters", type=int, default=10)
     ap.add_argument("--cpu-iters", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-natural", action="store_true", help="skip the natural-order comparison line")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -99,20 +143,14 @@ def main():
     niter = vol.niter
 
     log("timing %d steps" % args.steps)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.solve(y, s, m, out=out)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+    ms_step = time_solve(plan, fmap, y, s, m, out, args.steps, torch)
     wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / max(args.steps, 1)
     tr = plan.trace()
     nmask = plan.mask_count()
     value = nmask * niter / (ms_step * 1e-3)
     log("step %.3f ms (wall %.3f ms), %.3e voxel-iterations/s" % (ms_step, wall * 1e3 / args.steps, value))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     # iteration loop alone (graph replays), from the solved state
     ev0.record(stream)
@@ -129,17 +167,28 @@ def main():
     for k, (ms, nl) in kt.items():
         if nl == 0:
             continue
-        b = bytes_per_voxel(k, args.precision, L, args.ordering, args.precond) * vol.mask.size
+        b = bytes_per_voxel(k, args.precision, L, args.ordering, args.precond) * nmask
         avg = ms / nl
         kinfo[k] = dict(avg_us=avg * 1e3, launches=nl, total_ms=ms, bytes=b,
                         gbs=b / (avg * 1e-3) / 1e9 if avg > 0 else 0.0)
     dom = max(kinfo, key=lambda k: kinfo[k]["total_ms"])
     iter_bytes = sum(bytes_per_voxel(k, args.precision, L, args.ordering, args.precond) * kinfo[k]["launches"]
-                     for k in kinfo) / args.kernel_iters * vol.mask.size
+                     for k in kinfo) / args.kernel_iters * nmask
     iter_frac = iter_bytes / (ms_loop * 1e-3 / niter) / (HBM_PEAK_GBS * 1e9)
     for k, v in kinfo.items():
         log("  %-10s %9.2f us/launch  %8.1f GB/s  (%d launches)" % (k, v["avg_us"], v["gbs"], v["launches"]))
     log("loop %.3f ms for %d iterations; whole-iteration %.1f%% of HBM peak" % (ms_loop, niter, 100 * iter_frac))
+
+    natural = None
+    if not args.no_natural and args.ordering == "redblack" and args.precond == "ic0":
+        log("natural-order IC(0) on the same volume")
+        with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=fmap.NATURAL)) as pn:
+            pn.solve(y, s, m, out=out)
+            ms_nat = time_solve(pn, fmap, y, s, m, out, 1, torch)
+            trn = pn.trace()
+        natural = {"ms_per_step": ms_nat, "value": nmask * niter / (ms_nat * 1e-3),
+                   "final_cost": float(trn[-1, 0])}
+        log("natural order: %.3f ms per step, %.3e voxel-iterations/s" % (ms_nat, natural["value"]))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -184,7 +233,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": kinfo[dom]["gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(dom, args),
         },
         "iteration": {
             "loop_ms": ms_loop,
@@ -194,6 +243,7 @@ def main():
             "kernels_us": {k: round(v["avg_us"], 3) for k, v in kinfo.items()},
         },
         "final_cost": float(tr[-1, 0]),
+        "natural_order": natural,
         "cpu_baseline": cpu,
     }
     plan.close()

@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/fmap.h: parameter validation,
 // plan and workspace management, the kernel chain of one NCG iteration and
 // the HIP graph that replays the whole iteration loop.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -81,15 +82,18 @@ struct fm_plan {
   double *wf_tmp = nullptr;  // water-fat init: swept map and 3 CG vectors
   bool setup_done = false;
   bool solved = false;
-  // position in the kernel chain: launch q reads S[q&1], writes S[(q+1)&1]
+  // position in the kernel chain: launch q reads S[q&1], writes S[(q+1)&1];
+  // iteration index and partial-sum count at the current position
   uint64_t q = 0;
+  int64_t iter_host = 0;
+  int last_nparts = 0;
   // device allocations (freed with the plan); stencil-read arrays are
   // padded by pad elements on both sides
   std::vector<void *> bases;
   int64_t pad = 0;
   // graphs of the iteration loop keyed by (chain parity, iterations)
   hipStream_t cap_stream = nullptr;
-  std::map<std::pair<int, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  std::map<std::vector<int64_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
 namespace {
@@ -165,6 +169,8 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.hinv = p->hinv;
   a.write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? 1 : 0;
   a.store_piv = 0;
+  a.par = (int32_t)(p->iter_host & 1);
+  a.nparts_in = p->last_nparts;
   a.sin = p->S + (q & 1);
   a.sout = p->S + ((q + 1) & 1);
   a.pin = p->part + (size_t)(q & 1) * p->part_rows * kMaxK;
@@ -176,24 +182,20 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   return a;
 }
 
-// Optional per-launch event recorder (measurement path only).
+// Optional per-launch event recorder (measurement path only): the events are
+// attached to the dispatch itself (hipExtLaunchKernelGGL), so they bracket the
+// kernel's execution without extra packets in between.
 struct Recorder {
-  hipStream_t s = nullptr;
   std::vector<hipEvent_t> ev;
   std::vector<int> cls;
   hipError_t err = hipSuccess;
-  void begin(int c) {
-    hipEvent_t e = nullptr;
-    if (err == hipSuccess) err = hipEventCreate(&e);
-    if (err == hipSuccess) err = hipEventRecord(e, s);
-    ev.push_back(e);
+  void pair(int c, hipEvent_t *e0, hipEvent_t *e1) {
+    *e0 = *e1 = nullptr;
+    if (err == hipSuccess) err = hipEventCreate(e0);
+    if (err == hipSuccess) err = hipEventCreate(e1);
+    ev.push_back(*e0);
+    ev.push_back(*e1);
     cls.push_back(c);
-  }
-  void end() {
-    hipEvent_t e = nullptr;
-    if (err == hipSuccess) err = hipEventCreate(&e);
-    if (err == hipSuccess) err = hipEventRecord(e, s);
-    ev.push_back(e);
   }
   ~Recorder() {
     for (auto e : ev)
@@ -201,10 +203,16 @@ struct Recorder {
   }
 };
 
-#define FM_REC_BEGIN(c) \
-  if (rec) rec->begin(c)
-#define FM_REC_END() \
-  if (rec) rec->end()
+#define FM_LAUNCH(cls, kernel, grid, block, s, ...)                                   \
+  do {                                                                                \
+    if (rec) {                                                                        \
+      hipEvent_t e0_, e1_;                                                            \
+      rec->pair(cls, &e0_, &e1_);                                                     \
+      hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0_, e1_, 0, __VA_ARGS__);     \
+    } else {                                                                          \
+      hipLaunchKernelGGL(kernel, grid, block, 0, s, __VA_ARGS__);                     \
+    }                                                                                 \
+  } while (0)
 
 // Preconditioner step p = P^{-1} g (g from gsrc, or G[iter&1] if null),
 // leaving the dot products g^T p and g_prev^T p as partial sums.
@@ -217,30 +225,25 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
   };
   if (p->prm.precond == FM_PRECOND_IC0) {
     if (p->prm.ordering == FM_ORDER_NATURAL) {
-      FM_REC_BEGIN(FM_K_PRECOND_A);
-      hipLaunchKernelGGL(fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), 0, s, pargs(p, p->q++), p->wf, gsrc);
-      FM_REC_END();
+      FM_LAUNCH(FM_K_PRECOND_A, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, pargs(p, p->q++), p->wf, gsrc);
       FM_LAUNCH_CHECK();
-      FM_REC_BEGIN(FM_K_PRECOND_B);
-      hipLaunchKernelGGL(fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), 0, s, pargs(p, p->q++), p->wf, gsrc);
-      FM_REC_END();
+      p->last_nparts = 0;
+      FM_LAUNCH(FM_K_PRECOND_B, fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, pargs(p, p->q++), p->wf, gsrc);
       FM_LAUNCH_CHECK();
+      p->last_nparts = p->wf.ntiles;
     } else {
-      FM_REC_BEGIN(FM_K_PRECOND_A);
-      hipLaunchKernelGGL(fm::k_rb_black<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, pargs(p, p->q++), gsrc);
-      FM_REC_END();
+      FM_LAUNCH(FM_K_PRECOND_A, fm::k_rb_black<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
       FM_LAUNCH_CHECK();
-      FM_REC_BEGIN(FM_K_PRECOND_B);
-      hipLaunchKernelGGL(fm::k_rb_red<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, pargs(p, p->q++), gsrc);
-      FM_REC_END();
+      p->last_nparts = p->sgrid;
+      FM_LAUNCH(FM_K_PRECOND_B, fm::k_rb_red<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
       FM_LAUNCH_CHECK();
+      p->last_nparts = p->sgrid;
     }
   } else {
-    FM_REC_BEGIN(FM_K_PRECOND_A);
-    hipLaunchKernelGGL(fm::k_diag<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, pargs(p, p->q++), gsrc,
+    FM_LAUNCH(FM_K_PRECOND_A, fm::k_diag<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc,
                        p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
-    FM_REC_END();
     FM_LAUNCH_CHECK();
+    p->last_nparts = p->sgrid;
   }
   return FM_OK;
 }
@@ -256,22 +259,19 @@ uint64_t launches_per_iteration(const fm_plan *p) {
 // iteration's gradient pass (or by the final pass).
 template <typename T, int LMAX>
 fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) {
-  FM_REC_BEGIN(FM_K_GRAD);
-  hipLaunchKernelGGL((fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, iter_args<T>(p, p->q++));
-  FM_REC_END();
+  FM_LAUNCH(FM_K_GRAD, (fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
   FM_LAUNCH_CHECK();
+  p->last_nparts = p->sgrid;
   fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
   if (st) return st;
-  FM_REC_BEGIN(FM_K_DIR);
-  hipLaunchKernelGGL(fm::k_dir<T>, dim3(p->sgrid), dim3(fm::kNT), 0, s, iter_args<T>(p, p->q++));
-  FM_REC_END();
+  FM_LAUNCH(FM_K_DIR, fm::k_dir<T>, dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
   FM_LAUNCH_CHECK();
+  p->last_nparts = p->sgrid;
   for (int k = 1; k < p->prm.nmls; ++k) {
-    FM_REC_BEGIN(FM_K_MLS);
-    hipLaunchKernelGGL((fm::k_mls<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, iter_args<T>(p, p->q++));
-    FM_REC_END();
+    FM_LAUNCH(FM_K_MLS, (fm::k_mls<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
     FM_LAUNCH_CHECK();
   }
+  p->iter_host += 1;
   return FM_OK;
 }
 
@@ -283,11 +283,13 @@ fm_status enqueue_final(fm_plan *p, double *f_out, hipStream_t s) {
   a.fout = f_out;
   hipLaunchKernelGGL((fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
   FM_LAUNCH_CHECK();
+  p->last_nparts = p->sgrid;
   const uint64_t q = p->q++;
   hipLaunchKernelGGL(fm::k_finish, dim3(1), dim3(kBlock), 0, s, (const fm::State *)(p->S + (q & 1)),
                      p->S + ((q + 1) & 1), (const double *)(p->part + (size_t)(q & 1) * p->part_rows * kMaxK),
-                     p->prm.beta, p->trace, p->status);
+                     p->last_nparts, p->prm.beta, p->trace, p->status);
   FM_LAUNCH_CHECK();
+  p->last_nparts = 0;
   return FM_OK;
 }
 
@@ -413,10 +415,12 @@ void free_plan(fm_plan *p) {
 // launches occupy the same chain positions modulo 2).
 fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
   if (niter <= 0) return FM_OK;
-  const auto key = std::make_pair((int)(p->q & 1), niter);
+  const std::vector<int64_t> key = {(int64_t)(p->q & 1), niter, p->iter_host & 1, p->last_nparts};
   auto it = p->graphs.find(key);
   if (it == p->graphs.end()) {
     const uint64_t q0 = p->q;
+    const int64_t it0 = p->iter_host;
+    const int np0 = p->last_nparts;
     FM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     fm_status st = dispatch<OpLoop>(p, niter, p->cap_stream);
     hipGraph_t g = nullptr;
@@ -424,6 +428,8 @@ fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
     if (st) {
       if (g) (void)hipGraphDestroy(g);
       p->q = q0;
+      p->iter_host = it0;
+      p->last_nparts = np0;
       return st;
     }
     if (e != hipSuccess) return fail(FM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -436,6 +442,8 @@ fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
     it = p->graphs.emplace(key, std::make_pair(g, ge)).first;
   } else {
     p->q += launches_per_iteration(p) * (uint64_t)niter;
+    p->iter_host += niter;
+    p->last_nparts = p->sgrid;  // the last pass of an iteration is a streaming pass
   }
   FM_HIP(hipGraphLaunch(it->second.second, s));
   return FM_OK;
@@ -443,6 +451,8 @@ fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
 
 template <typename T>
 fm_status enqueue_start(fm_plan *p, const double *f0, hipStream_t s) {
+  p->iter_host = 0;
+  p->last_nparts = 0;
   const uint64_t q = p->q++;
   hipLaunchKernelGGL(fm::k_start<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, f0, (const uint8_t *)p->code,
                      (T *)p->F[1], (T *)p->Z[1], (T *)p->G[1], p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls,
@@ -688,6 +698,8 @@ fm_status fm_precondition(fm_plan *p, const double *curv, const double *g, doubl
     const uint64_t q = p->q++;
     hipLaunchKernelGGL(fm::k_state_init, dim3(1), dim3(1), 0, s, p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls);
     FM_LAUNCH_CHECK();
+    p->iter_host = 0;
+    p->last_nparts = 0;
     if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) {
       hipLaunchKernelGGL(fm::k_hinv<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, p->prm.beta,
                          (const uint8_t *)p->code, (const T *)p->D, p->hinv, p->status);
@@ -758,7 +770,7 @@ fm_status fm_time_kernels(fm_plan *p, int32_t niter, double *ms, int32_t *launch
     launches[k] = 0;
   }
   Recorder rec;
-  rec.s = s;
+
   for (int i = 0; i < niter; ++i) {
     fm_status st = dispatch<OpIterationTimed>(p, s, &rec);
     if (st) return st;

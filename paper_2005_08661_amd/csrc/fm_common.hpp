@@ -320,15 +320,18 @@ __device__ __forceinline__ int iter_after(const State &s) {
   return s.iter;
 }
 
-// Common prologue: load the incoming state, sum the incoming partials and
-// apply them.  Returns the updated state (identical in every block).
+// Common prologue: load the incoming state and sum the incoming partials
+// (their count nparts_in is fixed by the launch sequence, so both loads are
+// issued together), then apply them.  Returns the updated state (identical in
+// every block).
 template <int NT = kBlock>
 __device__ __forceinline__ State take_state(const State *__restrict__ sin, const double *__restrict__ pin,
-                                            double beta, double *trace, int32_t *status) {
+                                            int nparts_in, double beta, double *trace, int32_t *status) {
   State s = *sin;
+  double t[kMaxK];
+  sum_partials<NT>(pin, nparts_in, t);
   if (s.kind != PK_NONE) {
-    double t[kMaxK];
-    sum_partials<NT>(pin, s.nparts, t);
+    if (s.nparts != nparts_in && blockIdx.x == 0 && threadIdx.x == 0) set_status(status, 7);
     consume(s, t, beta, trace, status);
   }
   return s;

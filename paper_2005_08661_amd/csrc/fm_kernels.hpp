@@ -224,6 +224,8 @@ struct IterArgs {
   double *hinv;  // 1 / (D + beta deg), written by the gradient pass when needed
   int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0))
   int32_t store_piv;   // preconditioner passes also store every pivot
+  int32_t par;         // parity of the iteration this launch belongs to
+  int32_t nparts_in;   // partial sums left by the previous launch
   const State *sin;    // incoming scalar state
   State *sout;         // outgoing scalar state (block 0)
   const double *pin;   // incoming partial sums
@@ -253,9 +255,9 @@ __device__ __forceinline__ void load_echoes(const T2<T> *__restrict__ dat, int64
 
 // End of a solve (one block): consume the final gradient pass (the cost of
 // the final map) and leave a state from which the iteration can continue.
-__global__ __launch_bounds__(kBlock) void k_finish(const State *sin, State *sout, const double *pin, double beta,
-                                                    double *trace, int32_t *status) {
-  const State st = take_state(sin, pin, beta, trace, status);
+__global__ __launch_bounds__(kBlock) void k_finish(const State *sin, State *sout, const double *pin, int nparts_in,
+                                                    double beta, double *trace, int32_t *status) {
+  const State st = take_state(sin, pin, nparts_in, beta, trace, status);
   put_state(st, sout, PK_NONE, 0);
 }
 

@@ -90,8 +90,8 @@ __device__ __forceinline__ void st_coh(T *p, T v) {
 template <typename T>
 __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc) {
   const Geo g = a.geo;
-  const State st = take_state<64>(a.sin, a.pin, a.beta, a.trace, a.status);
-  const int it = st.iter;
+  const State st = take_state<64>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const int ticket = take_ticket(w.ticket_fwd);
   if (ticket >= w.ntiles) {  // counters not reset: refuse rather than index out of range
@@ -203,8 +203,8 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
 template <typename T>
 __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc) {
   const Geo g = a.geo;
-  const State st = take_state<64>(a.sin, a.pin, a.beta, a.trace, a.status);
-  const int it = st.iter;
+  const State st = take_state<64>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const T *__restrict__ gp = a.G[(it + 1) & 1];
   const int ticket = take_ticket(w.ticket_bwd);

@@ -55,7 +55,7 @@ template <typename T, int LMAX>
 __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
   constexpr int V = Vpt<T>::v;
   const Geo g = a.geo;
-  const int it = iter_after(*a.sin);
+  const int it = a.par;
   const T *__restrict__ fin = a.F[(it + 1) & 1];
   const T *__restrict__ zp = a.Z[(it + 1) & 1];
   T *__restrict__ fo = a.F[it & 1];
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
   const T alpha = (T)st.alpha;
   const T beta = (T)a.beta;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -144,7 +144,7 @@ template <typename T>
 __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a, const T *__restrict__ gsrc) {
   constexpr int V = Vpt<T>::v;
   const Geo g = a.geo;
-  const int it = iter_after(*a.sin);
+  const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const T *__restrict__ gp = a.G[(it + 1) & 1];
   const double *__restrict__ hv = a.hinv;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a, const T *__rest
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
   const double beta = a.beta, b2 = a.beta * a.beta;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
@@ -218,7 +218,7 @@ template <typename T>
 __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a, const T *__restrict__ gsrc) {
   constexpr int V = Vpt<T>::v;
   const Geo g = a.geo;
-  const int it = iter_after(*a.sin);
+  const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const T *__restrict__ gp = a.G[(it + 1) & 1];
   const Offs of(g);
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a, const T *__restri
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
   for (; base < n; base += stride) {
@@ -273,7 +273,7 @@ template <typename T>
 __global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict__ gsrc, int identity) {
   constexpr int V = Vpt<T>::v;
   const Geo g = a.geo;
-  const int it = iter_after(*a.sin);
+  const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const T *__restrict__ gp = a.G[(it + 1) & 1];
   const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
@@ -342,7 +342,7 @@ template <typename T>
 __global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a) {
   constexpr int V = Vpt<T>::v;
   const Geo g = a.geo;
-  const int it = iter_after(*a.sin);
+  const int it = a.par;
   const T *__restrict__ zp = a.Z[(it + 1) & 1];
   T *__restrict__ zo = a.Z[it & 1];
   const T *__restrict__ f = a.F[it & 1];
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a) {
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
   const T mu = (T)st.mu;
   double acc[3] = {0.0, 0.0, 0.0};
   for (; base < n; base += stride) {
@@ -410,7 +410,7 @@ template <typename T, int LMAX>
 __global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a) {
   constexpr int V = Vpt<T>::v;
   const Geo g = a.geo;
-  const int it = iter_after(*a.sin);
+  const int it = a.par;
   const T *__restrict__ f = a.F[it & 1];
   const T *__restrict__ z = a.Z[it & 1];
   const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a) {
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.beta, a.trace, a.status);
+  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
   const T alpha = (T)st.alpha;
   double acc[2] = {0.0, 0.0};
   for (; base < n; base += stride) {
