@@ -650,3 +650,120 @@ int fmo_pwls_cg(const fmo_problem *pb, const uint8_t *mask, const double *rho,
   free(lap);
   return FMO_OK;
 }
+
+/* Exact second derivative of the per-voxel data term at fj. */
+static double voxel_hess(const pairs_t *pr, int64_t n, int64_t j, double fj) {
+  double h = 0.0;
+  for (int q = 0; q < pr->np; ++q) {
+    const double w = pr->w[(int64_t)q * n + j];
+    const double d = pr->d[q];
+    const double x = pr->a[(int64_t)q * n + j] + d * fj;
+    h += w * d * d * cos(x);
+  }
+  return h;
+}
+
+int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, const double *fhat,
+                const double *dldf, int32_t maxit, double rtol, double *v, double *dldbeta,
+                double *dzhat, int32_t *iters) {
+  if (check_pb(pb) || !zhat || !mask || !fhat || !dldf || !v || maxit < 0) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  const int L = pb->necho;
+  const double beta = pb->beta;
+  pairs_t pr;
+  if (pairs_build(pb, zhat, mask, &pr)) return FMO_ERR_ARG;
+  const size_t nb = sizeof(double) * (size_t)(n ? n : 1);
+  double *h = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  double *curv = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  double *piv = (double *)malloc(nb), *r = (double *)malloc(nb), *z = (double *)malloc(nb);
+  double *d = (double *)malloc(nb), *hd = (double *)malloc(nb), *lap = (double *)malloc(nb);
+  int st = FMO_OK;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!mask[j]) continue;
+    double a, b;
+    voxel_terms(&pr, n, j, fhat[j], &a, &b, &curv[j]);
+    h[j] = voxel_hess(&pr, n, j, fhat[j]);
+  }
+  /* preconditioner: IC(0) (or the chosen variant) of the Huber model */
+  if (pb->precond == FMO_PRECOND_IC0) st = fmo_factor(pb, mask, curv, piv);
+  int it = 0;
+  if (st == FMO_OK) {
+    for (int64_t j = 0; j < n; ++j) {
+      v[j] = 0.0;
+      r[j] = mask[j] ? dldf[j] : 0.0;
+      d[j] = 0.0;
+    }
+    const double bnorm = sqrt(dot_mask(mask, n, r, r));
+    double rho_prev = 0.0;
+    int64_t nbr[6];
+    for (it = 0; it < maxit; ++it) {
+      if (sqrt(dot_mask(mask, n, r, r)) <= rtol * bnorm) break;
+      if (pb->precond == FMO_PRECOND_IC0) {
+        fmo_apply(pb, mask, piv, r, z);
+      } else {
+        for (int64_t j = 0; j < n; ++j) {
+          const double hh = curv[j] + beta * neighbours(pb, mask, j, nbr);
+          z[j] = mask[j] ? (pb->precond == FMO_PRECOND_DIAG ? r[j] / hh : r[j]) : 0.0;
+        }
+      }
+      const double rho = dot_mask(mask, n, r, z);
+      const double bcg = (it > 0 && rho_prev != 0.0) ? rho / rho_prev : 0.0;
+      for (int64_t j = 0; j < n; ++j) d[j] = mask[j] ? z[j] + bcg * d[j] : 0.0;
+      fmo_laplacian(pb, mask, d, lap);
+      for (int64_t j = 0; j < n; ++j) hd[j] = mask[j] ? h[j] * d[j] + beta * lap[j] : 0.0;
+      const double dhd = dot_mask(mask, n, d, hd);
+      if (!(dhd > 0.0)) {
+        st = FMO_ERR_NOT_PD;
+        break;
+      }
+      const double alpha = rho / dhd;
+      for (int64_t j = 0; j < n; ++j) {
+        v[j] += alpha * d[j];
+        r[j] -= alpha * hd[j];
+      }
+      rho_prev = rho;
+    }
+  }
+  if (iters) *iters = it;
+  if (st == FMO_OK) {
+    fmo_laplacian(pb, mask, fhat, lap);
+    if (dldbeta) *dldbeta = -dot_mask(mask, n, v, lap);
+    if (dzhat) {
+      for (int64_t k = 0; k < 2 * (int64_t)L * n; ++k) dzhat[k] = 0.0;
+      /* g_j = sum_{m<n} 4 pi dt Im(Gamma_mn conj(zhat_m) zhat_n e^{i 2 pi dt f_j});
+       * for G = Im(u conj(z_m) z_n): dG/dz_n = i conj(u) z_m, dG/dz_m = -i u z_n */
+      for (int64_t j = 0; j < n; ++j) {
+        if (!mask[j] || v[j] == 0.0) continue;
+        int q = 0;
+        for (int m = 0; m < L; ++m)
+          for (int k = m + 1; k < L; ++k, ++q) {
+            const double dt = pb->te[m] - pb->te[k];
+            const double th = TWO_PI * dt * fhat[j];
+            const double gre = pb->gam[2 * (m * L + k)], gim = pb->gam[2 * (m * L + k) + 1];
+            const double ure = gre * cos(th) - gim * sin(th), uim = gre * sin(th) + gim * cos(th);
+            const double *zm = zhat + 2 * ((int64_t)m * n + j), *zn = zhat + 2 * ((int64_t)k * n + j);
+            const double c = -v[j] * 2.0 * TWO_PI * dt;
+            /* i conj(u) z_m */
+            const double an_re = -(ure * zm[1] - uim * zm[0]), an_im = ure * zm[0] + uim * zm[1];
+            /* -i u z_n */
+            const double pre = ure * zn[0] - uim * zn[1], pim = ure * zn[1] + uim * zn[0];
+            const double am_re = pim, am_im = -pre;
+            dzhat[2 * ((int64_t)k * n + j)] += c * an_re;
+            dzhat[2 * ((int64_t)k * n + j) + 1] += c * an_im;
+            dzhat[2 * ((int64_t)m * n + j)] += c * am_re;
+            dzhat[2 * ((int64_t)m * n + j) + 1] += c * am_im;
+          }
+      }
+    }
+  }
+  free(h);
+  free(curv);
+  free(piv);
+  free(r);
+  free(z);
+  free(d);
+  free(hd);
+  free(lap);
+  pairs_free(&pr);
+  return st;
+}

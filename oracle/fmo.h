@@ -126,6 +126,20 @@ int fmo_pwls_weights(int64_t n, int32_t ncoil, int32_t L, const double *y, const
 int fmo_pwls_cg(const fmo_problem *pb, const uint8_t *mask, const double *rho,
                 const double *ftilde, int32_t niters, double *f);
 
+/* Implicit adjoint of a converged map fhat (stationary point of Psi):
+ * v = H^{-1} dL/df with the exact Hessian H = diag(h) + beta C^T C,
+ * h_j = sum_{m<n} w_mn (2 pi dt_mn)^2 cos(x_mn), solved by conjugate gradients
+ * preconditioned with IC(0) of the Huber model D + beta C^T C (problem
+ * ordering) until ||r|| <= rtol ||dL/df|| or maxit iterations.  Then
+ *   dL/dbeta = -v^T C^T C fhat,
+ *   dL/dzhat_l = -v_j sum over pairs of d g_j / d zhat_l (gradient of a real
+ *                function of complex values: d/dRe + i d/dIm),
+ * written to dzhat [L][n] (interleaved complex).  *iters receives the CG
+ * iterations used; FMO_ERR_NOT_PD if a CG curvature d^T H d is not positive. */
+int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, const double *fhat,
+                const double *dldf, int32_t maxit, double rtol, double *v, double *dldbeta,
+                double *dzhat, int32_t *iters);
+
 #ifdef __cplusplus
 }
 #endif

@@ -198,6 +198,30 @@ def pwls_cg(pb, mask, rho, ftilde, niters=10):
     return out
 
 
+def adjoint(pb, zhat, mask, fhat, dldf, maxit=500, rtol=1e-12):
+    """Implicit adjoint at a converged map: returns (v, dL/dbeta, dL/dzhat [L, ...], CG iterations)."""
+    zhat, mask, fhat, dldf = _c128(zhat), _u8(mask), _f64(fhat), _f64(dldf)
+    v = np.zeros(pb.shape)
+    dzh = np.zeros(zhat.shape, np.complex128)
+    db = C.c_double(0.0)
+    its = C.c_int32(0)
+    c = pb.c()
+    _check(lib().fmo_adjoint(C.byref(c), _p(zhat), _p(mask), _p(fhat), _p(dldf), C.c_int32(maxit),
+                             C.c_double(rtol), _p(v), C.byref(db), _p(dzh), C.byref(its)))
+    return v, db.value, dzh, its.value
+
+
+def zhat_to_y_grad(dzhat, sens, ncoil):
+    """dL/dy_cl = (s_c / sqrt(sum |s|^2)) dL/dzhat_l (zhat is linear in y)."""
+    L = dzhat.shape[0]
+    if sens is None:
+        return dzhat.reshape((1, L) + dzhat.shape[1:]).copy()
+    s = np.asarray(sens, np.complex128)
+    S = np.sqrt((np.abs(s) ** 2).sum(0))
+    scale = np.where(S > 0, 1.0 / np.where(S > 0, S, 1.0), 0.0)
+    return np.stack([np.stack([s[c] * scale * dzhat[l] for l in range(L)]) for c in range(ncoil)])
+
+
 # --- whole pipeline for a synthetic volume --------------------------------------
 
 def problem_for(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, beta=None):
