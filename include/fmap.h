@@ -164,6 +164,38 @@ fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
  * synchronising the stream. */
 fm_status fm_mask_count(fm_plan *plan, int64_t *count, hipStream_t stream);
 
+/* Implicit adjoint of the map left by the last fm_solve / fm_iterate (not part
+ * of the paper: it differentiates the minimiser of Sec. II eq. (cost), whose
+ * gradient vanishes there).  With H = diag(h) + beta C^T C the exact Hessian
+ * of the cost at the map (h_j from the cosines of the echo-pair terms, not
+ * the Huber bound of Sec. III-B eq. (ls_huber)), it solves H v = dL/df by
+ * conjugate gradients preconditioned as the iteration is (IC(0) of the Huber
+ * model in the plan's ordering, its diagonal, or none), stopping once
+ * ||r|| <= rtol ||dL/df|| or after maxit iterations, and returns
+ *   dL/dbeta = -v^T C^T C f                               (host float64)
+ *   dL/dy_cl = -(s_c / sqrt(sum |s|^2)) v d g / d zhat_l  (dev complex64,
+ *              layout of y; d/dRe + i d/dIm convention, as torch uses)
+ * where g is the gradient of the cost in f.
+ *   dldf    dev float64 [N] (values outside the mask are ignored)
+ *   sens    the coil maps given to fm_setup (NULL iff ncoil == 1); only read
+ *           when dldy is not NULL
+ *   dldy    dev complex64 [ncoil][necho][nx][ny][nz], or NULL
+ *   v_out   dev float64 [N] (v, 0 outside the mask), or NULL
+ *   dldbeta host float64, or NULL;  iters host int32 (CG iterations), or NULL
+ * The derivative is that of the exact minimiser, so it describes the solver's
+ * output to the extent that the iteration has converged.  Synchronises the
+ * stream (convergence is checked every few CG iterations).  Returns
+ * FM_ERR_STATE without a previous solve, FM_ERR_NOT_PD if the Hessian is not
+ * positive definite along a CG direction (the map is not a strict local
+ * minimum).  The first call allocates the adjoint workspace (about 10 values
+ * per voxel). */
+fm_status fm_adjoint(fm_plan *plan, const double *dldf, const void *sens, void *dldy, double *v_out,
+                     double *dldbeta, int32_t maxit, double rtol, int32_t *iters, hipStream_t stream);
+
+/* Change beta of an existing plan (for tuning beta by gradient without a new
+ * plan).  The next call must be fm_solve. */
+fm_status fm_set_beta(fm_plan *plan, double beta);
+
 /* Kernel classes reported by fm_time_kernels. */
 enum {
   FM_K_GRAD = 0,      /* gradient pass: data term, stencil, f update        */

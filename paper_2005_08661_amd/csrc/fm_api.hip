@@ -17,6 +17,7 @@
 #include "fm_kernels.hpp"
 #include "fm_stream.hpp"
 #include "fm_natural.hpp"
+#include "fm_adjoint.hpp"
 
 using fm::kBlock;
 using fm::kMaxGrid;
@@ -94,6 +95,13 @@ struct fm_plan {
   // graphs of the iteration loop keyed by (chain parity, iterations)
   hipStream_t cap_stream = nullptr;
   std::map<std::vector<int64_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  // implicit adjoint workspace (allocated by the first fm_adjoint call)
+  bool adj_ready = false;
+  void *aR = nullptr, *aZ = nullptr, *aX = nullptr, *aDc = nullptr, *aH = nullptr, *aV = nullptr;
+  void *aDd[2] = {nullptr, nullptr};
+  double *a_hinv = nullptr, *a_ipiv = nullptr, *a_part = nullptr;
+  fm::State *aS = nullptr;
+  int32_t *a_status = nullptr;
 };
 
 namespace {
@@ -475,6 +483,177 @@ fm_status read_status(fm_plan *p, hipStream_t s, int32_t *status) {
   return FM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Implicit adjoint: CG on the exact Hessian at fhat, preconditioned like the
+// iteration.  The chain has its own state/partial ping-pong (position aq).
+fm_status adj_alloc(fm_plan *p) {
+  if (p->adj_ready) return FM_OK;
+  const size_t n = (size_t)p->n, ts = p->tsize;
+  bool ok = plan_alloc_padded(p, &p->aR, n, ts) && plan_alloc_padded(p, &p->aZ, n, ts) &&
+            plan_alloc_padded(p, &p->aX, n, ts) && plan_alloc_padded(p, &p->aDc, n, ts) &&
+            plan_alloc_padded(p, &p->aH, n, ts) && plan_alloc_padded(p, &p->aV, n, ts) &&
+            plan_alloc_padded(p, &p->aDd[0], n, ts) && plan_alloc_padded(p, &p->aDd[1], n, ts) &&
+            plan_alloc_padded(p, (void **)&p->a_hinv, n, sizeof(double)) &&
+            plan_alloc_padded(p, (void **)&p->a_ipiv, n, sizeof(double)) &&
+            plan_alloc(p, (void **)&p->a_part, sizeof(double) * 2 * p->part_rows * kMaxK) &&
+            plan_alloc(p, (void **)&p->aS, sizeof(fm::State) * 2) && plan_alloc(p, (void **)&p->a_status, sizeof(int32_t));
+  if (!ok) return fail(FM_ERR_ALLOC, "hipMalloc of the adjoint workspace failed");
+  if (hipMemset(p->a_part, 0, sizeof(double) * 2 * p->part_rows * kMaxK) != hipSuccess ||
+      hipMemset(p->aS, 0, sizeof(fm::State) * 2) != hipSuccess)
+    return fail(FM_ERR_HIP, "hipMemset of the adjoint state failed");
+  p->adj_ready = true;
+  return FM_OK;
+}
+
+template <typename T>
+fm::AdjArgs<T> adj_args(fm_plan *p, uint64_t q, int par, int nparts_in) {
+  fm::AdjArgs<T> a{};
+  a.geo = p->geo;
+  a.L = p->prm.necho;
+  a.beta = p->prm.beta;
+  a.dat = (const fm::T2<T> *)p->dat;
+  a.code = p->code;
+  a.pairs = (const fm::PairC<T> *)p->pairs;
+  a.F = (const T *)p->F[p->iter_host & 1];  // the final pass wrote fhat there
+  a.R = (T *)p->aR;
+  a.Zp = (const T *)p->aZ;
+  a.Dd[0] = (T *)p->aDd[0];
+  a.Dd[1] = (T *)p->aDd[1];
+  a.V = (T *)p->aV;
+  a.H = (T *)p->aH;
+  a.Dc = (T *)p->aDc;
+  a.hinv = p->a_hinv;
+  a.par = par;
+  a.nparts_in = nparts_in;
+  a.sin = p->aS + (q & 1);
+  a.sout = p->aS + ((q + 1) & 1);
+  a.pin = p->a_part + (size_t)(q & 1) * p->part_rows * kMaxK;
+  a.pout = p->a_part + (size_t)((q + 1) & 1) * p->part_rows * kMaxK;
+  a.status = p->a_status;
+  return a;
+}
+
+// Arguments of the iteration's preconditioner passes pointed at the adjoint
+// buffers: right-hand side r, output z, curvature D of the Huber model.
+template <typename T>
+fm::IterArgs<T> adj_precond_args(fm_plan *p, uint64_t q, int nparts_in) {
+  fm::IterArgs<T> a{};
+  a.geo = p->geo;
+  a.L = p->prm.necho;
+  a.beta = p->prm.beta;
+  a.dat = (const fm::T2<T> *)p->dat;
+  a.code = p->code;
+  a.pairs = (const fm::PairC<T> *)p->pairs;
+  for (int i = 0; i < 2; ++i) {
+    a.F[i] = (T *)p->aV;
+    a.Z[i] = (T *)p->aV;
+    a.G[i] = (T *)p->aR;
+  }
+  a.D = (T *)p->aDc;
+  a.X = (T *)p->aX;
+  a.P = (T *)p->aZ;
+  a.ipiv = p->a_ipiv;
+  a.hinv = p->a_hinv;
+  a.write_hinv = 0;
+  a.store_piv = 0;
+  a.par = 0;
+  a.nparts_in = nparts_in;
+  a.sin = p->aS + (q & 1);
+  a.sout = p->aS + ((q + 1) & 1);
+  a.pin = p->a_part + (size_t)(q & 1) * p->part_rows * kMaxK;
+  a.pout = p->a_part + (size_t)((q + 1) & 1) * p->part_rows * kMaxK;
+  a.status = p->a_status;
+  a.trace = nullptr;
+  return a;
+}
+
+template <typename T>
+fm_status adj_enqueue_iteration(fm_plan *p, uint64_t &q, int &np, int k, hipStream_t s) {
+  const T *r = (const T *)p->aR;
+  Recorder *rec = nullptr;
+  if (p->prm.precond == FM_PRECOND_IC0) {
+    if (p->prm.ordering == FM_ORDER_NATURAL) {
+      FM_LAUNCH(0, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np), p->wf, r);
+      FM_LAUNCH_CHECK();
+      np = 0;
+      FM_LAUNCH(0, fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np), p->wf, r);
+      FM_LAUNCH_CHECK();
+      np = p->wf.ntiles;
+    } else {
+      FM_LAUNCH(0, fm::k_rb_black<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np), r);
+      FM_LAUNCH_CHECK();
+      np = p->sgrid;
+      FM_LAUNCH(0, fm::k_rb_red<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np), r);
+      FM_LAUNCH_CHECK();
+      np = p->sgrid;
+    }
+  } else {
+    FM_LAUNCH(0, fm::k_diag<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np), r,
+              p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
+    FM_LAUNCH_CHECK();
+    np = p->sgrid;
+  }
+  FM_LAUNCH(0, fm::k_adj_dir<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np));
+  FM_LAUNCH_CHECK();
+  np = p->sgrid;
+  FM_LAUNCH(0, fm::k_adj_update<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np));
+  FM_LAUNCH_CHECK();
+  np = p->sgrid;
+  return FM_OK;
+}
+
+fm_status adj_finish(fm_plan *p, uint64_t &q, int &np, fm::State *host, hipStream_t s) {
+  hipLaunchKernelGGL(fm::k_finish, dim3(1), dim3(kBlock), 0, s, (const fm::State *)(p->aS + (q & 1)),
+                     p->aS + ((q + 1) & 1), (const double *)(p->a_part + (size_t)(q & 1) * p->part_rows * kMaxK),
+                     np, p->prm.beta, (double *)nullptr, p->a_status);
+  FM_LAUNCH_CHECK();
+  ++q;
+  np = 0;
+  FM_HIP(hipMemcpyAsync(host, p->aS + (q & 1), sizeof(fm::State), hipMemcpyDeviceToHost, s));
+  FM_HIP(hipStreamSynchronize(s));
+  return FM_OK;
+}
+
+constexpr int kAdjCheck = 8;  // CG iterations between convergence checks on the host
+
+template <typename T, int LMAX>
+struct OpAdjoint {
+  static fm_status run(fm_plan *p, const double *dldf, const void *sens, void *dldy, double *vout, int maxit,
+                       double rtol, fm::State *out, hipStream_t s) {
+    uint64_t q = 0;
+    int np = 0;
+    const int write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? 1 : 0;
+    hipLaunchKernelGGL((fm::k_adj_setup<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, 0),
+                       dldf, rtol * rtol, write_hinv);
+    FM_LAUNCH_CHECK();
+    np = p->sgrid;
+    fm::State st{};
+    int k = 0;
+    while (k < maxit) {
+      const int chunk = (maxit - k) < kAdjCheck ? (maxit - k) : kAdjCheck;
+      for (int i = 0; i < chunk; ++i, ++k) {
+        fm_status e = adj_enqueue_iteration<T>(p, q, np, k, s);
+        if (e) return e;
+      }
+      fm_status e = adj_finish(p, q, np, &st, s);
+      if (e) return e;
+      if (st.cg_done) break;
+    }
+    if (maxit == 0) {
+      fm_status e = adj_finish(p, q, np, &st, s);
+      if (e) return e;
+    }
+    hipLaunchKernelGGL((fm::k_adj_out<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, np),
+                       (const float2 *)sens, p->prm.ncoil, (float2 *)dldy, vout);
+    FM_LAUNCH_CHECK();
+    np = p->sgrid;
+    fm_status e = adj_finish(p, q, np, &st, s);
+    if (e) return e;
+    *out = st;
+    return FM_OK;
+  }
+};
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -783,6 +962,44 @@ fm_status fm_time_kernels(fm_plan *p, int32_t niter, double *ms, int32_t *launch
     ms[rec.cls[k]] += t;
     launches[rec.cls[k]] += 1;
   }
+  return FM_OK;
+}
+
+fm_status fm_adjoint(fm_plan *p, const double *dldf, const void *sens, void *dldy, double *v_out,
+                     double *dldbeta, int32_t maxit, double rtol, int32_t *iters, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!dldf) return fail(FM_ERR_ARG, "dL/df must not be NULL");
+  if (!sens && p->prm.ncoil != 1 && dldy) return fail(FM_ERR_ARG, "sens may be NULL only when ncoil == 1");
+  if (maxit < 0 || !(rtol >= 0.0) || !std::isfinite(rtol)) return fail(FM_ERR_ARG, "maxit must be >= 0 and rtol finite, >= 0");
+  if (!p->solved) return fail(FM_ERR_STATE, "fm_adjoint needs a converged map from fm_solve or fm_iterate");
+  fm_status st = adj_alloc(p);
+  if (st) return st;
+  FM_HIP(hipMemsetAsync(p->a_status, 0, sizeof(int32_t), s));
+  fm::State out{};
+  st = dispatch<OpAdjoint>(p, dldf, sens, dldy, v_out, (int)maxit, rtol, &out, s);
+  if (st) return st;
+  int32_t status = 0;
+  FM_HIP(hipMemcpyAsync(&status, p->a_status, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  FM_HIP(hipStreamSynchronize(s));
+  if (iters) *iters = out.cg_it;
+  if (dldbeta) *dldbeta = out.cg_dbeta;
+  if (status == FM_ERR_NOT_PD) return fail(FM_ERR_NOT_PD, "adjoint CG: the Hessian is not positive definite at the map");
+  if (status) return fail((fm_status)status, "adjoint CG reported a device-side error");
+  return FM_OK;
+}
+
+fm_status fm_set_beta(fm_plan *p, double beta) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!(beta >= 0.0) || !std::isfinite(beta)) return fail(FM_ERR_ARG, "beta must be finite and >= 0");
+  for (auto &kv : p->graphs) {
+    if (kv.second.second) (void)hipGraphExecDestroy(kv.second.second);
+    if (kv.second.first) (void)hipGraphDestroy(kv.second.first);
+  }
+  p->graphs.clear();
+  p->prm.beta = beta;
+  p->solved = false;
   return FM_OK;
 }
 

@@ -10,7 +10,10 @@ namespace fm {
 
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
 constexpr int kWave = 64;        // CDNA wavefront
-constexpr int kMaxGrid = 512;    // blocks (hence partial sums) of a streaming pass
+#ifndef FM_MAXGRID
+#define FM_MAXGRID 512
+#endif
+constexpr int kMaxGrid = FM_MAXGRID;  // blocks (hence partial sums) of a streaming pass
 constexpr int kMaxK = 4;         // values reduced per kernel
 
 // Neighbour code of a voxel: bit 0 = inside the mask; bits 1..6 = the
@@ -31,6 +34,10 @@ enum PartKind : int32_t {
   PK_DIR = 4,    // z^T C^T C f, ||C z||^2, sum z^2 D
   PK_MLS = 5,    // S1 = z^T dphi(f + alpha z), S2 = sum z^2 d(f + alpha z)
   PK_COUNT = 6,  // in-mask voxel count
+  PK_ADJ_INIT = 7, // adjoint CG: ||b||^2 of the right-hand side dL/df
+  PK_ADJ_CURV = 8, // adjoint CG: d^T H d
+  PK_ADJ_UPD = 9,  // adjoint CG: ||r||^2 after the update
+  PK_ADJ_FIN = 10, // adjoint: v^T C^T C fhat
 };
 
 // Scalar state of one solve.  Two copies ping-pong along the kernel chain:
@@ -58,6 +65,17 @@ struct State {
   int32_t nmls;     // line-search steps per iteration
   int32_t trace_cap;// rows of the trace (iterations recorded)
   int32_t ls_done;  // line search of this iteration stopped (zero curvature)
+  // conjugate gradients of the implicit adjoint (H v = dL/df); the
+  // preconditioner passes leave r^T M^{-1} r in gtp
+  double cg_rho;      // r^T z of the current CG iteration
+  double cg_rho_prev; // r^T z of the previous one
+  double cg_alpha;    // CG step
+  double cg_b2;       // ||dL/df||^2
+  double cg_r2;       // ||r||^2
+  double cg_rtol2;    // squared relative tolerance
+  double cg_dbeta;    // dL/dbeta = -v^T C^T C fhat
+  int32_t cg_it;      // CG updates applied
+  int32_t cg_done;    // converged (or broken down): later passes are no-ops
 };
 
 // Per echo-pair constants (m < n): weight factor 2|Gamma_mn|, phase of
@@ -296,6 +314,39 @@ __device__ __forceinline__ void consume(State &s, const double (&t)[kMaxK], doub
         }
       }
       s.ls_left -= 1;
+      break;
+    }
+    case PK_ADJ_INIT:
+    case PK_ADJ_UPD: {
+      if (s.kind == PK_ADJ_INIT) s.cg_b2 = t[0];
+      if (!s.cg_done) {
+        s.cg_r2 = t[0];
+        if (!isfinite(t[0])) {
+          s.cg_done = 1;
+          if (w) set_status(status, 6);
+        } else if (s.cg_r2 <= s.cg_rtol2 * s.cg_b2) {
+          s.cg_done = 1;
+        }
+      }
+      break;
+    }
+    case PK_ADJ_CURV: {
+      if (!s.cg_done) {
+        if (t[0] > 0.0) {
+          s.cg_alpha = s.cg_rho / t[0];
+          s.cg_rho_prev = s.cg_rho;
+          s.cg_it += 1;
+        } else {
+          // the true Hessian is not positive definite along d
+          s.cg_alpha = 0.0;
+          s.cg_done = 1;
+          if (w) set_status(status, 5);
+        }
+      }
+      break;
+    }
+    case PK_ADJ_FIN: {
+      s.cg_dbeta = -t[0];
       break;
     }
     default:

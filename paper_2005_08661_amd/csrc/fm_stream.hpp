@@ -20,7 +20,10 @@ namespace fm {
 #define FM_VPT64 2
 #endif
 
-constexpr int kNT = 512;
+#ifndef FM_NT
+#define FM_NT 512
+#endif
+constexpr int kNT = FM_NT;  // threads per block of the streaming passes
 
 template <typename T>
 struct Vpt {

@@ -30,7 +30,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "device allocat
 
 EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval", "fm_precondition",
             "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
-            "fm_status_string", "fm_last_error"]
+            "fm_adjoint", "fm_set_beta", "fm_status_string", "fm_last_error"]
 KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls"]
 
 
@@ -71,6 +71,9 @@ def lib():
         L.fm_get_trace.argtypes = [vp, vp, vp]
         L.fm_mask_count.argtypes = [vp, C.POINTER(C.c_int64), vp]
         L.fm_time_kernels.argtypes = [vp, C.c_int32, vp, vp, vp]
+        L.fm_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32, C.c_double,
+                                 C.POINTER(C.c_int32), vp]
+        L.fm_set_beta.argtypes = [vp, C.c_double]
         L.fm_status_string.restype = C.c_char_p
         L.fm_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -254,6 +257,25 @@ class Plan:
                                      C.c_void_p(n.ctypes.data), _stream()))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
+    def adjoint(self, dldf, want_dy=True, want_v=False, maxit=1000, rtol=1e-10):
+        """Implicit adjoint of the last solve for the cotangent dldf (float64 volume).
+
+        Returns dict(dbeta=float, dy=complex64 tensor like y or None, v=float64 volume or None,
+        iters=int).  The coil maps are the ones given to the last solve."""
+        import torch
+        g = self._vec(dldf)
+        dy = torch.zeros_like(self._y) if want_dy else None
+        v = self._vol(torch.float64, g.device) if want_v else None
+        db = C.c_double(0.0)
+        its = C.c_int32(0)
+        _check(lib().fm_adjoint(self._h, _ptr(g), _ptr(self._s), _ptr(dy), _ptr(v), C.byref(db),
+                                C.c_int32(int(maxit)), C.c_double(float(rtol)), C.byref(its), _stream()))
+        return dict(dbeta=db.value, dy=dy, v=v, iters=its.value)
+
+    def set_beta(self, beta):
+        _check(lib().fm_set_beta(self._h, C.c_double(float(beta))))
+        self.params.beta = float(beta)
+
     def mask_count(self):
         v = C.c_int64(0)
         _check(lib().fm_mask_count(self._h, C.byref(v), _stream()))
@@ -280,3 +302,44 @@ def solve_volume(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, 
         f = plan.solve(y, s, m, f0)
         tr = plan.trace()
         return f.cpu().numpy(), tr
+
+
+def _autograd_function():
+    import torch
+
+    class FieldMapSolve(torch.autograd.Function):
+        """f = argmin of the regularised cost for (y, beta); backward by the implicit adjoint.
+
+        forward(y, sens, mask, beta, plan, f0, maxit, rtol): y complex64 [ncoil, L, X, Y, Z],
+        beta a 0-d float tensor.  Gradients flow to y and beta."""
+
+        @staticmethod
+        def forward(ctx, y, sens, mask, beta, plan, f0=None, maxit=1000, rtol=1e-10):
+            plan.set_beta(float(beta))
+            f = plan.solve(y.detach(), None if sens is None else sens.detach(), mask, f0)
+            ctx.plan, ctx.maxit, ctx.rtol = plan, maxit, rtol
+            ctx.beta_dtype = beta.dtype
+            return f
+
+        @staticmethod
+        def backward(ctx, gf):
+            out = ctx.plan.adjoint(gf.detach(), want_dy=ctx.needs_input_grad[0], maxit=ctx.maxit,
+                                   rtol=ctx.rtol)
+            dy = out["dy"] if ctx.needs_input_grad[0] else None
+            db = None
+            if ctx.needs_input_grad[3]:
+                db = torch.tensor(out["dbeta"], dtype=ctx.beta_dtype, device=gf.device)
+            return dy, None, None, db, None, None, None, None
+
+    return FieldMapSolve
+
+
+_FMS = None
+
+
+def fieldmap_solve(y, sens, mask, beta, plan, f0=None, maxit=1000, rtol=1e-10):
+    """Differentiable solve (torch.autograd): returns the float64 map; see FieldMapSolve."""
+    global _FMS
+    if _FMS is None:
+        _FMS = _autograd_function()
+    return _FMS.apply(y, sens, mask, beta, plan, f0, maxit, rtol)

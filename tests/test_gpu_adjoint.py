@@ -1,0 +1,197 @@
+"""Implicit adjoint on the GPU (fm_adjoint) against the FP64 oracle and finite differences.
+
+The adjoint is compared with the oracle's adjoint evaluated at the GPU's own
+map, so the check isolates the backward computation from the forward solve.
+Bars: F64 within 1e-7 relative (both CGs solved to 1e-12), MIX within 1e-3
+relative (FP32 per-voxel vectors and trig, CG to 1e-6); finite differences
+of converged F64 solves within 1e-4 relative (dbeta) and 1e-3 along random
+directions of y (complex64 inputs, h = 1e-3).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_08661_amd import fmap, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    fmap.lib()
+
+
+ORDER = {"natural": fmap.NATURAL, "redblack": fmap.REDBLACK}
+PREC = {"f64": fmap.F64, "mix": fmap.MIX}
+
+
+def small_volume():
+    return synth.random_volume((6, 5, 4), 2, 3, 11, beta=0.05, niter=10)
+
+
+def ragged_volume():
+    vol = synth.fieldmap_volume((20, 17, 11), 3, [0.0, 1.0e-3, 3.0e-3], 0.1, 15, synth.SEED_BASE + 903, 3,
+                                150.0, False, 25.0, mask="full", name="20x17x11 random mask")
+    rng = np.random.default_rng(9)
+    vol.mask = (rng.uniform(size=vol.shape) < 0.85).astype(np.uint8)
+    return vol
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def gpu_solve_and_adjoint(vol, prec, order, niter, dldf, rtol, precond=fmap.IC0):
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=order, precond=precond, niter=niter)) as plan:
+        f = plan.solve(y, s, m)
+        out = plan.adjoint(torch.from_numpy(dldf).cuda(), want_v=True, rtol=rtol)
+        torch.cuda.synchronize()
+        return f.cpu().numpy(), out["v"].cpu().numpy(), out["dbeta"], out["dy"].cpu().numpy(), out["iters"]
+
+
+def oracle_adjoint(vol, f, dldf, order=O.NATURAL, precond=O.IC0):
+    pb = O.problem_for(vol, order, precond)
+    zh = O.combine(vol.y, vol.sens)
+    v, db, dz, its = O.adjoint(pb, zh, vol.mask, f, dldf, maxit=2000, rtol=1e-12)
+    return v, db, O.zhat_to_y_grad(dz, vol.sens, vol.ncoil), its
+
+
+@pytest.mark.parametrize("order", ["redblack", "natural"])
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", ["small", "ragged"])
+def test_adjoint_matches_oracle_at_gpu_map(vname, prec, order):
+    vol = small_volume() if vname == "small" else ragged_volume()
+    say("adjoint %s %s %s" % (vname, prec, order))
+    rng = np.random.default_rng(21)
+    dldf = rng.standard_normal(vol.shape) * vol.mask
+    rtol = 1e-12 if prec == "f64" else 1e-6
+    f, v, db, dy, its = gpu_solve_and_adjoint(vol, PREC[prec], ORDER[order], 400, dldf, rtol)
+    vo, dbo, dyo, itso = oracle_adjoint(vol, f, dldf, ORDER[order])
+    bar = 1e-7 if prec == "f64" else 1e-3
+    assert rel(v, vo) < bar
+    assert abs(db - dbo) <= bar * abs(dbo)
+    assert rel(dy, dyo) < bar
+    assert np.all(v[vol.mask == 0] == 0)
+    if prec == "f64":
+        # same preconditioner and ordering: the same CG iteration count (+-1 at the tolerance edge)
+        assert abs(its - itso) <= 1
+
+
+@pytest.mark.parametrize("precond", [fmap.DIAG, fmap.NONE])
+def test_adjoint_other_preconditioners(precond):
+    vol = ragged_volume()
+    say("adjoint preconditioner %d" % precond)
+    rng = np.random.default_rng(22)
+    dldf = rng.standard_normal(vol.shape) * vol.mask
+    f, v, db, dy, its = gpu_solve_and_adjoint(vol, fmap.F64, fmap.NATURAL, 400, dldf, 1e-12, precond)
+    vo, dbo, dyo, _ = oracle_adjoint(vol, f, dldf)
+    assert rel(v, vo) < 1e-7 and abs(db - dbo) <= 1e-7 * abs(dbo) and rel(dy, dyo) < 1e-7
+
+
+def test_adjoint_finite_differences():
+    """dL/dbeta and dL/dy of L = c^T f against central differences of converged GPU solves."""
+    vol = small_volume()
+    say("adjoint finite differences")
+    rng = np.random.default_rng(23)
+    c = rng.standard_normal(vol.shape) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    prm = fmap.params_for(vol, precision=fmap.F64, ordering=fmap.REDBLACK, niter=3000)
+    with fmap.Plan(prm) as plan:
+        f = plan.solve(y, s, m)
+        out = plan.adjoint(torch.from_numpy(c).cuda())
+        ct = torch.from_numpy(c).cuda()
+
+        def loss(beta=None, yy=None):
+            if beta is not None:
+                plan.set_beta(beta)
+            ff = plan.solve(y if yy is None else yy, s, m, f0=f)
+            plan.set_beta(vol.beta)
+            return float((ct * ff).sum())
+
+        h = 1e-5
+        fd = (loss(beta=vol.beta + h) - loss(beta=vol.beta - h)) / (2 * h)
+        assert out["dbeta"] == pytest.approx(fd, rel=1e-4)
+        dy = out["dy"]
+        g = torch.Generator().manual_seed(24)
+        for k in range(20):
+            u = torch.complex(torch.randn(y.shape, generator=g), torch.randn(y.shape, generator=g)).to(y.device)
+            h = 1e-3
+            yp, ym = y + h * u, y - h * u  # complex64: compare along the perturbation actually applied
+            fd = (loss(yy=yp) - loss(yy=ym)) / (2 * h)
+            du = (yp.to(torch.complex128) - ym.to(torch.complex128)) / (2 * h)
+            dyd = dy.to(torch.complex128)
+            an = float((dyd.real * du.real + dyd.imag * du.imag).sum())
+            assert an == pytest.approx(fd, rel=1e-3, abs=1e-9), k
+
+
+def test_autograd_function_matches_adjoint():
+    vol = small_volume()
+    say("autograd")
+    y, s, m = fmap.to_device(vol)
+    prm = fmap.params_for(vol, precision=fmap.F64, ordering=fmap.REDBLACK, niter=2000)
+    ftrue = torch.from_numpy(vol.f_true * vol.mask).cuda()
+    with fmap.Plan(prm) as plan:
+        yv = y.clone().requires_grad_(True)
+        beta = torch.tensor(vol.beta, dtype=torch.float64, requires_grad=True)
+        f = fmap.fieldmap_solve(yv, s, m, beta, plan)
+        loss = ((f - ftrue) ** 2 * m).sum()
+        loss.backward()
+        f2 = plan.solve(y, s, m)
+        ref = plan.adjoint(2 * (f2 - ftrue) * m)
+        torch.testing.assert_close(yv.grad, ref["dy"], rtol=1e-9, atol=1e-12)
+        assert float(beta.grad) == pytest.approx(ref["dbeta"], rel=1e-9)
+
+
+def test_adjoint_edge_cases():
+    vol = small_volume()
+    say("adjoint edge cases")
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, niter=50)) as plan:
+        with pytest.raises(fmap.FmapError) as e:
+            plan.setup(y, s, m)
+            plan.adjoint(torch.zeros(vol.shape, dtype=torch.float64, device="cuda"))
+        assert e.value.status == 7
+        plan.solve(y, s, m)
+        out = plan.adjoint(torch.zeros(vol.shape, dtype=torch.float64, device="cuda"), want_v=True)
+        assert out["iters"] == 0 and out["dbeta"] == 0.0
+        assert not out["dy"].abs().any() and not out["v"].any()
+        rng = np.random.default_rng(3)
+        dldf = torch.from_numpy(rng.standard_normal(vol.shape) * vol.mask).cuda()
+        out0 = plan.adjoint(dldf, maxit=0, want_v=True)
+        assert out0["iters"] == 0 and not out0["v"].any()
+        a = plan.adjoint(dldf, maxit=3)
+        assert a["iters"] == 3
+        # repeated calls give bit-identical results
+        b1, b2 = plan.adjoint(dldf), plan.adjoint(dldf)
+        assert b1["dbeta"] == b2["dbeta"] and torch.equal(b1["dy"], b2["dy"])
+        with pytest.raises(fmap.FmapError):
+            plan.adjoint(dldf, rtol=-1.0)
+
+
+def test_adjoint_full_size_mix():
+    """128x128x64, 8 coils, L = ||f - f_true||^2: MIX adjoint against the oracle at the GPU's map."""
+    vol = synth.mid_fieldmap()
+    say("adjoint full size %s" % (vol.shape,))
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.MIX, ordering=fmap.REDBLACK)) as plan:
+        f = plan.solve(y, s, m)
+        ftrue = torch.from_numpy(vol.f_true).cuda()
+        dldf_t = 2.0 * (f - ftrue) * m
+        out = plan.adjoint(dldf_t, want_v=True, rtol=1e-6)
+        torch.cuda.synchronize()
+        fn, dldf = f.cpu().numpy(), dldf_t.cpu().numpy()
+        dy, db, its = out["dy"].cpu().numpy(), out["dbeta"], out["iters"]
+    say("gpu adjoint: %d CG iterations, dL/dbeta %.6e" % (its, db))
+    vo, dbo, dyo, itso = oracle_adjoint(vol, fn, dldf, O.REDBLACK)
+    say("oracle adjoint: %d CG iterations, dL/dbeta %.6e" % (itso, dbo))
+    assert abs(db - dbo) <= 1e-3 * abs(dbo)
+    assert rel(dy, dyo) < 1e-3
