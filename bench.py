@@ -98,6 +98,54 @@ def time_solve(plan, fmap, y, s, m, out, steps, torch):
     return ev0.elapsed_time(ev1) / max(steps, 1)
 
 
+def bench_batched(args, fmap, synth, torch, prec):
+    """16 uneven volumes (64..160 x 64..160 x 32..96, 4 coils, TE 0/2/5 ms, beta 2^U[-6,-2]):
+    one batched solve against a loop of single-volume solves, same precision and ordering."""
+    log("batched: generating 16 volumes")
+    vols = synth.batched(16)
+    dev = [fmap.to_device(v) for v in vols]
+    ys, ss, ms = [d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev]
+    nvox = sum(int(v.mask.sum()) for v in vols)
+    niter = vols[0].niter
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    prms = [fmap.params_for(v, precision=prec, ordering=fmap.REDBLACK) for v in vols]
+    with fmap.Batch(prms) as b:
+        grid, tune_ms = b.autotune(ys, ss, ms, probe_iters=3)
+        log("batched: autotuned %d workgroups (%.3f ms per iteration)" % (grid, tune_ms))
+        outs = b.solve(ys, ss, ms)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            outs = b.solve(ys, ss, ms)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_b = ev0.elapsed_time(ev1) / args.steps
+    plans = [fmap.Plan(p) for p in prms]
+    louts = [torch.zeros(v.shape, dtype=torch.float64, device="cuda") for v in vols]
+    for pl, (y, s, m), o in zip(plans, dev, louts):
+        pl.solve(y, s, m, out=o)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        for pl, (y, s, m), o in zip(plans, dev, louts):
+            pl.solve(y, s, m, out=o)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_l = ev0.elapsed_time(ev1) / args.steps
+    diff = max(float(torch.sqrt(torch.mean(((a - c)[mm.bool()]) ** 2))) for a, c, mm in zip(outs, louts, ms))
+    for pl in plans:
+        pl.close()
+    res = {"volumes": len(vols), "voxels": nvox, "grid": grid, "niter": niter, "precision": args.precision,
+           "ms_per_solve": ms_b, "value": nvox * niter / (ms_b * 1e-3),
+           "loop_ms_per_solve": ms_l, "loop_value": nvox * niter / (ms_l * 1e-3),
+           "speedup_vs_loop": ms_l / ms_b, "max_rms_diff_vs_loop_hz": diff,
+           "shapes": [list(v.shape) for v in vols]}
+    log("batched: %.3f ms per solve (%.3e voxel-iterations/s); loop of single solves %.3f ms; x%.2f; "
+        "max RMS difference %.2e Hz" % (ms_b, res["value"], ms_l, res["speedup_vs_loop"], diff))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +160,8 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-natural", action="store_true", help="skip the natural-order comparison line")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-volume batched comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the implicit-adjoint timing")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -190,6 +240,26 @@ def main():
                    "final_cost": float(trn[-1, 0])}
         log("natural order: %.3f ms per step, %.3e voxel-iterations/s" % (ms_nat, natural["value"]))
 
+    adjoint = None
+    if not args.no_adjoint:
+        # backward of L = ||f - f_true||^2 over the mask at the solved map (config of the differentiable form)
+        ftrue = torch.from_numpy(vol.f_true).cuda()
+        plan.solve(y, s, m, out=out)
+        dldf = 2.0 * (out - ftrue) * m
+        plan.adjoint(dldf, rtol=1e-6)  # workspace allocation, untimed
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.adjoint(dldf, rtol=1e-6)
+        torch.cuda.synchronize()
+        ms_adj = (time.perf_counter() - t0) * 1e3
+        adjoint = {"ms": ms_adj, "cg_iterations": res["iters"], "rtol": 1e-6, "dL_dbeta": res["dbeta"],
+                   "loss": "||f - f_true||^2 over the mask", "outputs": "dL/dbeta, dL/dy (complex64, 8 coils)"}
+        log("adjoint: %.3f ms, %d CG iterations" % (ms_adj, res["iters"]))
+
+    batched = None
+    if not args.no_batched:
+        batched = bench_batched(args, fmap, synth, torch, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -244,6 +314,8 @@ def main():
         },
         "final_cost": float(tr[-1, 0]),
         "natural_order": natural,
+        "adjoint": adjoint,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     plan.close()

@@ -196,6 +196,46 @@ fm_status fm_adjoint(fm_plan *plan, const double *dldf, const void *sens, void *
  * plan).  The next call must be fm_solve. */
 fm_status fm_set_beta(fm_plan *plan, double beta);
 
+/* ---- Batches: many volumes in one launch per pass ------------------------
+ * Not part of the paper: for throughput, nvol field-map volumes of possibly
+ * different grid sizes and beta are solved together; every pass of the
+ * Algorithm is one launch for all volumes (workgroups are partitioned among
+ * the volumes in proportion to their sizes) and the iteration loop is one HIP
+ * graph.  Each volume's iteration is the same as fm_solve's (its own scalar
+ * state, line search and trace), up to the order of floating-point sums.
+ * All volumes must share ncoil, necho, te, niter, nmls, precision, ordering
+ * and preconditioner; supported: the field-map model with red-black IC(0),
+ * the diagonal preconditioner or none. */
+typedef struct fm_batch fm_batch;
+
+/* prm: host array of nvol parameter sets (grid sizes and beta may differ). */
+fm_status fm_batch_create(int32_t nvol, const fm_params *prm, fm_batch **batch);
+fm_status fm_batch_destroy(fm_batch *batch);
+
+/* Solve all volumes.  y, sens, mask, f0 and f_out are host arrays of nvol
+ * device pointers with the layouts of fm_solve (sens may be NULL when
+ * ncoil == 1; f0 may be NULL, or have NULL entries, for the paper's initial
+ * map).  Synchronises the stream at the end. */
+fm_status fm_batch_solve(fm_batch *batch, const void *const *y, const void *const *sens,
+                         const uint8_t *const *mask, const double *const *f0, double *const *f_out,
+                         hipStream_t stream);
+
+/* Trace of volume v of the last batched solve (as fm_get_trace). */
+fm_status fm_batch_get_trace(fm_batch *batch, int32_t v, double *trace, hipStream_t stream);
+
+/* Workgroups of the batched launches (partitioned among the volumes); *used
+ * receives the count actually used (at least nvol, at most one per chunk). */
+fm_status fm_batch_set_grid(fm_batch *batch, int32_t grid, int32_t *used);
+
+/* Autotuner: time probe_iters iterations on the given data for each
+ * candidate workgroup count (256, 512, ... up to one per chunk of voxels),
+ * keep the fastest, and report it (*grid_out) with its time per iteration in
+ * milliseconds (*ms_out).  Either output may be NULL.  Leaves no solve
+ * behind: call fm_batch_solve afterwards. */
+fm_status fm_batch_autotune(fm_batch *batch, const void *const *y, const void *const *sens,
+                            const uint8_t *const *mask, int32_t probe_iters, int32_t *grid_out,
+                            double *ms_out, hipStream_t stream);
+
 /* Kernel classes reported by fm_time_kernels. */
 enum {
   FM_K_GRAD = 0,      /* gradient pass: data term, stencil, f update        */

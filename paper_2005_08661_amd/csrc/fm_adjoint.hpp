@@ -43,6 +43,7 @@ struct AdjArgs {
   double *hinv;    // 1 / (D + beta deg) for the red-black preconditioner
   int32_t par;     // CG iteration parity
   int32_t nparts_in;
+  int32_t nvals_in;
   const State *sin;
   State *sout;
   const double *pin;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kNT) void k_adj_dir(AdjArgs<T> a) {
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, nullptr, a.status);
+  State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, nullptr, a.status);
   double acc[1] = {0.0};
   if (!st.cg_done) {
     const double rho = st.gtp;  // r^T M^{-1} r from the preconditioner passes
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(kNT) void k_adj_update(AdjArgs<T> a) {
   };
   int base = (int)blockIdx.x * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, nullptr, a.status);
+  const State st = take_state<kNT, 1>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, nullptr, a.status);
   double acc[1] = {0.0};
   if (!st.cg_done) {
     const T alpha = (T)st.cg_alpha;

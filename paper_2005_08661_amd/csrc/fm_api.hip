@@ -4,6 +4,7 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -88,6 +89,7 @@ struct fm_plan {
   uint64_t q = 0;
   int64_t iter_host = 0;
   int last_nparts = 0;
+  int last_nvals = 0;   // values per partial block at the current position
   // device allocations (freed with the plan); stencil-read arrays are
   // padded by pad elements on both sides
   std::vector<void *> bases;
@@ -179,6 +181,7 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.store_piv = 0;
   a.par = (int32_t)(p->iter_host & 1);
   a.nparts_in = p->last_nparts;
+  a.nvals_in = p->last_nvals;
   a.sin = p->S + (q & 1);
   a.sout = p->S + ((q + 1) & 1);
   a.pin = p->part + (size_t)(q & 1) * p->part_rows * kMaxK;
@@ -224,6 +227,11 @@ struct Recorder {
 
 // Preconditioner step p = P^{-1} g (g from gsrc, or G[iter&1] if null),
 // leaving the dot products g^T p and g_prev^T p as partial sums.
+void set_parts(fm_plan *p, int nparts, int nvals) {
+  p->last_nparts = nparts;
+  p->last_nvals = nvals;
+}
+
 template <typename T>
 fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *rec = nullptr) {
   auto pargs = [&](fm_plan *pp, uint64_t q) {
@@ -235,23 +243,23 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
     if (p->prm.ordering == FM_ORDER_NATURAL) {
       FM_LAUNCH(FM_K_PRECOND_A, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, pargs(p, p->q++), p->wf, gsrc);
       FM_LAUNCH_CHECK();
-      p->last_nparts = 0;
+      set_parts(p, 0, 0);
       FM_LAUNCH(FM_K_PRECOND_B, fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, pargs(p, p->q++), p->wf, gsrc);
       FM_LAUNCH_CHECK();
-      p->last_nparts = p->wf.ntiles;
+      set_parts(p, p->wf.ntiles, 2);
     } else {
-      FM_LAUNCH(FM_K_PRECOND_A, fm::k_rb_black<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
+      FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
       FM_LAUNCH_CHECK();
-      p->last_nparts = p->sgrid;
-      FM_LAUNCH(FM_K_PRECOND_B, fm::k_rb_red<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
+      set_parts(p, p->sgrid, 2);
+      FM_LAUNCH(FM_K_PRECOND_B, (fm::k_rb_red<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
       FM_LAUNCH_CHECK();
-      p->last_nparts = p->sgrid;
+      set_parts(p, p->sgrid, 2);
     }
   } else {
-    FM_LAUNCH(FM_K_PRECOND_A, fm::k_diag<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc,
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_diag<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc,
                        p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
     FM_LAUNCH_CHECK();
-    p->last_nparts = p->sgrid;
+    set_parts(p, p->sgrid, 2);
   }
   return FM_OK;
 }
@@ -262,22 +270,26 @@ uint64_t launches_per_iteration(const fm_plan *p) {
   return 1 + precond + 1 + (uint64_t)(p->prm.nmls - 1);
 }
 
+// Values per partial block left by the last pass of an iteration.
+int tail_nvals(const fm_plan *p) { return p->prm.nmls > 1 ? 2 : 3; }
+
 // One NCG iteration: gradient, preconditioner (+ dots), direction, and the
 // remaining line-search passes; the last pass is consumed by the next
 // iteration's gradient pass (or by the final pass).
 template <typename T, int LMAX>
 fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) {
-  FM_LAUNCH(FM_K_GRAD, (fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+  FM_LAUNCH(FM_K_GRAD, (fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
   FM_LAUNCH_CHECK();
-  p->last_nparts = p->sgrid;
+  set_parts(p, p->sgrid, 4);
   fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
   if (st) return st;
-  FM_LAUNCH(FM_K_DIR, fm::k_dir<T>, dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+  FM_LAUNCH(FM_K_DIR, (fm::k_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
   FM_LAUNCH_CHECK();
-  p->last_nparts = p->sgrid;
+  set_parts(p, p->sgrid, 3);
   for (int k = 1; k < p->prm.nmls; ++k) {
-    FM_LAUNCH(FM_K_MLS, (fm::k_mls<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    FM_LAUNCH(FM_K_MLS, (fm::k_mls<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
     FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
   }
   p->iter_host += 1;
   return FM_OK;
@@ -289,15 +301,15 @@ fm_status enqueue_final(fm_plan *p, double *f_out, hipStream_t s) {
   fm::IterArgs<T> a = iter_args<T>(p, p->q++);
   a.final_pass = 1;
   a.fout = f_out;
-  hipLaunchKernelGGL((fm::k_grad<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
+  hipLaunchKernelGGL((fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
   FM_LAUNCH_CHECK();
-  p->last_nparts = p->sgrid;
+  set_parts(p, p->sgrid, 4);
   const uint64_t q = p->q++;
   hipLaunchKernelGGL(fm::k_finish, dim3(1), dim3(kBlock), 0, s, (const fm::State *)(p->S + (q & 1)),
                      p->S + ((q + 1) & 1), (const double *)(p->part + (size_t)(q & 1) * p->part_rows * kMaxK),
-                     p->last_nparts, p->prm.beta, p->trace, p->status);
+                     p->last_nparts, p->last_nvals, p->prm.beta, p->trace, p->status);
   FM_LAUNCH_CHECK();
-  p->last_nparts = 0;
+  set_parts(p, 0, 0);
   return FM_OK;
 }
 
@@ -423,12 +435,12 @@ void free_plan(fm_plan *p) {
 // launches occupy the same chain positions modulo 2).
 fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
   if (niter <= 0) return FM_OK;
-  const std::vector<int64_t> key = {(int64_t)(p->q & 1), niter, p->iter_host & 1, p->last_nparts};
+  const std::vector<int64_t> key = {(int64_t)(p->q & 1), niter, p->iter_host & 1, p->last_nparts, p->last_nvals};
   auto it = p->graphs.find(key);
   if (it == p->graphs.end()) {
     const uint64_t q0 = p->q;
     const int64_t it0 = p->iter_host;
-    const int np0 = p->last_nparts;
+    const int np0 = p->last_nparts, nv0 = p->last_nvals;
     FM_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
     fm_status st = dispatch<OpLoop>(p, niter, p->cap_stream);
     hipGraph_t g = nullptr;
@@ -437,7 +449,7 @@ fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
       if (g) (void)hipGraphDestroy(g);
       p->q = q0;
       p->iter_host = it0;
-      p->last_nparts = np0;
+      set_parts(p, np0, nv0);
       return st;
     }
     if (e != hipSuccess) return fail(FM_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -451,7 +463,7 @@ fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
   } else {
     p->q += launches_per_iteration(p) * (uint64_t)niter;
     p->iter_host += niter;
-    p->last_nparts = p->sgrid;  // the last pass of an iteration is a streaming pass
+    set_parts(p, p->sgrid, tail_nvals(p));  // the last pass of an iteration is a streaming pass
   }
   FM_HIP(hipGraphLaunch(it->second.second, s));
   return FM_OK;
@@ -460,7 +472,7 @@ fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
 template <typename T>
 fm_status enqueue_start(fm_plan *p, const double *f0, hipStream_t s) {
   p->iter_host = 0;
-  p->last_nparts = 0;
+  set_parts(p, 0, 0);
   const uint64_t q = p->q++;
   hipLaunchKernelGGL(fm::k_start<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, f0, (const uint8_t *)p->code,
                      (T *)p->F[1], (T *)p->Z[1], (T *)p->G[1], p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls,
@@ -506,7 +518,7 @@ fm_status adj_alloc(fm_plan *p) {
 }
 
 template <typename T>
-fm::AdjArgs<T> adj_args(fm_plan *p, uint64_t q, int par, int nparts_in) {
+fm::AdjArgs<T> adj_args(fm_plan *p, uint64_t q, int par, int nparts_in, int nvals_in) {
   fm::AdjArgs<T> a{};
   a.geo = p->geo;
   a.L = p->prm.necho;
@@ -525,6 +537,7 @@ fm::AdjArgs<T> adj_args(fm_plan *p, uint64_t q, int par, int nparts_in) {
   a.hinv = p->a_hinv;
   a.par = par;
   a.nparts_in = nparts_in;
+  a.nvals_in = nvals_in;
   a.sin = p->aS + (q & 1);
   a.sout = p->aS + ((q + 1) & 1);
   a.pin = p->a_part + (size_t)(q & 1) * p->part_rows * kMaxK;
@@ -536,7 +549,7 @@ fm::AdjArgs<T> adj_args(fm_plan *p, uint64_t q, int par, int nparts_in) {
 // Arguments of the iteration's preconditioner passes pointed at the adjoint
 // buffers: right-hand side r, output z, curvature D of the Huber model.
 template <typename T>
-fm::IterArgs<T> adj_precond_args(fm_plan *p, uint64_t q, int nparts_in) {
+fm::IterArgs<T> adj_precond_args(fm_plan *p, uint64_t q, int nparts_in, int nvals_in) {
   fm::IterArgs<T> a{};
   a.geo = p->geo;
   a.L = p->prm.necho;
@@ -558,6 +571,7 @@ fm::IterArgs<T> adj_precond_args(fm_plan *p, uint64_t q, int nparts_in) {
   a.store_piv = 0;
   a.par = 0;
   a.nparts_in = nparts_in;
+  a.nvals_in = nvals_in;
   a.sin = p->aS + (q & 1);
   a.sout = p->aS + ((q + 1) & 1);
   a.pin = p->a_part + (size_t)(q & 1) * p->part_rows * kMaxK;
@@ -568,47 +582,55 @@ fm::IterArgs<T> adj_precond_args(fm_plan *p, uint64_t q, int nparts_in) {
 }
 
 template <typename T>
-fm_status adj_enqueue_iteration(fm_plan *p, uint64_t &q, int &np, int k, hipStream_t s) {
+fm_status adj_enqueue_iteration(fm_plan *p, uint64_t &q, int &np, int &nv, int k, hipStream_t s) {
   const T *r = (const T *)p->aR;
   Recorder *rec = nullptr;
   if (p->prm.precond == FM_PRECOND_IC0) {
     if (p->prm.ordering == FM_ORDER_NATURAL) {
-      FM_LAUNCH(0, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np), p->wf, r);
+      FM_LAUNCH(0, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np, nv), p->wf, r);
       FM_LAUNCH_CHECK();
       np = 0;
-      FM_LAUNCH(0, fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np), p->wf, r);
+      nv = 0;
+      FM_LAUNCH(0, fm::k_ic_bwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np, nv), p->wf, r);
       FM_LAUNCH_CHECK();
       np = p->wf.ntiles;
+      nv = 2;
     } else {
-      FM_LAUNCH(0, fm::k_rb_black<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np), r);
+      FM_LAUNCH(0, (fm::k_rb_black<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np, nv), r);
       FM_LAUNCH_CHECK();
       np = p->sgrid;
-      FM_LAUNCH(0, fm::k_rb_red<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np), r);
+      nv = 2;
+      FM_LAUNCH(0, (fm::k_rb_red<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np, nv), r);
       FM_LAUNCH_CHECK();
       np = p->sgrid;
+      nv = 2;
     }
   } else {
-    FM_LAUNCH(0, fm::k_diag<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np), r,
+    FM_LAUNCH(0, (fm::k_diag<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np, nv), r,
               p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
     FM_LAUNCH_CHECK();
     np = p->sgrid;
+    nv = 2;
   }
-  FM_LAUNCH(0, fm::k_adj_dir<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np));
+  FM_LAUNCH(0, fm::k_adj_dir<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
   FM_LAUNCH_CHECK();
   np = p->sgrid;
-  FM_LAUNCH(0, fm::k_adj_update<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np));
+  nv = 1;
+  FM_LAUNCH(0, fm::k_adj_update<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
   FM_LAUNCH_CHECK();
   np = p->sgrid;
+  nv = 1;
   return FM_OK;
 }
 
-fm_status adj_finish(fm_plan *p, uint64_t &q, int &np, fm::State *host, hipStream_t s) {
+fm_status adj_finish(fm_plan *p, uint64_t &q, int &np, int &nv, fm::State *host, hipStream_t s) {
   hipLaunchKernelGGL(fm::k_finish, dim3(1), dim3(kBlock), 0, s, (const fm::State *)(p->aS + (q & 1)),
                      p->aS + ((q + 1) & 1), (const double *)(p->a_part + (size_t)(q & 1) * p->part_rows * kMaxK),
-                     np, p->prm.beta, (double *)nullptr, p->a_status);
+                     np, nv, p->prm.beta, (double *)nullptr, p->a_status);
   FM_LAUNCH_CHECK();
   ++q;
   np = 0;
+  nv = 0;
   FM_HIP(hipMemcpyAsync(host, p->aS + (q & 1), sizeof(fm::State), hipMemcpyDeviceToHost, s));
   FM_HIP(hipStreamSynchronize(s));
   return FM_OK;
@@ -621,33 +643,35 @@ struct OpAdjoint {
   static fm_status run(fm_plan *p, const double *dldf, const void *sens, void *dldy, double *vout, int maxit,
                        double rtol, fm::State *out, hipStream_t s) {
     uint64_t q = 0;
-    int np = 0;
+    int np = 0, nv = 0;
     const int write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? 1 : 0;
-    hipLaunchKernelGGL((fm::k_adj_setup<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, 0),
+    hipLaunchKernelGGL((fm::k_adj_setup<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, 0, 0),
                        dldf, rtol * rtol, write_hinv);
     FM_LAUNCH_CHECK();
     np = p->sgrid;
+    nv = 1;
     fm::State st{};
     int k = 0;
     while (k < maxit) {
       const int chunk = (maxit - k) < kAdjCheck ? (maxit - k) : kAdjCheck;
       for (int i = 0; i < chunk; ++i, ++k) {
-        fm_status e = adj_enqueue_iteration<T>(p, q, np, k, s);
+        fm_status e = adj_enqueue_iteration<T>(p, q, np, nv, k, s);
         if (e) return e;
       }
-      fm_status e = adj_finish(p, q, np, &st, s);
+      fm_status e = adj_finish(p, q, np, nv, &st, s);
       if (e) return e;
       if (st.cg_done) break;
     }
     if (maxit == 0) {
-      fm_status e = adj_finish(p, q, np, &st, s);
+      fm_status e = adj_finish(p, q, np, nv, &st, s);
       if (e) return e;
     }
-    hipLaunchKernelGGL((fm::k_adj_out<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, np),
+    hipLaunchKernelGGL((fm::k_adj_out<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, np, nv),
                        (const float2 *)sens, p->prm.ncoil, (float2 *)dldy, vout);
     FM_LAUNCH_CHECK();
     np = p->sgrid;
-    fm_status e = adj_finish(p, q, np, &st, s);
+    nv = 1;
+    fm_status e = adj_finish(p, q, np, nv, &st, s);
     if (e) return e;
     *out = st;
     return FM_OK;
@@ -813,6 +837,7 @@ fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *m
     a.sens = (const float2 *)sens;
     a.mask = mask;
     a.dat = (fm::T2<T> *)p->dat;
+    a.estride = p->n;
     a.code = p->code;
     a.f0 = p->f0buf;
     a.inv_2pi_dt = 1.0 / (two_pi * (p->prm.te[1] - p->prm.te[0]));
@@ -878,7 +903,7 @@ fm_status fm_precondition(fm_plan *p, const double *curv, const double *g, doubl
     hipLaunchKernelGGL(fm::k_state_init, dim3(1), dim3(1), 0, s, p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls);
     FM_LAUNCH_CHECK();
     p->iter_host = 0;
-    p->last_nparts = 0;
+    set_parts(p, 0, 0);
     if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) {
       hipLaunchKernelGGL(fm::k_hinv<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, p->prm.beta,
                          (const uint8_t *)p->code, (const T *)p->D, p->hinv, p->status);
@@ -1032,3 +1057,6 @@ fm_status fm_mask_count(fm_plan *p, int64_t *count, hipStream_t s) {
 
 // Water-fat initialisation lives with the rest of the plan internals.
 #include "fm_waterfat.inc"
+
+// Batched solves of many volumes.
+#include "fm_batch.inc"

@@ -11,7 +11,7 @@ namespace fm {
 constexpr int kBlock = 256;      // threads per block of the streaming kernels
 constexpr int kWave = 64;        // CDNA wavefront
 #ifndef FM_MAXGRID
-#define FM_MAXGRID 512
+#define FM_MAXGRID 1024
 #endif
 constexpr int kMaxGrid = FM_MAXGRID;  // blocks (hence partial sums) of a streaming pass
 constexpr int kMaxK = 4;         // values reduced per kernel
@@ -214,36 +214,95 @@ __device__ __forceinline__ void block_sum(double (&v)[K]) {
   __syncthreads();
 }
 
-// Store this block's K partial sums (layout [block][kMaxK], unused slots 0).
+// Agent-coherent loads and stores (data exchanged between workgroups of one
+// kernel, possibly on different XCDs).
+template <typename T>
+__device__ __forceinline__ T ld_coh(const T *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_coh(T *p, T v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Store the K partial sums of unit idx (of count units; a unit is a
+// workgroup, or a tile of the wavefront sweep).  Layout: value k of unit u at
+// pout[k * count + u] (one row per value), so a consumer reads only the rows
+// that the producer wrote.
 template <int K, int NT = kBlock>
-__device__ __forceinline__ void store_partials(double (&v)[K], double *__restrict__ pout) {
+__device__ __forceinline__ void store_partials_at(double (&v)[K], int idx, int count, double *__restrict__ pout) {
   static_assert(K <= kMaxK, "too many reduced values");
   block_sum<K, NT>(v);
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) pout[(size_t)blockIdx.x * kMaxK + k] = (k < K) ? v[k] : 0.0;
+    for (int k = 0; k < K; ++k) pout[(size_t)k * count + idx] = v[k];
   }
 }
 
-// Sum the predecessor's partials; every thread gets the totals.
-template <int NT = kBlock>
-__device__ __forceinline__ void sum_partials(const double *__restrict__ pin, int nparts, double (&tot)[kMaxK]) {
+template <int K, int NT = kBlock>
+__device__ __forceinline__ void store_partials(double (&v)[K], double *__restrict__ pout) {
+  store_partials_at<K, NT>(v, (int)blockIdx.x, (int)gridDim.x, pout);
+}
+
+// Sum the first nvals rows of the predecessor's nparts partials; every thread
+// gets the totals.  KR (>= nvals) rows are loaded unconditionally (every row
+// index is inside the buffer) and masked afterwards, and the block loop is
+// unrolled over the usual partial count, so all loads are in flight at once.
+template <int KR, int NT = kBlock>
+__device__ __forceinline__ void sum_partials(const double *__restrict__ pin, int nparts, int nvals,
+                                             double (&tot)[kMaxK], int rowstride) {
+  static_assert(KR <= kMaxK, "too many reduced values");
+  constexpr int U = (kMaxGrid + NT - 1) / NT < 4 ? (kMaxGrid + NT - 1) / NT : 4;
+  double acc[KR];
 #pragma unroll
-  for (int k = 0; k < kMaxK; ++k) tot[k] = 0.0;
-  for (int b = threadIdx.x; b < nparts; b += NT) {
+  for (int k = 0; k < KR; ++k) acc[k] = 0.0;
+  for (int b0 = 0; b0 < nparts; b0 += U * NT) {
+    double x[U][KR];
 #pragma unroll
-    for (int k = 0; k < kMaxK; ++k) tot[k] += pin[(size_t)b * kMaxK + k];
+    for (int u = 0; u < U; ++u) {
+      const int b = b0 + u * NT + (int)threadIdx.x;
+      const int bb = b < nparts ? b : 0;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) x[u][k] = pin[(size_t)k * rowstride + bb];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = b0 + u * NT + (int)threadIdx.x < nparts;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) acc[k] += (ok && k < nvals) ? x[u][k] : 0.0;
+    }
   }
-  block_sum<kMaxK, NT>(tot);
+  block_sum<KR, NT>(acc);
+#pragma unroll
+  for (int k = 0; k < kMaxK; ++k) tot[k] = k < KR ? acc[k < KR ? k : 0] : 0.0;
 }
 
 __device__ __forceinline__ void set_status(int32_t *status, int code) { atomicCAS(status, 0, code); }
 
+// Line-search setup from A = z^T C^T C f, B = ||C z||^2 and d0 = sum z^2 D:
+// the first step from alpha = 0 is alpha = -z^T g / (d0 + beta B).
+__device__ __forceinline__ void start_line_search(State &s, double A, double B, double d0, double beta,
+                                                  double *trace, bool leader) {
+  const bool w = (leader && threadIdx.x == 0);
+  s.A = A;
+  s.B = B;
+  const double den = d0 + beta * B;
+  s.ls_left = s.nmls - 1;  // line-search passes still to consume
+  s.ls_done = 0;
+  if (den > 0.0) {
+    s.alpha = -s.ztg / den;
+  } else {
+    s.alpha = 0.0;
+    s.ls_done = 1;
+  }
+  if (w && s.iter < s.trace_cap) trace[(size_t)s.iter * 8 + 6] = B;
+}
+
 // Apply the incoming partial sums to the scalar state (identically in every
 // block).  trace (row-major [trace_cap+1][8]) is written by block 0 only.
 __device__ __forceinline__ void consume(State &s, const double (&t)[kMaxK], double beta, double *trace,
-                                        int32_t *status) {
-  const bool w = (blockIdx.x == 0 && threadIdx.x == 0);
+                                        int32_t *status, bool leader) {
+  const bool w = (leader && threadIdx.x == 0);
   switch (s.kind) {
     case PK_GRAD: {
       s.cost = t[0] + 0.5 * beta * t[1];
@@ -288,19 +347,7 @@ __device__ __forceinline__ void consume(State &s, const double (&t)[kMaxK], doub
       break;
     }
     case PK_DIR: {
-      // first line-search step from alpha = 0: alpha = -z^T g / (d0 + beta B)
-      s.A = t[0];
-      s.B = t[1];
-      const double den = t[2] + beta * t[1];
-      s.ls_left = s.nmls - 1;  // line-search passes still to consume
-      s.ls_done = 0;
-      if (den > 0.0) {
-        s.alpha = -s.ztg / den;
-      } else {
-        s.alpha = 0.0;
-        s.ls_done = 1;
-      }
-      if (w && s.iter < s.trace_cap) trace[(size_t)s.iter * 8 + 6] = t[1];
+      start_line_search(s, t[0], t[1], t[2], beta, trace, leader);
       break;
     }
     case PK_MLS: {
@@ -375,22 +422,28 @@ __device__ __forceinline__ int iter_after(const State &s) {
 // (their count nparts_in is fixed by the launch sequence, so both loads are
 // issued together), then apply them.  Returns the updated state (identical in
 // every block).
-template <int NT = kBlock>
+// KR bounds the number of values the kernel may consume (nvals_in <= KR).
+// The partials of this consumer are pin[k * rowstride + b], b < nparts_in
+// (rowstride < 0: rowstride = nparts_in).  leader: the workgroup that writes
+// the trace and the outgoing state (the first one of its volume).
+template <int NT = kBlock, int KR = 4>
 __device__ __forceinline__ State take_state(const State *__restrict__ sin, const double *__restrict__ pin,
-                                            int nparts_in, double beta, double *trace, int32_t *status) {
+                                            int nparts_in, int nvals_in, double beta, double *trace,
+                                            int32_t *status, int rowstride = -1, bool leader = blockIdx.x == 0) {
   State s = *sin;
   double t[kMaxK];
-  sum_partials<NT>(pin, nparts_in, t);
+  sum_partials<KR, NT>(pin, nparts_in, nvals_in, t, rowstride < 0 ? nparts_in : rowstride);
   if (s.kind != PK_NONE) {
-    if (s.nparts != nparts_in && blockIdx.x == 0 && threadIdx.x == 0) set_status(status, 7);
-    consume(s, t, beta, trace, status);
+    if ((s.nparts != nparts_in || nvals_in > KR) && leader && threadIdx.x == 0) set_status(status, 7);
+    consume(s, t, beta, trace, status, leader);
   }
   return s;
 }
 
-// Epilogue: block 0 publishes the state with the kind of partials it leaves.
-__device__ __forceinline__ void put_state(State s, State *__restrict__ sout, int kind, int nparts) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+// Epilogue: the leader publishes the state with the kind of partials it leaves.
+__device__ __forceinline__ void put_state(State s, State *__restrict__ sout, int kind, int nparts,
+                                          bool leader = blockIdx.x == 0) {
+  if (leader && threadIdx.x == 0) {
     s.kind = kind;
     s.nparts = nparts;
     *sout = s;

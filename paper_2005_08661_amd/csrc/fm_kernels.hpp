@@ -36,7 +36,8 @@ struct SetupArgs {
   const float2 *y;     // [ncoil][L][n]
   const float2 *sens;  // [ncoil][n] or nullptr
   const uint8_t *mask;
-  T2<T> *dat;          // [L][n] (|zhat|, angle/2pi)
+  T2<T> *dat;          // [L][estride] (|zhat|, angle/2pi)
+  int64_t estride;     // echo stride of dat (n, or the batch's padded total)
   uint8_t *code;
   double *f0;          // field-map init output (double) or nullptr
   double inv_2pi_dt;   // 1 / (2 pi (t_2 - t_1))
@@ -47,7 +48,7 @@ struct SetupArgs {
   int32_t nsweep;      // water-fat sweep values (0 = no sweep)
   double sweep_half;   // |delta_f| / 2
   double *ftilde;      // water-fat sweep output or nullptr
-  double *partials;    // [gridDim.x][kMaxK] in-mask counts
+  double *partials;    // [kMaxK][gridDim.x] in-mask counts
 };
 
 template <typename T>
@@ -107,7 +108,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
       T2<T> d;
       d.x = (T)mag[l];
       d.y = (T)ph[l];
-      a.dat[(int64_t)l * g.n + j] = d;
+      a.dat[(int64_t)l * a.estride + j] = d;
     }
     if (a.ftilde) {
       // Sec. III-A water-fat start: the sweep value of least per-voxel cost
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
 // In-mask count from the setup partials (one block).
 __global__ __launch_bounds__(kBlock) void k_count(const double *__restrict__ partials, int nparts, double *nmask) {
   double t[kMaxK];
-  sum_partials(partials, nparts, t);
+  sum_partials<1>(partials, nparts, 1, t, nparts);
   if (threadIdx.x == 0) *nmask = t[0];
 }
 
@@ -206,6 +207,25 @@ __global__ void k_state_init(State *sout, int trace_cap, int nmls) { init_state(
 // f^i = f^{i-1} + alpha z^{i-1} of the previous iteration):
 //   g_j = dphi_j(f_j) + beta (C^T C f)_j,  D_j = Huber curvature (eq. (ls_huber)).
 // Grid totals: sum phi, f^T C^T C f, ||g||^2, z_prev^T g.
+// Batches: many volumes advance together, one launch per pass.  The
+// per-voxel arrays of all volumes are concatenated (each volume padded by its
+// own x-plane on both sides); the launch's workgroups are partitioned among
+// the volumes, and each volume keeps its own scalar state and partial sums.
+struct VolDesc {
+  Geo geo;
+  int64_t off;     // global index of the volume's voxel 0
+  int32_t b0, nb;  // its workgroups [b0, b0 + nb) of a streaming launch
+  double beta;
+};
+
+struct Batch {
+  const VolDesc *vol;        // [nvol]
+  const int32_t *blockvol;   // [grid] volume of each workgroup
+  int64_t estride;           // echo stride of the echo data (all padded voxels)
+  int64_t trace_stride;      // doubles per volume trace
+  double *const *fouts;      // final pass: output map of each volume
+};
+
 template <typename T>
 struct IterArgs {
   Geo geo;
@@ -225,7 +245,8 @@ struct IterArgs {
   int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0))
   int32_t store_piv;   // preconditioner passes also store every pivot
   int32_t par;         // parity of the iteration this launch belongs to
-  int32_t nparts_in;   // partial sums left by the previous launch
+  int32_t nparts_in;   // partial sums left by the previous launch (blocks)
+  int32_t nvals_in;    // values per block in them
   const State *sin;    // incoming scalar state
   State *sout;         // outgoing scalar state (block 0)
   const double *pin;   // incoming partial sums
@@ -234,7 +255,56 @@ struct IterArgs {
   double *trace;       // [trace_cap + 1][8]
   double *fout;        // final pass: user output (double) or nullptr
   int32_t final_pass;
+  Batch bt;            // batched launches only
 };
+
+// A workgroup's view of its volume: geometry, offset of the volume in the
+// concatenated arrays, position among the volume's workgroups, and where its
+// state and incoming partial sums are.
+struct VolView {
+  Geo g;
+  int off;
+  int vol;
+  int bl, nb;       // workgroup index within the volume, workgroups of the volume
+  int pfirst;       // first incoming partial of the volume
+  int pcount;       // incoming partials of the volume
+  int prow;         // row stride of the incoming partials
+  int64_t es;       // echo stride
+  double beta;
+  bool leader;
+};
+
+template <bool BATCH, typename A>
+__device__ __forceinline__ VolView vol_view(const A &a) {
+  VolView w;
+  if (!BATCH) {
+    w.g = a.geo;
+    w.off = 0;
+    w.vol = 0;
+    w.bl = (int)blockIdx.x;
+    w.nb = (int)gridDim.x;
+    w.pfirst = 0;
+    w.pcount = a.nparts_in;
+    w.prow = a.nparts_in;
+    w.es = a.geo.n;
+    w.beta = a.beta;
+  } else {
+    const int v = a.bt.blockvol[blockIdx.x];
+    const VolDesc d = a.bt.vol[v];
+    w.g = d.geo;
+    w.off = (int)d.off;
+    w.vol = v;
+    w.bl = (int)blockIdx.x - d.b0;
+    w.nb = d.nb;
+    w.pfirst = d.b0;
+    w.pcount = a.nparts_in ? d.nb : 0;  // the predecessor used the same partition
+    w.prow = (int)gridDim.x;
+    w.es = a.bt.estride;
+    w.beta = d.beta;
+  }
+  w.leader = (w.bl == 0);
+  return w;
+}
 
 template <typename T, int LMAX>
 __device__ __forceinline__ void load_echoes(const T2<T> *__restrict__ dat, int64_t n, int j, int L,
@@ -256,9 +326,20 @@ __device__ __forceinline__ void load_echoes(const T2<T> *__restrict__ dat, int64
 // End of a solve (one block): consume the final gradient pass (the cost of
 // the final map) and leave a state from which the iteration can continue.
 __global__ __launch_bounds__(kBlock) void k_finish(const State *sin, State *sout, const double *pin, int nparts_in,
-                                                    double beta, double *trace, int32_t *status) {
-  const State st = take_state(sin, pin, nparts_in, beta, trace, status);
+                                                    int nvals_in, double beta, double *trace, int32_t *status) {
+  const State st = take_state<kBlock, 4>(sin, pin, nparts_in, nvals_in, beta, trace, status);
   put_state(st, sout, PK_NONE, 0);
+}
+
+// End of a batched solve: workgroup v consumes volume v's partial sums.
+__global__ __launch_bounds__(kBlock) void k_finish_batch(Batch bt, const State *sin, State *sout, const double *pin,
+                                                          int nparts_in, int rowstride, int nvals_in, double *trace,
+                                                          int32_t *status) {
+  const int v = (int)blockIdx.x;
+  const VolDesc d = bt.vol[v];
+  const State st = take_state<kBlock, 4>(sin + v, pin + (nparts_in ? d.b0 : 0), nparts_in ? d.nb : 0, nvals_in,
+                                         d.beta, trace + (size_t)v * bt.trace_stride, status, rowstride, true);
+  put_state(st, sout + v, PK_NONE, 0, true);
 }
 
 // hinv_j = 1 / (D_j + beta deg_j) for the standalone preconditioner call.

@@ -76,21 +76,12 @@ __device__ __forceinline__ T shfl_up_t(T v, int d) {
   return __shfl_up(v, (unsigned)d, 64);
 }
 
-// Agent-coherent loads/stores of the values exchanged between tiles.
-template <typename T>
-__device__ __forceinline__ T ld_coh(const T *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ void st_coh(T *p, T v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc) {
   const Geo g = a.geo;
-  const State st = take_state<64>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<64, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
   const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const int ticket = take_ticket(w.ticket_fwd);
@@ -203,7 +194,7 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
 template <typename T>
 __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc) {
   const Geo g = a.geo;
-  const State st = take_state<64>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<64, 1>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
   const int it = a.par;
   const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
   const T *__restrict__ gp = a.G[(it + 1) & 1];
@@ -286,14 +277,7 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
     publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);
   }
   // per-tile partial sums, indexed by tile so the order is fixed
-  block_sum<2, 64>(acc);
-  if (threadIdx.x == 0) {
-    const int ti = tile.x * w.nty + tile.y;
-    a.pout[(size_t)ti * kMaxK + 0] = acc[0];
-    a.pout[(size_t)ti * kMaxK + 1] = acc[1];
-    a.pout[(size_t)ti * kMaxK + 2] = 0.0;
-    a.pout[(size_t)ti * kMaxK + 3] = 0.0;
-  }
+  store_partials_at<2, 64>(acc, tile.x * w.nty + tile.y, w.ntiles, a.pout);
   put_state(st, a.sout, PK_DOTS, w.ntiles);
 }
 

@@ -21,7 +21,7 @@ namespace fm {
 #endif
 
 #ifndef FM_NT
-#define FM_NT 512
+#define FM_NT 256
 #endif
 constexpr int kNT = FM_NT;  // threads per block of the streaming passes
 
@@ -48,23 +48,87 @@ struct Offs {
 
 __device__ __forceinline__ bool has_nb(uint32_t c, int k) { return (c >> (k + 1)) & 1u; }
 
+// Arguments as seen by one workgroup, with the ping-pong slots of the launch's
+// iteration parity resolved (c = current, p = previous; no array members, so
+// nothing is indexed at run time and everything stays in registers).  For a
+// batched launch every per-voxel pointer is moved to the workgroup's volume,
+// and the scalar state, incoming partial sums, trace, beta and geometry are
+// that volume's.
+template <typename T>
+struct VArgs {
+  Geo geo;
+  int32_t L;
+  double beta;
+  const T2<T> *dat;
+  const uint8_t *code;
+  const PairC<T> *pairs;
+  T *Fc, *Fp, *Zc, *Zp, *Gc, *Gp;
+  T *D, *P;
+  double *ipiv, *hinv;
+  int32_t write_hinv, store_piv, nparts_in, nvals_in, final_pass;
+  const State *sin;
+  State *sout;
+  const double *pin;
+  double *pout;
+  int32_t *status;
+  double *trace;
+  double *fout;
+};
+
+template <bool BATCH, typename T>
+__device__ __forceinline__ VArgs<T> at_volume(const IterArgs<T> &a0, const VolView &vw) {
+  VArgs<T> a;
+  const int o = BATCH ? vw.off : 0;
+  const bool odd = (a0.par & 1) != 0;
+  a.geo = vw.g;
+  a.L = a0.L;
+  a.beta = vw.beta;
+  a.dat = a0.dat + o;
+  a.code = a0.code + o;
+  a.pairs = a0.pairs;
+  a.Fc = (odd ? a0.F[1] : a0.F[0]) + o;
+  a.Fp = (odd ? a0.F[0] : a0.F[1]) + o;
+  a.Zc = (odd ? a0.Z[1] : a0.Z[0]) + o;
+  a.Zp = (odd ? a0.Z[0] : a0.Z[1]) + o;
+  a.Gc = (odd ? a0.G[1] : a0.G[0]) + o;
+  a.Gp = (odd ? a0.G[0] : a0.G[1]) + o;
+  a.D = a0.D + o;
+  a.P = a0.P + o;
+  a.ipiv = a0.ipiv + o;
+  a.hinv = a0.hinv + o;
+  a.write_hinv = a0.write_hinv;
+  a.store_piv = a0.store_piv;
+  a.nparts_in = vw.pcount;
+  a.nvals_in = a0.nvals_in;
+  a.final_pass = a0.final_pass;
+  a.sin = a0.sin + vw.vol;
+  a.sout = a0.sout + vw.vol;
+  a.pin = a0.pin + vw.pfirst;
+  a.pout = a0.pout;
+  a.status = a0.status;
+  a.trace = a0.trace + (BATCH ? (size_t)vw.vol * a0.bt.trace_stride : 0);
+  a.fout = BATCH ? (a0.bt.fouts ? a0.bt.fouts[vw.vol] : nullptr) : a0.fout;
+  return a;
+}
+
 // ---------------------------------------------------------------------------
 // Gradient pass of iteration i (Sec. III eq. (ls_grad)), fused with the update
 // f^i = f^{i-1} + alpha z^{i-1} of the previous iteration:
 //   g_j = dphi_j(f_j) + beta (C^T C f)_j,  D_j = Huber curvature (eq. (ls_huber)),
 // hinv_j = 1 / (D_j + beta deg_j) for the red-black preconditioner.
 // Partial sums: sum phi, f^T C^T C f, ||g||^2, z_prev^T g.
-template <typename T, int LMAX>
-__global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
+template <typename T, int LMAX, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a0) {
   constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const int it = a.par;
-  const T *__restrict__ fin = a.F[(it + 1) & 1];
-  const T *__restrict__ zp = a.Z[(it + 1) & 1];
-  T *__restrict__ fo = a.F[it & 1];
-  T *__restrict__ gg = a.G[it & 1];
+  const T *__restrict__ fin = a.Fp;
+  const T *__restrict__ zp = a.Zp;
+  T *__restrict__ fo = a.Fc;
+  T *__restrict__ gg = a.Gc;
   const Offs of(g);
-  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T f0[V], z0[V], fn[V][6], zn[V][6], rho[V][LMAX], tau[V][LMAX];
   auto load = [&](int b) {
@@ -80,12 +144,12 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
         fn[v][k] = fin[jj + of.o[k]];
         zn[v][k] = zp[jj + of.o[k]];
       }
-      load_echoes<T, LMAX>(a.dat, (int64_t)n, jj, a.L, rho[v], tau[v]);
+      load_echoes<T, LMAX>(a.dat, vw.es, jj, a.L, rho[v], tau[v]);
     }
   };
-  int base = (int)blockIdx.x * chunk;
+  int base = vw.bl * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<kNT, 3>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const T alpha = (T)st.alpha;
   const T beta = (T)a.beta;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -131,7 +195,7 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
     if (base + stride < n) load(base + stride);
   }
   store_partials<4, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_GRAD, gridDim.x);
+  put_state(st, a.sout, PK_GRAD, vw.nb, vw.leader);
 }
 
 // ---------------------------------------------------------------------------
@@ -143,16 +207,17 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a) {
 // and p_b = x_b (no later neighbour); then p_r = x_r + (beta / h_r) sum_k p_k.
 // 1/h is read from hinv (written once per voxel by the gradient pass).
 // Partial sums: g^T p and g_prev^T p over the colour of the pass.
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a, const T *__restrict__ gsrc) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a0, const T *__restrict__ gsrc) {
   constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const int it = a.par;
-  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
-  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const T *__restrict__ gg = gsrc ? gsrc + vw.off : a.Gc;
+  const T *__restrict__ gp = a.Gp;
   const double *__restrict__ hv = a.hinv;
   const Offs of(g);
-  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T d0[V], g0[V], gp0[V], gn[V][6];
   double hn[V][6];
@@ -172,9 +237,9 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a, const T *__rest
       }
     }
   };
-  int base = (int)blockIdx.x * chunk;
+  int base = vw.bl * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta, b2 = a.beta * a.beta;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
@@ -214,18 +279,19 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a, const T *__rest
   }
   if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_DOTS_A, gridDim.x);
+  put_state(st, a.sout, PK_DOTS_A, vw.nb, vw.leader);
 }
 
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a, const T *__restrict__ gsrc) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a0, const T *__restrict__ gsrc) {
   constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const int it = a.par;
-  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
-  const T *__restrict__ gp = a.G[(it + 1) & 1];
+  const T *__restrict__ gg = gsrc ? gsrc + vw.off : a.Gc;
+  const T *__restrict__ gp = a.Gp;
   const Offs of(g);
-  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T g0[V], gp0[V], pn[V][6];
   double h0[V];
@@ -242,9 +308,9 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a, const T *__restri
       for (int k = 0; k < 6; ++k) pn[v][k] = a.P[jj + of.o[k]];
     }
   };
-  int base = (int)blockIdx.x * chunk;
+  int base = vw.bl * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
   for (; base < n; base += stride) {
@@ -268,18 +334,19 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a, const T *__restri
     if (base + stride < n) load(base + stride);
   }
   store_partials<2, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_DOTS, gridDim.x);
+  put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
 }
 
 // Diagonal (P = diag H) or identity preconditioner.
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict__ gsrc, int identity) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a0, const T *__restrict__ gsrc, int identity) {
   constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const int it = a.par;
-  const T *__restrict__ gg = gsrc ? gsrc : a.G[it & 1];
-  const T *__restrict__ gp = a.G[(it + 1) & 1];
-  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  const T *__restrict__ gg = gsrc ? gsrc + vw.off : a.Gc;
+  const T *__restrict__ gp = a.Gp;
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T d0[V], g0[V], gp0[V];
   auto load = [&](int b) {
@@ -293,9 +360,9 @@ __global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict
       gp0[v] = gp[jj];
     }
   };
-  int base = (int)blockIdx.x * chunk;
+  int base = vw.bl * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
@@ -332,7 +399,7 @@ __global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict
   }
   if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_DOTS, gridDim.x);
+  put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,17 +408,18 @@ __global__ __launch_bounds__(kNT) void k_diag(IterArgs<T> a, const T *__restrict
 // z = -p + mu z_prev, A = z^T C^T C f, B = ||C z||^2 (once per outer
 // iteration) and d0 = sum z^2 D, from which the next kernel takes the first
 // step alpha = -z^T g / (d0 + beta B).
-template <typename T>
-__global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a) {
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a0) {
   constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const int it = a.par;
-  const T *__restrict__ zp = a.Z[(it + 1) & 1];
-  T *__restrict__ zo = a.Z[it & 1];
-  const T *__restrict__ f = a.F[it & 1];
+  const T *__restrict__ zp = a.Zp;
+  T *__restrict__ zo = a.Zc;
+  const T *__restrict__ f = a.Fc;
   const T *__restrict__ p = a.P;
   const Offs of(g);
-  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T p0[V], z0[V], f0[V], d0[V], pn[V][6], zn[V][6], fn[V][6];
   auto load = [&](int b) {
@@ -372,9 +440,9 @@ __global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a) {
       }
     }
   };
-  int base = (int)blockIdx.x * chunk;
+  int base = vw.bl * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const T mu = (T)st.mu;
   double acc[3] = {0.0, 0.0, 0.0};
   for (; base < n; base += stride) {
@@ -403,20 +471,21 @@ __global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a) {
     if (base + stride < n) load(base + stride);
   }
   store_partials<3, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_DIR, gridDim.x);
+  put_state(st, a.sout, PK_DIR, vw.nb, vw.leader);
 }
 
 // One further line-search pass (Sec. III-C eq. (ls_update)) at the current
 // alpha: S1 = z^T grad Phi(f + alpha z), S2 = sum z^2 d(f + alpha z); the next
 // kernel applies alpha <- alpha - (S1 + beta A + alpha beta B) / (S2 + beta B).
-template <typename T, int LMAX>
-__global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a) {
+template <typename T, int LMAX, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a0) {
   constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const int it = a.par;
-  const T *__restrict__ f = a.F[it & 1];
-  const T *__restrict__ z = a.Z[it & 1];
-  const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
+  const T *__restrict__ f = a.Fc;
+  const T *__restrict__ z = a.Zc;
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T f0[V], z0[V], rho[V][LMAX], tau[V][LMAX];
   auto load = [&](int b) {
@@ -427,12 +496,12 @@ __global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a) {
       c[v] = j < n ? a.code[jj] : 0u;
       f0[v] = f[jj];
       z0[v] = z[jj];
-      load_echoes<T, LMAX>(a.dat, (int64_t)n, jj, a.L, rho[v], tau[v]);
+      load_echoes<T, LMAX>(a.dat, vw.es, jj, a.L, rho[v], tau[v]);
     }
   };
-  int base = (int)blockIdx.x * chunk;
+  int base = vw.bl * chunk;
   if (base < n) load(base);
-  const State st = take_state<kNT>(a.sin, a.pin, a.nparts_in, a.beta, a.trace, a.status);
+  const State st = take_state<kNT, 3>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const T alpha = (T)st.alpha;
   double acc[2] = {0.0, 0.0};
   for (; base < n; base += stride) {
@@ -448,7 +517,7 @@ __global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a) {
     if (base + stride < n) load(base + stride);
   }
   store_partials<2, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_MLS, gridDim.x);
+  put_state(st, a.sout, PK_MLS, vw.nb, vw.leader);
 }
 
 }  // namespace fm

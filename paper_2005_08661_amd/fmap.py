@@ -30,7 +30,8 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "device allocat
 
 EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval", "fm_precondition",
             "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
-            "fm_adjoint", "fm_set_beta", "fm_status_string", "fm_last_error"]
+            "fm_adjoint", "fm_set_beta", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
+            "fm_batch_get_trace", "fm_batch_set_grid", "fm_batch_autotune", "fm_status_string", "fm_last_error"]
 KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls"]
 
 
@@ -74,6 +75,13 @@ def lib():
         L.fm_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32, C.c_double,
                                  C.POINTER(C.c_int32), vp]
         L.fm_set_beta.argtypes = [vp, C.c_double]
+        L.fm_batch_create.argtypes = [C.c_int32, vp, C.POINTER(vp)]
+        L.fm_batch_destroy.argtypes = [vp]
+        L.fm_batch_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fm_batch_get_trace.argtypes = [vp, C.c_int32, vp, vp]
+        L.fm_batch_set_grid.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
+        L.fm_batch_autotune.argtypes = [vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double), vp]
         L.fm_status_string.restype = C.c_char_p
         L.fm_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -280,6 +288,106 @@ class Plan:
         v = C.c_int64(0)
         _check(lib().fm_mask_count(self._h, C.byref(v), _stream()))
         return v.value
+
+
+def _ptr_array(ts):
+    arr = (C.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+class Batch:
+    """Many field-map volumes solved together (fm_batch): one launch per pass for all."""
+
+    def __init__(self, params_list):
+        self.params = list(params_list)
+        self.nvol = len(self.params)
+        self.shapes = [(p.nx, p.ny, p.nz) for p in self.params]
+        arr = (Params * self.nvol)(*self.params)
+        h = C.c_void_p()
+        _check(lib().fm_batch_create(C.c_int32(self.nvol), C.cast(arr, C.c_void_p), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _inputs(self, ys, sens, masks):
+        import torch
+        if not (len(ys) == len(masks) == self.nvol) or (sens is not None and len(sens) != self.nvol):
+            raise ValueError("need one y, mask (and sens) per volume")
+        P0 = self.params[0]
+        yy, ss, mm = [], [], []
+        for v in range(self.nvol):
+            shp = self.shapes[v]
+            if tuple(ys[v].shape) != (P0.ncoil, P0.necho) + shp or not ys[v].is_cuda:
+                raise ValueError("y[%d] must be a device tensor of shape %s" % (v, (P0.ncoil, P0.necho) + shp))
+            if tuple(masks[v].shape) != shp:
+                raise ValueError("mask[%d] must have shape %s" % (v, shp))
+            yy.append(ys[v].to(torch.complex64).contiguous())
+            mm.append(masks[v].to(torch.uint8).contiguous())
+            if sens is None or sens[v] is None:
+                if P0.ncoil != 1:
+                    raise ValueError("sens is needed for more than one coil")
+                ss.append(None)
+            else:
+                if tuple(sens[v].shape) != (P0.ncoil,) + shp:
+                    raise ValueError("sens[%d] must have shape %s" % (v, (P0.ncoil,) + shp))
+                ss.append(sens[v].to(torch.complex64).contiguous())
+        self._keep = (yy, ss, mm)
+        return yy, ss, mm
+
+    def solve(self, ys, sens, masks, f0=None):
+        import torch
+        yy, ss, mm = self._inputs(ys, sens, masks)
+        outs = [torch.zeros(shp, dtype=torch.float64, device=mm[0].device) for shp in self.shapes]
+        f0s = None
+        if f0 is not None:
+            f0s = [None if f is None else self._vec(f, v) for v, f in enumerate(f0)]
+        _check(lib().fm_batch_solve(self._h, _ptr_array(yy), _ptr_array(ss) if ss[0] is not None else None,
+                                    _ptr_array(mm), _ptr_array(f0s) if f0s is not None else None,
+                                    _ptr_array(outs), _stream()))
+        return outs
+
+    def _vec(self, t, v):
+        import torch
+        if tuple(t.shape) != self.shapes[v] or not t.is_cuda:
+            raise ValueError("f0[%d] must be a device tensor of shape %s" % (v, self.shapes[v]))
+        return t.to(torch.float64).contiguous()
+
+    def trace(self, v):
+        tr = np.zeros((self.params[0].niter + 1, TRACE_W))
+        _check(lib().fm_batch_get_trace(self._h, C.c_int32(int(v)), C.c_void_p(tr.ctypes.data), _stream()))
+        return tr
+
+    def set_grid(self, grid):
+        used = C.c_int32(0)
+        _check(lib().fm_batch_set_grid(self._h, C.c_int32(int(grid)), C.byref(used)))
+        return used.value
+
+    def autotune(self, ys, sens, masks, probe_iters=5):
+        """Time the candidate workgroup counts on these inputs; returns (grid, ms per iteration)."""
+        yy, ss, mm = self._inputs(ys, sens, masks)
+        g = C.c_int32(0)
+        ms = C.c_double(0.0)
+        _check(lib().fm_batch_autotune(self._h, _ptr_array(yy), _ptr_array(ss) if ss[0] is not None else None,
+                                       _ptr_array(mm), C.c_int32(int(probe_iters)), C.byref(g), C.byref(ms),
+                                       _stream()))
+        return g.value, ms.value
 
 
 def to_device(vol, device="cuda"):
