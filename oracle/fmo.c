@@ -767,3 +767,96 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
   pairs_free(&pr);
   return st;
 }
+
+int fmo_components(const fmo_problem *pb, int32_t ncoil, const double *y, const double *s,
+                   const uint8_t *mask, const double *f, int32_t K, int32_t npeak, const double *fat_hz,
+                   const double *fat_amp, double *out) {
+  if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 1 || pb->necho < 1 || !pb->te || ncoil < 1 || !y ||
+      (!s && ncoil != 1) || !mask || !f || !out || (K != 1 && K != 2))
+    return FMO_ERR_ARG;
+  if (K == 2 && (npeak < 1 || !fat_hz || !fat_amp)) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  const int L = pb->necho;
+  const int M = L * ncoil;
+  /* gamma [L][K] */
+  double *gre = (double *)calloc((size_t)L * K, sizeof(double));
+  double *gim = (double *)calloc((size_t)L * K, sizeof(double));
+  double *are = (double *)malloc(sizeof(double) * (size_t)M * K);
+  double *aim = (double *)malloc(sizeof(double) * (size_t)M * K);
+  if (!gre || !gim || !are || !aim) return FMO_ERR_ARG;
+  for (int l = 0; l < L; ++l) {
+    gre[l * K] = 1.0;
+    if (K == 2)
+      for (int p = 0; p < npeak; ++p) {
+        gre[l * K + 1] += fat_amp[p] * cos(TWO_PI * fat_hz[p] * pb->te[l]);
+        gim[l * K + 1] += fat_amp[p] * sin(TWO_PI * fat_hz[p] * pb->te[l]);
+      }
+  }
+  for (int64_t j = 0; j < n; ++j) {
+    double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
+    if (mask[j]) {
+      /* A[(l, c)][k] = e^{i 2 pi f t_l} gamma_lk s_cj */
+      for (int l = 0; l < L; ++l) {
+        const double ph = TWO_PI * f[j] * pb->te[l];
+        const double er = cos(ph), ei = sin(ph);
+        for (int c = 0; c < ncoil; ++c) {
+          const double sr = s ? s[2 * ((int64_t)c * n + j)] : 1.0;
+          const double si = s ? s[2 * ((int64_t)c * n + j) + 1] : 0.0;
+          for (int k = 0; k < K; ++k) {
+            const double ur = er * gre[l * K + k] - ei * gim[l * K + k];
+            const double ui = er * gim[l * K + k] + ei * gre[l * K + k];
+            are[(l * ncoil + c) * K + k] = ur * sr - ui * si;
+            aim[(l * ncoil + c) * K + k] = ur * si + ui * sr;
+          }
+        }
+      }
+      /* normal equations N = A^H A, b = A^H y */
+      double nr[2][2] = {{0, 0}, {0, 0}}, ni[2][2] = {{0, 0}, {0, 0}}, br[2] = {0, 0}, bi[2] = {0, 0};
+      for (int r = 0; r < M; ++r) {
+        const int l = r / ncoil, c = r % ncoil;
+        const double yr = y[2 * (((int64_t)c * L + l) * n + j)], yi = y[2 * (((int64_t)c * L + l) * n + j) + 1];
+        for (int a = 0; a < K; ++a) {
+          const double ar = are[r * K + a], ai = aim[r * K + a];
+          br[a] += ar * yr + ai * yi;
+          bi[a] += ar * yi - ai * yr;
+          for (int b = 0; b < K; ++b) {
+            const double cr = are[r * K + b], ci = aim[r * K + b];
+            nr[a][b] += ar * cr + ai * ci;
+            ni[a][b] += ar * ci - ai * cr;
+          }
+        }
+      }
+      if (K == 1) {
+        if (nr[0][0] > 0.0) {
+          xr[0] = br[0] / nr[0][0];
+          xi[0] = bi[0] / nr[0][0];
+        }
+      } else {
+        /* 2x2 complex inverse: N^{-1} = adj(N) / det(N) */
+        const double dr = nr[0][0] * nr[1][1] - ni[0][0] * ni[1][1] - (nr[0][1] * nr[1][0] - ni[0][1] * ni[1][0]);
+        const double di = nr[0][0] * ni[1][1] + ni[0][0] * nr[1][1] - (nr[0][1] * ni[1][0] + ni[0][1] * nr[1][0]);
+        const double dd = dr * dr + di * di;
+        if (dd > 0.0) {
+          /* y0 = N11 b0 - N01 b1, y1 = -N10 b0 + N00 b1; x = y / det */
+          const double y0r = nr[1][1] * br[0] - ni[1][1] * bi[0] - (nr[0][1] * br[1] - ni[0][1] * bi[1]);
+          const double y0i = nr[1][1] * bi[0] + ni[1][1] * br[0] - (nr[0][1] * bi[1] + ni[0][1] * br[1]);
+          const double y1r = -(nr[1][0] * br[0] - ni[1][0] * bi[0]) + nr[0][0] * br[1] - ni[0][0] * bi[1];
+          const double y1i = -(nr[1][0] * bi[0] + ni[1][0] * br[0]) + nr[0][0] * bi[1] + ni[0][0] * br[1];
+          xr[0] = (y0r * dr + y0i * di) / dd;
+          xi[0] = (y0i * dr - y0r * di) / dd;
+          xr[1] = (y1r * dr + y1i * di) / dd;
+          xi[1] = (y1i * dr - y1r * di) / dd;
+        }
+      }
+    }
+    for (int k = 0; k < K; ++k) {
+      out[2 * ((int64_t)k * n + j)] = xr[k];
+      out[2 * ((int64_t)k * n + j) + 1] = xi[k];
+    }
+  }
+  free(gre);
+  free(gim);
+  free(are);
+  free(aim);
+  return FMO_OK;
+}

@@ -140,6 +140,18 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
                 const double *dldf, int32_t maxit, double rtol, double *v, double *dldbeta,
                 double *dzhat, int32_t *iters);
 
+/* Component images at a field map f (Sec. II-III, eq. (wf)): for every voxel
+ * the least-squares solution x = A^+ y_j of A x = y_j with
+ * A = (diag(e^{i 2 pi f_j t}) gamma) (x) s_j  (L*ncoil x K; reading R15 of the
+ * dimensions), y_j stacked echo-major, gamma = 1 (K = 1, magnetisation m) or
+ * [1, c] (K = 2, water and fat), c_l = sum_p amp_p e^{i 2 pi hz_p t_l}.  The
+ * normal equations A^H A x = A^H y are formed and solved explicitly; x = 0
+ * where A = 0 (no coil sensitivity) and outside the mask.
+ *   y [ncoil][L][n], s [ncoil][n] or NULL (ncoil == 1), out [K][n] complex. */
+int fmo_components(const fmo_problem *pb, int32_t ncoil, const double *y, const double *s,
+                   const uint8_t *mask, const double *f, int32_t K, int32_t npeak, const double *fat_hz,
+                   const double *fat_amp, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -222,6 +222,22 @@ def zhat_to_y_grad(dzhat, sens, ncoil):
     return np.stack([np.stack([s[c] * scale * dzhat[l] for l in range(L)]) for c in range(ncoil)])
 
 
+def components(pb, y, sens, mask, f, fat_hz=None, fat_amp=None):
+    """Eq. (wf) images at map f: [1, ...] magnetisation (field map) or [2, ...] water, fat."""
+    y = _c128(y)
+    ncoil = y.shape[0]
+    s = None if sens is None else _c128(sens)
+    mask, f = _u8(mask), _f64(f)
+    K = 1 if fat_hz is None else 2
+    fh = _f64(fat_hz if fat_hz is not None else [0.0])
+    fa = _f64(fat_amp if fat_amp is not None else [0.0])
+    out = np.zeros((K,) + pb.shape, np.complex128)
+    c = pb.c()
+    _check(lib().fmo_components(C.byref(c), C.c_int32(ncoil), _p(y), _p(s), _p(mask), _p(f), C.c_int32(K),
+                                C.c_int32(len(fh)), _p(fh), _p(fa), _p(out)))
+    return out
+
+
 # --- whole pipeline for a synthetic volume --------------------------------------
 
 def problem_for(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, beta=None):

@@ -84,3 +84,67 @@ def test_waterfat_pipeline_monotone_and_accurate_on_small_volume():
     c = out["trace"][:, O.TR["cost"]]
     assert np.all(np.diff(c) <= 1e-13 * abs(c[0]))
     assert np.isfinite(out["f"]).all()
+
+
+# --- eq. (wf): component images at the estimated map -------------------------
+
+def _pb(shape, te):
+    return O.Problem(shape, te, O.gamma_fieldmap(len(te)), 0.0)
+
+
+def test_components_recover_noise_free_water_and_fat():
+    """y = e^{i 2 pi f t} s (w + f c_l) exactly: eq. (wf) returns w and f at the true map."""
+    rng = np.random.default_rng(40)
+    ncoil, shape = 3, (3, 4, 2)
+    te = 1.2e-3 + 1.0e-3 * np.arange(6)
+    fat_hz = synth.FAT_PPM * synth.GAMMA_MHZ_PER_T * 3.0
+    cl = np.array([np.sum(synth.FAT_AMP * np.exp(2j * np.pi * fat_hz * t)) for t in te])
+    w, fa = _rand_c(rng, *shape), _rand_c(rng, *shape)
+    fmap = rng.uniform(-200, 200, shape)
+    s = _rand_c(rng, ncoil, *shape)
+    y = np.stack([np.stack([s[c] * (w + fa * cl[l]) * np.exp(2j * np.pi * fmap * te[l]) for l in range(6)])
+                  for c in range(ncoil)])
+    mask = np.ones(shape, np.uint8)
+    out = O.components(_pb(shape, te), y, s, mask, fmap, fat_hz, synth.FAT_AMP)
+    np.testing.assert_allclose(out[0], w, atol=1e-11)
+    np.testing.assert_allclose(out[1], fa, atol=1e-11)
+
+
+def test_components_equal_lstsq_of_the_kronecker_system():
+    """Noisy voxel: the oracle's normal equations agree with numpy lstsq on A = (diag(e^{iwt}) gamma) (x) s."""
+    rng = np.random.default_rng(41)
+    ncoil, L = 4, 5
+    te = 1e-3 * np.array([1.0, 2.1, 3.0, 4.2, 5.0])
+    fat_hz = synth.FAT_PPM * synth.GAMMA_MHZ_PER_T * 3.0
+    cl = np.array([np.sum(synth.FAT_AMP * np.exp(2j * np.pi * fat_hz * t)) for t in te])
+    gamma = np.stack([np.ones(L), cl], axis=1)
+    shape = (1, 1, 3)
+    y = _rand_c(rng, ncoil, L, *shape)
+    s = _rand_c(rng, ncoil, *shape)
+    fmap = rng.uniform(-300, 300, shape)
+    mask = np.ones(shape, np.uint8)
+    out = O.components(_pb(shape, te), y, s, mask, fmap, fat_hz, synth.FAT_AMP)
+    for j in range(3):
+        A = np.kron(np.diag(np.exp(2j * np.pi * fmap.flat[j] * te)) @ gamma, s[:, 0, 0, j].reshape(-1, 1))
+        yj = np.array([y[c, l, 0, 0, j] for l in range(L) for c in range(ncoil)])
+        ref = np.linalg.lstsq(A, yj, rcond=None)[0]
+        np.testing.assert_allclose(out[:, 0, 0, j], ref, rtol=1e-11, atol=1e-12)
+    # field-map case (gamma = 1): the phase-corrected, coil-combined echo average
+    out1 = O.components(_pb(shape, te), y, s, mask, fmap)
+    S = (np.abs(s) ** 2).sum(0)
+    ref1 = sum(np.conj(s[c]) * np.exp(-2j * np.pi * fmap * te[l]) * y[c, l] for c in range(ncoil)
+               for l in range(L)) / (L * S)
+    np.testing.assert_allclose(out1[0], ref1, rtol=1e-12)
+
+
+def test_components_zero_where_undefined():
+    rng = np.random.default_rng(42)
+    shape, te = (2, 2, 2), [0.0, 1e-3, 2e-3]
+    y = _rand_c(rng, 2, 3, *shape)
+    s = _rand_c(rng, 2, *shape)
+    s[:, 0, 0, 0] = 0.0
+    mask = np.ones(shape, np.uint8)
+    mask[1, 1, 1] = 0
+    out = O.components(_pb(shape, te), y, s, mask, np.zeros(shape), [-434.0], [1.0])
+    assert np.all(out[:, 0, 0, 0] == 0) and np.all(out[:, 1, 1, 1] == 0)
+    assert np.all(out[:, 0, 1, 0] != 0)
