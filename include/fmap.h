@@ -164,6 +164,19 @@ fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
  * synchronising the stream. */
 fm_status fm_mask_count(fm_plan *plan, int64_t *count, hipStream_t stream);
 
+/* Component images at a field map, eq. (wf): for every voxel the least-squares
+ * fit x = A^+ y_j with A = (diag(e^{i 2 pi f_j t}) gamma) (x) s_j, i.e. the
+ * magnetisation m (field-map model, K = 1) or the water and fat images
+ * (water-fat model, K = 2; gamma = [1, c], c_l the fat spectrum at t_l).
+ *   y, sens as for fm_setup (the data of the map)
+ *   f       dev float64 [N] map in Hz, or NULL for the map of the last
+ *           fm_solve / fm_iterate
+ *   m_out   dev complex64 [K][nx][ny][nz]; 0 outside the mask and where
+ *           sum_c |s_c|^2 = 0
+ * Computed in FP64 in both precision modes.  Needs fm_setup (or fm_solve). */
+fm_status fm_components(fm_plan *plan, const void *y, const void *sens, const double *f, void *m_out,
+                        hipStream_t stream);
+
 /* Implicit adjoint of the map left by the last fm_solve / fm_iterate (not part
  * of the paper: it differentiates the minimiser of Sec. II eq. (cost), whose
  * gradient vanishes there).  With H = diag(h) + beta C^T C the exact Hessian

@@ -78,6 +78,8 @@ struct fm_plan {
   double *trace = nullptr;
   void *pairs = nullptr;
   void *pairs_d = nullptr;
+  double *comp_tab = nullptr;  // eq. (wf): te [L], then B = (gamma^H gamma)^{-1} gamma^H [K][L] complex
+  int ncomp = 1;
   double *gabs = nullptr;
   double *rho = nullptr;
   double *f0buf = nullptr;
@@ -136,6 +138,45 @@ std::vector<std::complex<double>> make_gamma(const fm_params &p) {
     for (int n = 0; n < L; ++n)
       G[(size_t)m * L + n] = i00 + i01 * std::conj(c[n]) + c[m] * i10 + c[m] * i11 * std::conj(c[n]);
   return G;
+}
+
+// B = (gamma^H gamma)^{-1} gamma^H (K x L, row-major, interleaved complex):
+// gamma = 1 (field map, K = 1) or [1, c] (water-fat, K = 2).
+std::vector<double> make_component_matrix(const fm_params &p, int *K) {
+  const int L = p.necho;
+  const double two_pi = 6.283185307179586476925286766559;
+  std::vector<double> out;
+  if (p.model == FM_FIELDMAP) {
+    *K = 1;
+    for (int l = 0; l < L; ++l) {
+      out.push_back(1.0 / L);
+      out.push_back(0.0);
+    }
+    return out;
+  }
+  *K = 2;
+  std::vector<std::complex<double>> c(L);
+  for (int l = 0; l < L; ++l) {
+    std::complex<double> v = 0.0;
+    for (int q = 0; q < p.npeak; ++q) v += p.fat_amp[q] * std::polar(1.0, two_pi * p.fat_hz[q] * p.te[l]);
+    c[l] = v;
+  }
+  std::complex<double> sc = 0.0;
+  double cc = 0.0;
+  for (int l = 0; l < L; ++l) {
+    sc += c[l];
+    cc += std::norm(c[l]);
+  }
+  const double det = L * cc - std::norm(sc);
+  // N^{-1} = [[cc, -sc], [-conj(sc), L]] / det;  B = N^{-1} [1 ... 1; conj(c)]
+  const std::complex<double> i00 = cc / det, i01 = -sc / det, i10 = -std::conj(sc) / det, i11 = (double)L / det;
+  for (int k = 0; k < 2; ++k)
+    for (int l = 0; l < L; ++l) {
+      const std::complex<double> v = (k == 0) ? i00 + i01 * std::conj(c[l]) : i10 + i11 * std::conj(c[l]);
+      out.push_back(v.real());
+      out.push_back(v.imag());
+    }
+  return out;
 }
 
 template <typename T>
@@ -803,6 +844,16 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   if (st) return cleanup(st);
   st = upload_pairs<double>(p, G, &p->pairs_d);
   if (st) return cleanup(st);
+  {
+    int K = 1;
+    std::vector<double> tab(prm->te, prm->te + prm->necho);
+    const auto Bm = make_component_matrix(*prm, &K);
+    tab.insert(tab.end(), Bm.begin(), Bm.end());
+    p->ncomp = K;
+    if (!plan_alloc(p, (void **)&p->comp_tab, sizeof(double) * tab.size()) ||
+        hipMemcpy(p->comp_tab, tab.data(), sizeof(double) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
+      return cleanup(fail(FM_ERR_ALLOC, "upload of the component matrix failed"));
+  }
   if (p->gabs) {
     std::vector<double> ga((size_t)L * L);
     for (size_t i = 0; i < ga.size(); ++i) ga[i] = std::abs(G[i]);
@@ -1025,6 +1076,29 @@ fm_status fm_set_beta(fm_plan *p, double beta) {
   p->graphs.clear();
   p->prm.beta = beta;
   p->solved = false;
+  return FM_OK;
+}
+
+fm_status fm_components(fm_plan *p, const void *y, const void *sens, const double *f, void *m_out,
+                        hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!y || !m_out) return fail(FM_ERR_ARG, "y and m_out must not be NULL");
+  if (!sens && p->prm.ncoil != 1) return fail(FM_ERR_ARG, "sens may be NULL only when ncoil == 1");
+  if (!p->setup_done) return fail(FM_ERR_STATE, "fm_components needs fm_setup or fm_solve first");
+  if (!f && !p->solved) return fail(FM_ERR_STATE, "f is NULL and there is no solved map");
+  const double *te = p->comp_tab;
+  const double2 *B = (const double2 *)(p->comp_tab + p->prm.necho);
+  if (p->mix) {
+    hipLaunchKernelGGL(fm::k_components<float>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, p->prm.ncoil,
+                       p->prm.necho, p->ncomp, (const float2 *)y, (const float2 *)sens, (const uint8_t *)p->code, f,
+                       (const float *)p->F[p->iter_host & 1], te, B, (float2 *)m_out);
+  } else {
+    hipLaunchKernelGGL(fm::k_components<double>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, p->prm.ncoil,
+                       p->prm.necho, p->ncomp, (const float2 *)y, (const float2 *)sens, (const uint8_t *)p->code, f,
+                       (const double *)p->F[p->iter_host & 1], te, B, (float2 *)m_out);
+  }
+  FM_LAUNCH_CHECK();
   return FM_OK;
 }
 

@@ -394,6 +394,69 @@ __global__ __launch_bounds__(kBlock) void k_eval(IterArgs<T> a, const double *__
   }
 }
 
+// Component images at a field map (eq. (wf)): with A = (diag(e^{i 2 pi f t})
+// gamma) (x) s_j, A^H A = (gamma^H gamma) sum_c |s_c|^2 and A^H y = gamma^H
+// diag(e^{-i 2 pi f t}) z, z_l = sum_c conj(s_c) y_cl, so
+//   x = B diag(e^{-i 2 pi f t}) z / sum_c |s_c|^2,  B = (gamma^H gamma)^{-1} gamma^H
+// (K x L, from the host).  FP64 in every precision mode; 0 outside the mask or
+// where the coil maps vanish.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_components(Geo g, int ncoil, int L, int K, const float2 *__restrict__ y,
+                                                        const float2 *__restrict__ sens,
+                                                        const uint8_t *__restrict__ code, const double *__restrict__ fu,
+                                                        const T *__restrict__ fw, const double *__restrict__ te,
+                                                        const double2 *__restrict__ B, float2 *__restrict__ out) {
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
+    double xr[2] = {0.0, 0.0}, xi[2] = {0.0, 0.0};
+    if (code[j] & NB_SELF) {
+      double ss = 1.0;
+      if (sens) {
+        ss = 0.0;
+        for (int c = 0; c < ncoil; ++c) {
+          const float2 sv = sens[(int64_t)c * g.n + j];
+          ss += (double)sv.x * sv.x + (double)sv.y * sv.y;
+        }
+      }
+      if (ss > 0.0) {
+        const double fj = fu ? fu[j] : (double)fw[j];
+        for (int l = 0; l < L; ++l) {
+          double zr = 0.0, zi = 0.0;
+          for (int c = 0; c < ncoil; ++c) {
+            const float2 yv = y[((int64_t)c * L + l) * g.n + j];
+            if (sens) {
+              const float2 sv = sens[(int64_t)c * g.n + j];
+              zr += (double)sv.x * yv.x + (double)sv.y * yv.y;
+              zi += (double)sv.x * yv.y - (double)sv.y * yv.x;
+            } else {
+              zr += yv.x;
+              zi += yv.y;
+            }
+          }
+          // e^{-i 2 pi f t_l} z_l
+          double sn, cs;
+          sincospi(2.0 * fj * te[l], &sn, &cs);
+          const double wr = cs * zr + sn * zi, wi = cs * zi - sn * zr;
+          for (int k = 0; k < K; ++k) {
+            const double2 b = B[k * L + l];
+            xr[k] += b.x * wr - b.y * wi;
+            xi[k] += b.x * wi + b.y * wr;
+          }
+        }
+        for (int k = 0; k < K; ++k) {
+          xr[k] /= ss;
+          xi[k] /= ss;
+        }
+      }
+    }
+    for (int k = 0; k < K; ++k) {
+      float2 o;
+      o.x = (float)xr[k];
+      o.y = (float)xi[k];
+      out[(int64_t)k * g.n + j] = o;
+    }
+  }
+}
+
 // Conversions between user float64 arrays and the working type.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_to_work(int64_t n, const double *__restrict__ src, T *dst) {

@@ -30,7 +30,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "device allocat
 
 EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval", "fm_precondition",
             "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
-            "fm_adjoint", "fm_set_beta", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
+            "fm_adjoint", "fm_set_beta", "fm_components", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
             "fm_batch_get_trace", "fm_batch_set_grid", "fm_batch_autotune", "fm_status_string", "fm_last_error"]
 KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls"]
 
@@ -75,6 +75,7 @@ def lib():
         L.fm_adjoint.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32, C.c_double,
                                  C.POINTER(C.c_int32), vp]
         L.fm_set_beta.argtypes = [vp, C.c_double]
+        L.fm_components.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fm_batch_create.argtypes = [C.c_int32, vp, C.POINTER(vp)]
         L.fm_batch_destroy.argtypes = [vp]
         L.fm_batch_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -279,6 +280,16 @@ class Plan:
         _check(lib().fm_adjoint(self._h, _ptr(g), _ptr(self._s), _ptr(dy), _ptr(v), C.byref(db),
                                 C.c_int32(int(maxit)), C.c_double(float(rtol)), C.byref(its), _stream()))
         return dict(dbeta=db.value, dy=dy, v=v, iters=its.value)
+
+    def components(self, f=None):
+        """Eq. (wf) images at map f (default: the last solved map) from the data of the last
+        setup/solve: complex64 [K, X, Y, Z], K = 1 (magnetisation) or 2 (water, fat)."""
+        import torch
+        K = 2 if self.params.model == WATERFAT else 1
+        fc = None if f is None else self._vec(f)
+        out = torch.zeros((K,) + self.shape, dtype=torch.complex64, device=self._y.device)
+        _check(lib().fm_components(self._h, _ptr(self._y), _ptr(self._s), _ptr(fc), _ptr(out), _stream()))
+        return out
 
     def set_beta(self, beta):
         _check(lib().fm_set_beta(self._h, C.c_double(float(beta))))

@@ -229,6 +229,52 @@ def test_waterfat_small_volume_matches_oracle(prec):
     assert err < (1e-3 if prec == "f64" else 0.05)
 
 
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("model", ["waterfat", "fieldmap"])
+def test_components_match_oracle(model, prec):
+    """Eq. (wf) images at the GPU's map (and at a given map) against the oracle's normal equations."""
+    if model == "waterfat":
+        vol = synth.waterfat_volume((24, 20, 8), 3, 1.2e-3 + 1e-3 * np.arange(6), 2.0 ** -4, 20,
+                                    synth.SEED_BASE + 77, 150.0, 40.0, name="water-fat 24x20x8")
+    else:
+        vol = ragged_volume()
+    say("components %s %s" % (model, prec))
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec])) as plan:
+        f = plan.solve(y, s, m)
+        got = plan.components().cpu().numpy()
+        rng = np.random.default_rng(3)
+        fg = (f.cpu().numpy() + rng.normal(0, 5.0, vol.shape)) * vol.mask
+        got2 = plan.components(torch.from_numpy(fg).cuda()).cpu().numpy()
+        gtrue = plan.components(torch.from_numpy(vol.f_true * vol.mask).cuda()).cpu().numpy()
+        fn = f.cpu().numpy()
+    pb = O.problem_for(vol)
+    wf = (vol.fat_hz, vol.fat_amp) if model == "waterfat" else (None, None)
+    ref = O.components(pb, vol.y, vol.sens, vol.mask, fn, *wf)
+    ref2 = O.components(pb, vol.y, vol.sens, vol.mask, fg, *wf)
+    scale = np.abs(ref).max()
+    # complex64 output; the map itself is FP32 in MIX (its rounding moves the phase by 2 pi f t eps)
+    tol = 2e-6 * scale if prec == "f64" else 5e-5 * scale
+    assert np.abs(got - ref).max() < tol
+    assert np.abs(got2 - ref2).max() < 2e-6 * scale
+    assert got.shape[0] == (2 if model == "waterfat" else 1)
+    assert np.all(got[:, vol.mask == 0] == 0)
+    if model == "waterfat":
+        # quality: fat fraction of the estimate against the generator's truth inside the object
+        # (noise-limited at the true map; reported, loosely bounded, at the 20-iteration estimate)
+        inside = (np.abs(vol.water) + np.abs(vol.fat)) > 0.5
+        ff_true = np.abs(vol.fat) / (np.abs(vol.water) + np.abs(vol.fat))
+
+        def ff_err(x):
+            ff = np.abs(x[1]) / np.maximum(np.abs(x[0]) + np.abs(x[1]), 1e-12)
+            return float(np.sqrt(np.mean((ff - ff_true)[inside] ** 2)))
+
+        e_true, e_est = ff_err(gtrue), ff_err(got)
+        say("  fat fraction RMS error: %.4f at the true map, %.4f at the estimate" % (e_true, e_est))
+        assert e_true < 0.03
+        assert e_est < 0.2
+
+
 @pytest.mark.parametrize("ordering", ["natural", "redblack"])
 def test_full_size_mid_volume_few_iterations(ordering):
     """128x128x64, 8 coils at the benchmark's launch configuration, 4
