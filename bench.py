@@ -146,6 +146,47 @@ def bench_batched(args, fmap, synth, torch, prec):
     return res
 
 
+def bench_waterfat(args, fmap, synth, torch):
+    """192x192x64, 8 coils, 6 echoes, six-peak fat: full solve (setup, sweep + PWLS start, 100
+    iterations) in MIX, the iteration loop alone, and the MIX map against an F64 solve."""
+    log("water-fat: generating 192x192x64, 8 coils, 6 echoes")
+    vol = synth.waterfat()
+    y, s, m = fmap.to_device(vol)
+    nmask = int(vol.mask.sum())
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = torch.zeros(vol.shape, dtype=torch.float64, device="cuda")
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.MIX, ordering=fmap.REDBLACK)) as plan:
+        plan.solve(y, s, m, out=out)
+        torch.cuda.synchronize()
+        ms_solve = time_solve(plan, fmap, y, s, m, out, args.steps, torch)
+        ev0.record(stream)
+        plan.setup(y, s, m)
+        plan.init()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_init = ev0.elapsed_time(ev1)
+        plan.solve(y, s, m, out=out)
+        ev0.record(stream)
+        plan.iterate(vol.niter, out=out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_loop = ev0.elapsed_time(ev1)
+        plan.solve(y, s, m, out=out)
+        f_mix = out.clone()
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=fmap.REDBLACK)) as plan:
+        f_64 = plan.solve(y, s, m)
+    mb = m.bool()
+    diff = float(torch.sqrt(torch.mean((f_mix - f_64)[mb] ** 2)))
+    res = {"grid": list(vol.shape), "coils": vol.ncoil, "echoes": vol.necho, "pairs": vol.necho * (vol.necho - 1) // 2,
+           "niter": vol.niter, "voxels": nmask, "ms_per_solve": ms_solve, "init_ms": ms_init,
+           "loop_ms": ms_loop, "loop_voxel_iterations_per_s": nmask * vol.niter / (ms_loop * 1e-3),
+           "rms_mix_vs_f64_hz": diff}
+    log("water-fat: solve %.3f ms (init %.3f ms, loop %.3f ms, %.3e voxel-iterations/s); MIX vs F64 %.2e Hz RMS"
+        % (ms_solve, ms_init, ms_loop, res["loop_voxel_iterations_per_s"], diff))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +203,7 @@ def main():
     ap.add_argument("--no-natural", action="store_true", help="skip the natural-order comparison line")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-volume batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the implicit-adjoint timing")
+    ap.add_argument("--no-waterfat", action="store_true", help="skip the 192x192x64 water-fat solve")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -260,6 +302,10 @@ def main():
     if not args.no_batched:
         batched = bench_batched(args, fmap, synth, torch, prec)
 
+    waterfat = None
+    if not args.no_waterfat:
+        waterfat = bench_waterfat(args, fmap, synth, torch)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -316,6 +362,7 @@ def main():
         "natural_order": natural,
         "adjoint": adjoint,
         "batched": batched,
+        "waterfat": waterfat,
         "cpu_baseline": cpu,
     }
     plan.close()

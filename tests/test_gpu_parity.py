@@ -291,3 +291,37 @@ def test_full_size_mid_volume_few_iterations(ordering):
     say("  f64 rms %.3e Hz, mix rms %.3e Hz" % (e64, emx))
     assert e64 < 1e-3
     assert emx < 0.05
+
+
+def test_waterfat_full_size_few_iterations():
+    """192x192x64, 8 coils, 6 echoes: the voxelwise sweep on a crop, then 3 iterations from the
+    GPU's initial map against the oracle from the same map (F64 and MIX)."""
+    vol = synth.waterfat()
+    say("water-fat full size %s" % (vol.shape,))
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.MIX, niter=3)) as plan:
+        plan.setup(y, s, m)
+        f0 = plan.init()
+        f_mix = plan.solve(y, s, m, f0=f0).cpu().numpy()
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, niter=3)) as plan:
+        f_64 = plan.solve(y, s, m, f0=f0).cpu().numpy()
+    f0n = f0.cpu().numpy()
+    pb = O.problem_for(vol, niter=3)
+    zh = O.combine(vol.y, vol.sens)
+    ref, _, _ = O.solve(pb, zh, vol.mask, f0n)
+    msk = vol.mask.astype(bool)
+    e64, emix = rms(f_64 - ref, msk), rms(f_mix - ref, msk)
+    say("  rms vs oracle: F64 %.3e Hz, MIX %.3e Hz" % (e64, emix))
+    assert e64 < 1e-3 and emix < 0.05
+    # the initial map (voxelwise sweep + PWLS) on a crop of the full-size data, against the oracle
+    sl = (slice(88, 104), slice(88, 104), slice(28, 36))
+    crop = synth.Volume(y=vol.y[(slice(None), slice(None)) + sl], sens=vol.sens[(slice(None),) + sl],
+                        te=vol.te, mask=vol.mask[sl], f_true=None, beta=vol.beta, niter=1, model="waterfat",
+                        fat_hz=vol.fat_hz, fat_amp=vol.fat_amp)
+    yc, sc, mc = fmap.to_device(crop)
+    with fmap.Plan(fmap.params_for(crop, precision=fmap.F64, niter=1)) as plan:
+        plan.setup(yc, sc, mc)
+        got = plan.init().cpu().numpy()
+    pbc = O.problem_for(crop)
+    ref0 = O.initial_map(crop, pbc, O.combine(crop.y, crop.sens))
+    assert rms(got - ref0, crop.mask.astype(bool)) < 1e-6
