@@ -784,7 +784,7 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   if (!plan_alloc_padded(p, (void **)&(ptr), n, (esize)))                             \
     return cleanup(fail(FM_ERR_ALLOC, "hipMalloc of " #ptr " failed"));
   FM_ALLOC(p->dat, 2 * ts * L * n);
-  FM_ALLOC(p->code, n);
+  FM_ALLOC_PAD(p->code, 1);  // padded like every array a kernel may address at neighbour offsets
   for (int i = 0; i < 2; ++i) {
     FM_ALLOC_PAD(p->F[i], ts);
     FM_ALLOC_PAD(p->Z[i], ts);
@@ -835,7 +835,8 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   }
 #undef FM_ALLOC
 #undef FM_ALLOC_PAD
-  if (hipMemset(p->S, 0, sizeof(fm::State) * 2) != hipSuccess || hipMemset(p->status, 0, sizeof(int32_t)) != hipSuccess ||
+  if (hipMemset(p->code - p->pad, 0, (size_t)n + 2 * (size_t)p->pad) != hipSuccess ||
+      hipMemset(p->S, 0, sizeof(fm::State) * 2) != hipSuccess || hipMemset(p->status, 0, sizeof(int32_t)) != hipSuccess ||
       hipMemset(p->nmask, 0, sizeof(double)) != hipSuccess || hipMemset(p->trace, 0, trace_bytes) != hipSuccess ||
       hipMemset(p->part, 0, sizeof(double) * 2 * p->part_rows * kMaxK) != hipSuccess)
     return cleanup(fail(FM_ERR_HIP, "hipMemset of the plan state failed"));

@@ -313,6 +313,7 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a0, const T *__restr
   const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
+  int bad = 0;
   for (; base < n; base += stride) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -324,7 +325,8 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a0, const T *__restr
 #pragma unroll
       for (int k = 0; k < 6; ++k)
         if (has_nb(cv, k)) s += (double)pn[v][k];
-      const double ip = h0[v];  // red pivots are h_r
+      const double ip = h0[v];  // red pivots are h_r (1/h stored as 0 when h_r <= 0)
+      if (!(ip > 0.0)) bad = 1;
       if (a.store_piv) a.ipiv[j] = ip;
       const T pj = (T)((double)g0[v] * ip + beta * s * ip);
       a.P[j] = pj;
@@ -333,6 +335,7 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a0, const T *__restr
     }
     if (base + stride < n) load(base + stride);
   }
+  if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
   put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
 }

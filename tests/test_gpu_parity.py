@@ -196,15 +196,17 @@ def test_edge_cases_empty_mask_single_voxel_and_line():
         assert rms(f - ref["f"], line.mask.astype(bool)) < 1e-9
 
 
-def test_zero_curvature_isolated_voxel_reports_not_pd():
-    say("edge: isolated voxel with zero data -> NOT_PD")
+@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+def test_zero_curvature_isolated_voxel_reports_not_pd(ordering):
+    say("edge: isolated voxel with zero data -> NOT_PD (%s)" % ordering)
     vol = ragged_volume()
     vol.mask[:] = 0
     vol.mask[2:6, 2:6, 2:5] = 1
-    vol.mask[10, 7, 5] = 1  # isolated voxel
+    vol.mask[10, 7, 5] = 1  # isolated voxel (a red one: 10 + 7 + 5 is even)
     vol.y[:, :, 10, 7, 5] = 0
     y, s, m = fmap.to_device(vol)
-    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64)) as plan:
+    order = fmap.NATURAL if ordering == "natural" else fmap.REDBLACK
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=order)) as plan:
         plan.solve(y, s, m)
         with pytest.raises(fmap.FmapError) as ei:
             plan.trace()
