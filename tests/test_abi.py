@@ -55,3 +55,33 @@ def test_status_strings_and_host_validation():
         assert len(L.fm_last_error()) > 0
     assert L.fm_plan_create(None, C.byref(h)) == 1
     assert L.fm_plan_destroy(None) == 0
+
+
+def test_size_and_batch_validation_before_any_device_work():
+    """Index bound (2^31 padded voxels per plan) and batch compatibility are checked on the host."""
+    if not os.path.exists(fmap.LIBPATH):
+        pytest.skip("libfmap.so not built")
+    L = fmap.lib()
+    h = C.c_void_p()
+    big = fmap.make_params((2048, 1024, 1024), 1, [0, 1e-3], 0.1)
+    assert L.fm_plan_create(C.byref(big), C.byref(h)) == 2 and not h.value
+    huge = fmap.make_params((1 << 12, 1 << 12, 1 << 12), 1, [0, 1e-3], 0.1)
+    assert L.fm_plan_create(C.byref(huge), C.byref(h)) == 2 and not h.value
+
+    def batch_status(prms):
+        arr = (fmap.Params * len(prms))(*prms)
+        b = C.c_void_p()
+        st = L.fm_batch_create(C.c_int32(len(prms)), C.cast(arr, C.c_void_p), C.byref(b))
+        assert not b.value
+        return st
+
+    a = fmap.make_params((8, 8, 8), 1, [0, 1e-3, 2e-3], 0.1, ordering=fmap.REDBLACK)
+    natural = fmap.make_params((8, 8, 8), 1, [0, 1e-3, 2e-3], 0.1, ordering=fmap.NATURAL)
+    other_te = fmap.make_params((8, 8, 8), 1, [0, 1e-3, 2.5e-3], 0.1, ordering=fmap.REDBLACK)
+    wf = fmap.make_params((8, 8, 8), 1, [0, 1e-3, 2e-3], 0.1, ordering=fmap.REDBLACK, model=fmap.WATERFAT,
+                          fat_hz=[-434.0], fat_amp=[1.0])
+    assert batch_status([a, natural]) == 1
+    assert batch_status([a, other_te]) == 1
+    assert batch_status([a, wf]) == 1
+    assert L.fm_batch_create(C.c_int32(0), None, C.byref(h)) == 1
+    assert L.fm_batch_destroy(None) == 0
