@@ -146,6 +146,47 @@ def bench_batched(args, fmap, synth, torch, prec):
     return res
 
 
+def bench_convergence(args, fmap, vol, y, s, m, torch, prec, ms_iter_rb):
+    """Iterations and time to reach a relative cost gap (Psi_i - Psi*) / (Psi_0 - Psi*) of 1e-3 and
+    1e-4 for each preconditioner on the benchmark volume, Psi* = the least cost of 400-iteration F64
+    solves with natural-order IC(0) and red-black IC(0).  Time = iterations x the measured time of one
+    iteration of that preconditioner."""
+    log("convergence: 400-iteration traces per preconditioner")
+    runs = {"ic0_natural": (fmap.NATURAL, fmap.IC0), "ic0_redblack": (fmap.REDBLACK, fmap.IC0),
+            "diag": (fmap.NATURAL, fmap.DIAG), "none": (fmap.NATURAL, fmap.NONE)}
+    traces, ms_iter = {}, {}
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, (order, pc) in runs.items():
+        prm = fmap.params_for(vol, precision=fmap.F64, ordering=order, precond=pc, niter=400)
+        with fmap.Plan(prm) as pl:
+            pl.solve(y, s, m)
+            traces[name] = pl.trace()[:, 0].copy()
+        # time per iteration in the benchmark's precision
+        with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=order, precond=pc, niter=20)) as pl:
+            pl.solve(y, s, m)
+            ev0.record(stream)
+            pl.iterate(20)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms_iter[name] = ev0.elapsed_time(ev1) / 20
+    best = min(float(t.min()) for t in traces.values())
+    res = {"reference_cost": best, "niter_max": 400}
+    for name, tr in traces.items():
+        gap = (tr - best) / (tr[0] - best)
+        row = {"ms_per_iteration": ms_iter[name]}
+        for tol in (1e-3, 1e-4):
+            hit = np.nonzero(gap <= tol)[0]
+            it = int(hit[0]) if hit.size else None
+            row["iters_%g" % tol] = it
+            row["ms_%g" % tol] = None if it is None else it * ms_iter[name]
+        res[name] = row
+        log("  %-13s %.4f ms/iteration; gap 1e-3 after %s iterations (%s ms), 1e-4 after %s (%s ms)" % (
+            name, ms_iter[name], row["iters_0.001"], None if row["ms_0.001"] is None else round(row["ms_0.001"], 2),
+            row["iters_0.0001"], None if row["ms_0.0001"] is None else round(row["ms_0.0001"], 2)))
+    return res
+
+
 def bench_waterfat(args, fmap, synth, torch):
     """192x192x64, 8 coils, 6 echoes, six-peak fat: full solve (setup, sweep + PWLS start, 100
     iterations) in MIX, the iteration loop alone, and the MIX map against an F64 solve."""
@@ -204,6 +245,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-volume batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the implicit-adjoint timing")
     ap.add_argument("--no-waterfat", action="store_true", help="skip the 192x192x64 water-fat solve")
+    ap.add_argument("--no-convergence", action="store_true",
+                    help="skip the time-to-accuracy comparison of the preconditioners")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -281,6 +324,10 @@ def main():
         natural = {"ms_per_step": ms_nat, "value": nmask * niter / (ms_nat * 1e-3),
                    "final_cost": float(trn[-1, 0])}
         log("natural order: %.3f ms per step, %.3e voxel-iterations/s" % (ms_nat, natural["value"]))
+
+    convergence = None
+    if not args.no_convergence and args.precond == "ic0":
+        convergence = bench_convergence(args, fmap, vol, y, s, m, torch, prec, ms_loop / niter)
 
     adjoint = None
     if not args.no_adjoint:
@@ -360,6 +407,7 @@ def main():
         },
         "final_cost": float(tr[-1, 0]),
         "natural_order": natural,
+        "convergence": convergence,
         "adjoint": adjoint,
         "batched": batched,
         "waterfat": waterfat,
