@@ -160,6 +160,13 @@ fm_status fm_iterate(fm_plan *plan, int32_t niter, double *f_out, hipStream_t st
  * FM_ERR_NOT_PD or FM_ERR_NONFINITE). */
 fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
 
+/* Device status of the work enqueued so far on this plan (synchronises the
+ * stream): FM_OK, or the first device-side error of the last solve
+ * (FM_ERR_NOT_PD for a non-positive IC(0) pivot, FM_ERR_NONFINITE,
+ * FM_ERR_TIMEOUT for an expired wavefront wait, FM_ERR_STATE for a broken
+ * launch chain).  The word is cleared by the next fm_solve. */
+fm_status fm_plan_status(fm_plan *plan, hipStream_t stream);
+
 /* Number of voxels inside the mask given to the last fm_setup (host int64),
  * synchronising the stream. */
 fm_status fm_mask_count(fm_plan *plan, int64_t *count, hipStream_t stream);

@@ -1103,6 +1103,16 @@ fm_status fm_components(fm_plan *p, const void *y, const void *sens, const doubl
   return FM_OK;
 }
 
+fm_status fm_plan_status(fm_plan *p, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  int32_t status = 0;
+  fm_status rs = read_status(p, s, &status);
+  if (rs) return rs;
+  if (status) return fail((fm_status)status, "the last solve reported a device-side error");
+  return FM_OK;
+}
+
 fm_status fm_get_trace(fm_plan *p, double *trace, hipStream_t s) {
   fm_status cs = check_plan(p);
   if (cs) return cs;

@@ -211,6 +211,12 @@ def test_zero_curvature_isolated_voxel_reports_not_pd(ordering):
         with pytest.raises(fmap.FmapError) as ei:
             plan.trace()
         assert ei.value.status == 5
+        with pytest.raises(fmap.FmapError) as ei:
+            plan.status()
+        assert ei.value.status == 5
+        vol.mask[10, 7, 5] = 0  # without the isolated voxel the status clears on the next solve
+        plan.solve(y, s, torch.from_numpy(vol.mask).cuda())
+        plan.status()
 
 
 @pytest.mark.parametrize("prec", ["f64", "mix"])
