@@ -179,6 +179,15 @@ std::vector<double> make_component_matrix(const fm_params &p, int *K) {
   return out;
 }
 
+// The setup kernel for an echo bucket and model.
+template <typename T>
+using SetupKernel = void (*)(fm::SetupArgs<T>);
+template <typename T>
+SetupKernel<T> setup_kernel(int lmax, bool wf) {
+  if (wf) return lmax <= 4 ? fm::k_setup<T, 4, true> : (lmax <= 8 ? fm::k_setup<T, 8, true> : fm::k_setup<T, 16, true>);
+  return lmax <= 4 ? fm::k_setup<T, 4, false> : (lmax <= 8 ? fm::k_setup<T, 8, false> : fm::k_setup<T, 16, false>);
+}
+
 template <typename T>
 std::vector<fm::PairC<T>> make_pairs(const fm_params &p, const std::vector<std::complex<double>> &G) {
   std::vector<fm::PairC<T>> out;
@@ -907,7 +916,7 @@ fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *m
       a.ftilde = p->wf_tmp;
     }
     a.partials = p->setup_part;
-    hipLaunchKernelGGL(fm::k_setup<T>, dim3(p->grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(setup_kernel<T>(p->lmax, p->prm.model == FM_WATERFAT), dim3(p->grid), dim3(kBlock), 0, s, a);
     FM_LAUNCH_CHECK();
     hipLaunchKernelGGL(fm::k_count, dim3(1), dim3(kBlock), 0, s, (const double *)p->setup_part, p->grid, p->nmask);
     FM_LAUNCH_CHECK();

@@ -51,7 +51,10 @@ struct SetupArgs {
   double *partials;    // [kMaxK][gridDim.x] in-mask counts
 };
 
-template <typename T>
+// LMAX bounds the echo count (compile-time register arrays); WF selects the
+// water-fat outputs (the sweep and the PWLS weights), so the field-map
+// instantiation carries none of their registers.
+template <typename T, int LMAX, bool WF>
 __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
   const Geo g = a.geo;
   double cnt[1] = {0.0};
@@ -85,8 +88,11 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
     }
     const double scale = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
     double z1r = 0, z1i = 0, z2r = 0, z2i = 0;
-    double mag[16], ph[16];
-    for (int l = 0; l < a.L; ++l) {
+    double mag[LMAX], ph[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) {
+      mag[l] = ph[l] = 0.0;
+      if (l >= a.L) continue;
       double re = 0.0, im = 0.0;
       for (int cc = 0; cc < a.ncoil; ++cc) {
         const float2 yv = a.y[((int64_t)cc * a.L + l) * g.n + j];
@@ -110,20 +116,32 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
       d.y = (T)ph[l];
       a.dat[(int64_t)l * a.estride + j] = d;
     }
-    if (a.ftilde) {
+    if (WF && a.ftilde) {
       // Sec. III-A water-fat start: the sweep value of least per-voxel cost
-      // (first one on ties), evaluated in FP64 in every precision mode.
+      // (first one on ties), evaluated in FP64 in every precision mode.  Per
+      // pair, 1 - cos(2 pi xi) = 2 sin^2(pi h) with h the wrap of xi; sin(pi h)
+      // from the FP64 Taylor form of sinx_cos (|pi h| <= pi/2).
       double best = 1.0 / 0.0, bestf = 0.0;
       if (in) {
         for (int q = 0; q < a.nsweep; ++q) {
           const double fs = -a.sweep_half + 2.0 * a.sweep_half * q / (a.nsweep - 1);
           double c0 = 0.0;
-          for (int pq = 0; pq < a.npairs; ++pq) {
-            const PairC<double> P = a.pairs_d[pq];
-            const double xi = P.g + (ph[P.n] - ph[P.m]) + fs * P.dt;
-            const double h = xi - rint(xi);
-            const double s = sinpi(h);
-            c0 += P.w * mag[P.m] * mag[P.n] * (2.0 * s * s);
+          int pq = 0;
+#pragma unroll
+          for (int m = 0; m < LMAX; ++m) {
+#pragma unroll
+            for (int n2 = m + 1; n2 < LMAX; ++n2) {
+              if (n2 < a.L) {
+                const PairC<double> P = a.pairs_d[pq];
+                const double xi = P.g + (ph[n2] - ph[m]) + fs * P.dt;
+                const double x = 3.14159265358979323846 * (xi - rint(xi));
+                double sx, cs;
+                sinx_cos(x, sx, cs);
+                const double sn = x * sx;
+                c0 += P.w * mag[m] * mag[n2] * (2.0 * sn * sn);
+                ++pq;
+              }
+            }
           }
           if (c0 < best) {
             best = c0;
@@ -138,10 +156,13 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
       const double pr = z1r * z2r + z1i * z2i, pi = z1r * z2i - z1i * z2r;
       a.f0[j] = in ? atan2(pi, pr) * a.inv_2pi_dt : 0.0;
     }
-    if (a.rho) {
+    if (WF && a.rho) {
       // rho_j = (1/S_j) sum_{m,n} |Gamma_mn| a_m a_n, a_m = sum_c |s_c| |y_cm|
-      double av[16];
-      for (int m = 0; m < a.L; ++m) {
+      double av[LMAX];
+#pragma unroll
+      for (int m = 0; m < LMAX; ++m) {
+        av[m] = 0.0;
+        if (m >= a.L) continue;
         double am = 0.0;
         for (int cc = 0; cc < a.ncoil; ++cc) {
           const float2 yv = a.y[((int64_t)cc * a.L + m) * g.n + j];
@@ -155,8 +176,11 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
         av[m] = am;
       }
       double r = 0.0;
-      for (int m = 0; m < a.L; ++m)
-        for (int n2 = 0; n2 < a.L; ++n2) r += a.gabs[m * a.L + n2] * av[m] * av[n2];
+#pragma unroll
+      for (int m = 0; m < LMAX; ++m)
+#pragma unroll
+        for (int n2 = 0; n2 < LMAX; ++n2)
+          if (m < a.L && n2 < a.L) r += a.gabs[m * a.L + n2] * av[m] * av[n2];
       a.rho[j] = (in && ss > 0.0) ? r / ss : 0.0;
     }
   }
