@@ -26,7 +26,7 @@
 namespace fm {
 
 constexpr int kTile = 8;         // tile edge (8x8 columns = one wavefront)
-constexpr int kStepU = 4;        // steps per unrolled group / prefetch distance
+constexpr int kStepU = 4;        // steps per unrolled group / prefetch distance (8 and 16 measured slower)
 constexpr int kSpinLimit = 1 << 16;  // polls per wait (each ~1 us): about 0.1 s
 
 struct Wavefront {
@@ -111,28 +111,29 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
   uint32_t rc[kStepU];
   double rh[kStepU], rbr[kStepU], rbyr[kStepU];
   T rg[kStepU], rbx[kStepU], rbyx[kStepU];
+  // Every lane issues the same loads at every step (addresses clamped into the
+  // arrays, values masked afterwards), so the number of memory operations per
+  // step is fixed and the compiler can wait for exactly the slot it consumes
+  // instead of draining every outstanding load.
   auto prefetch = [&](int S, int u) {
     const int z = S - la - lb;
-    rc[u] = 0u;
-    if (col_ok && z >= 0 && z < nz) {
-      const int64_t j = jcol + z;
-      const uint32_t c = a.code[j];
-      rc[u] = c;
-      rh[u] = (double)a.D[j] + beta * nb_deg(c);
-      rg[u] = gg[j];
-      if (la == 0 && (c & NB_XM)) {
-        rbr[u] = ld_coh(a.ipiv + (j - g.sx));
-        rbx[u] = ld_coh(a.X + (j - g.sx));
-      }
-      if (lb == 0 && (c & NB_YM)) {
-        rbyr[u] = ld_coh(a.ipiv + (j - g.sy));
-        rbyx[u] = ld_coh(a.X + (j - g.sy));
-      }
-    }
+    const bool ok = col_ok && z >= 0 && z < nz;
+    const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
+    const uint32_t c = a.code[j];
+    rc[u] = ok ? c : 0u;
+    rh[u] = (double)a.D[j] + beta * nb_deg(c);
+    rg[u] = gg[j];
+    const int64_t jx = (col_ok && la == 0 && x > 0) ? j - g.sx : j;  // tile boundary: the -x neighbour column
+    const int64_t jy = (col_ok && lb == 0 && y > 0) ? j - g.sy : j;
+    rbr[u] = ld_coh(a.ipiv + jx);
+    rbx[u] = ld_coh(a.X + jx);
+    rbyr[u] = ld_coh(a.ipiv + jy);
+    rbyx[u] = ld_coh(a.X + jy);
   };
   // boundary data of steps [0, kStepU) must be stored by the neighbour tiles
-  if (prog_x) px = wait_prog(prog_x, kStepU + kTile, px, a.status, timed_out);
-  if (prog_y) py = wait_prog(prog_y, kStepU + kTile, py, a.status, timed_out);
+  const int need0 = kStepU + kTile < nsteps ? kStepU + kTile : nsteps;
+  if (prog_x) px = wait_prog(prog_x, need0, px, a.status, timed_out);
+  if (prog_y) py = wait_prog(prog_y, need0, py, a.status, timed_out);
 #pragma unroll
   for (int u = 0; u < kStepU; ++u) prefetch(u, u);
   double r_prev = 0.0, x_prev = 0.0;  // this lane's previous z (same column)
@@ -174,11 +175,15 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
           r_new = ip;
           x_new = (double)(T)(((double)rg[u] + beta * sx) * ip);
         }
-        const int64_t j = jcol + z;
-        st_coh(a.ipiv + j, r_new);
-        st_coh(a.X + j, (T)x_new);
         r_prev = r_new;
         x_prev = x_new;
+      }
+      {
+        // out-of-range lanes store into the padding before voxel 0 (never read as data)
+        const bool ok = col_ok && z >= 0 && z < nz;
+        const int64_t j = ok ? jcol + z : -1;
+        st_coh(a.ipiv + j, r_new);
+        st_coh(a.X + j, (T)x_new);
       }
       r_out = r_new;
       x_out = x_new;
@@ -224,23 +229,23 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
   uint32_t rc[kStepU];
   double rip[kStepU];
   T rx[kStepU], rg[kStepU], rgp[kStepU], rbx[kStepU], rby[kStepU];
+  // same fixed per-step load pattern as the forward sweep
   auto prefetch = [&](int S, int u) {
     const int z = nz - 1 - (S - ra - rb);
-    rc[u] = 0u;
-    if (col_ok && z >= 0 && z < nz) {
-      const int64_t j = jcol + z;
-      const uint32_t c = a.code[j];
-      rc[u] = c;
-      rip[u] = ld_coh(a.ipiv + j);
-      rx[u] = ld_coh(a.X + j);
-      rg[u] = gg[j];
-      rgp[u] = gp[j];
-      if (la == kTile - 1 && (c & NB_XP)) rbx[u] = ld_coh(a.P + (j + g.sx));
-      if (lb == kTile - 1 && (c & NB_YP)) rby[u] = ld_coh(a.P + (j + g.sy));
-    }
+    const bool ok = col_ok && z >= 0 && z < nz;
+    const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
+    const uint32_t c = a.code[j];
+    rc[u] = ok ? c : 0u;
+    rip[u] = ld_coh(a.ipiv + j);
+    rx[u] = ld_coh(a.X + j);
+    rg[u] = gg[j];
+    rgp[u] = gp[j];
+    rbx[u] = ld_coh(a.P + ((col_ok && la == kTile - 1 && x + 1 < g.nx) ? j + g.sx : j));
+    rby[u] = ld_coh(a.P + ((col_ok && lb == kTile - 1 && y + 1 < g.ny) ? j + g.sy : j));
   };
-  if (prog_x) px = wait_prog(prog_x, kStepU + kTile, px, a.status, timed_out);
-  if (prog_y) py = wait_prog(prog_y, kStepU + kTile, py, a.status, timed_out);
+  const int need0 = kStepU + kTile < nsteps ? kStepU + kTile : nsteps;
+  if (prog_x) px = wait_prog(prog_x, need0, px, a.status, timed_out);
+  if (prog_y) py = wait_prog(prog_y, need0, py, a.status, timed_out);
 #pragma unroll
   for (int u = 0; u < kStepU; ++u) prefetch(u, u);
   double p_prev = 0.0, p_out = 0.0;
@@ -268,9 +273,9 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
           acc[0] += (double)rg[u] * p_new;
           acc[1] += (double)rgp[u] * p_new;
         }
-        st_coh(a.P + jcol + z, (T)p_new);
         p_prev = p_new;
       }
+      st_coh(a.P + (col_ok && z >= 0 && z < nz ? jcol + z : (int64_t)-1), (T)p_new);  // see the forward sweep
       p_out = p_new;
       if (S + kStepU < nsteps) prefetch(S + kStepU, u);
     }
