@@ -45,10 +45,12 @@ def bytes_per_voxel(kclass, precision, L, ordering, precond):
         if kclass == "precond_b":  # read code, x, 1/P (8), g, g_prev; write p
             return 1 + 4 * t + 8
     if rb:
-        if kclass == "precond_a":  # black: D, g_prev, p of black; g of all; 1/h of red
-            return 1 + 2.5 * t + 4
-        if kclass == "precond_b":  # red: g, g_prev, 1/h, p of red; p of black
-            return 1 + 2.5 * t + 4
+        # black pass with both dot products: D, p of black; g, g_prev of all; 1/h of red
+        if kclass == "precond_a":
+            return 1 + 3 * t + 4
+        # red pass fused with the direction: g, 1/h of red; p of black; z_prev, f, D of all / z
+        if kclass == "precond_b":
+            return 1 + 4.5 * t + 4
     if kclass == "precond_a":      # diagonal / identity: read code, D, g, g_prev; write 1/h (8), p
         return 1 + 4 * t + 8
     return 0
@@ -57,13 +59,14 @@ def bytes_per_voxel(kclass, precision, L, ordering, precond):
 KERNEL_SYMBOL = {"grad": "k_grad", "mls": "k_mls", "dir": "k_dir", "precond_a": None, "precond_b": None}
 
 
-def kernel_symbol(kclass, ordering, precond):
+def kernel_symbol(kclass, ordering, precond, nz):
     if kclass in ("precond_a", "precond_b"):
         if precond != "ic0":
             return "k_diag"
         if ordering == "natural":
             return "k_ic_fwd_wave" if kclass == "precond_a" else "k_ic_bwd_wave"
-        return "k_rb_black" if kclass == "precond_a" else "k_rb_red"
+        pair = "_pair" if nz % 2 == 0 else ""  # pair-mapped passes when every column length is even
+        return ("k_rb_black" if kclass == "precond_a" else "k_rb_red_dir") + pair
     return KERNEL_SYMBOL[kclass]
 
 
@@ -79,7 +82,7 @@ def measured_traffic(kclass, args):
         rec = json.load(fh)
     if rec.get("source_hash") != source_hash():
         return None
-    sym = kernel_symbol(kclass, args.ordering, args.precond)
+    sym = kernel_symbol(kclass, args.ordering, args.precond, int(args.shape.split(",")[2]))
     for name, v in rec["kernels"].items():
         if sym and ("fm::%s<" % sym) in name:
             return v["traffic_bytes"]

@@ -316,8 +316,13 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
 
 // Launches per iteration (must match enqueue_iteration).
 uint64_t launches_per_iteration(const fm_plan *p) {
-  const uint64_t precond = (p->prm.precond == FM_PRECOND_IC0) ? 2 : 1;
-  return 1 + precond + 1 + (uint64_t)(p->prm.nmls - 1);
+  // preconditioner passes + direction; red-black IC(0) forms the direction in its red pass
+  const uint64_t precond_dir = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_NATURAL) ? 3 : 2;
+  return 1 + precond_dir + (uint64_t)(p->prm.nmls - 1);
+}
+
+bool fused_red_dir(const fm_plan *p) {
+  return p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK;
 }
 
 // Values per partial block left by the last pass of an iteration.
@@ -331,10 +336,26 @@ fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) 
   FM_LAUNCH(FM_K_GRAD, (fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
   FM_LAUNCH_CHECK();
   set_parts(p, p->sgrid, 4);
-  fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
-  if (st) return st;
-  FM_LAUNCH(FM_K_DIR, (fm::k_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
-  FM_LAUNCH_CHECK();
+  if (fused_red_dir(p) && p->geo.nz % 2 == 0) {
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black_pair<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_rb_red_dir_pair<T, false>), dim3(p->sgrid), dim3(fm::kNT), s,
+              iter_args<T>(p, p->q++));
+    FM_LAUNCH_CHECK();
+  } else if (fused_red_dir(p)) {
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black<T, false, true>), dim3(p->sgrid), dim3(fm::kNT), s,
+              iter_args<T>(p, p->q++), (const T *)nullptr);
+    FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_rb_red_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    FM_LAUNCH_CHECK();
+  } else {
+    fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
+    if (st) return st;
+    FM_LAUNCH(FM_K_DIR, (fm::k_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    FM_LAUNCH_CHECK();
+  }
   set_parts(p, p->sgrid, 3);
   for (int k = 1; k < p->prm.nmls; ++k) {
     FM_LAUNCH(FM_K_MLS, (fm::k_mls<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));

@@ -30,6 +30,18 @@ struct Vpt {
   static constexpr int v = sizeof(T) == 4 ? FM_VPT32 : FM_VPT64;
 };
 
+// Per-kernel overrides of the voxels per thread (FP32 working type).
+#ifndef FM_V_GRAD
+#define FM_V_GRAD FM_VPT32
+#endif
+#ifndef FM_V_MLS
+#define FM_V_MLS FM_VPT32
+#endif
+template <typename T, int V32>
+struct Vk {
+  static constexpr int v = sizeof(T) == 4 ? V32 : FM_VPT64;
+};
+
 // Every array read at neighbour offsets is padded by one x-plane (sx
 // elements) on both sides, so j + off is always a valid address; the code
 // bits decide whether the value is a neighbour.  Indices are 32-bit (the
@@ -119,7 +131,7 @@ __device__ __forceinline__ VArgs<T> at_volume(const IterArgs<T> &a0, const VolVi
 // Partial sums: sum phi, f^T C^T C f, ||g||^2, z_prev^T g.
 template <typename T, int LMAX, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a0) {
-  constexpr int V = Vpt<T>::v;
+  constexpr int V = Vk<T, FM_V_GRAD>::v;
   const VolView vw = vol_view<BATCH>(a0);
   const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
@@ -206,8 +218,17 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a0) {
 //   P_b = h_b - beta^2 sum_k 1/h_k,   x_b = (g_b + beta sum_k g_k / h_k) / P_b,
 // and p_b = x_b (no later neighbour); then p_r = x_r + (beta / h_r) sum_k p_k.
 // 1/h is read from hinv (written once per voxel by the gradient pass).
-// Partial sums: g^T p and g_prev^T p over the colour of the pass.
-template <typename T, bool BATCH>
+//
+// Partial sums.  With DOTS = false (standalone preconditioner): g^T p and
+// g_prev^T p over the black voxels, the red pass adds the rest.  With
+// DOTS = true (the iteration): both dot products in full, from the factored
+// form M = L Lam L^T of the preconditioner, u^T M^{-1} g = (L^{-1} u)^T
+// Lam^{-1} (L^{-1} g).  L^{-1} g is g on red voxels and
+// y_b = g_b + beta sum_k g_k / h_k on black ones, with Lam = h_r, P_b, so
+//   g^T p      = sum_r g_r^2 / h_r       + sum_b y_b  y_b / P_b,
+//   g_prev^T p = sum_r g'_r g_r / h_r    + sum_b y'_b y_b / P_b,
+// and the direction can be formed in the red pass (k_rb_red_dir).
+template <typename T, bool BATCH, bool DOTS = false>
 __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a0, const T *__restrict__ gsrc) {
   constexpr int V = Vpt<T>::v;
   const VolView vw = vol_view<BATCH>(a0);
@@ -218,9 +239,10 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a0, const T *__res
   const double *__restrict__ hv = a.hinv;
   const Offs of(g);
   const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
+  constexpr int NGP = DOTS ? 6 : 1;
   uint32_t c[V];
-  T d0[V], g0[V], gp0[V], gn[V][6];
-  double hn[V][6];
+  T d0[V], g0[V], gp0[V], gn[V][6], gpn[V][NGP];
+  double hn[V][6], h0[V];
   auto load = [&](int b) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -230,10 +252,12 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a0, const T *__res
       d0[v] = a.D[jj];
       g0[v] = gg[jj];
       gp0[v] = gp[jj];
+      if (DOTS) h0[v] = hv[jj];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         gn[v][k] = gg[jj + of.o[k]];
         hn[v][k] = hv[jj + of.o[k]];
+        if (DOTS) gpn[v][k < NGP ? k : 0] = gp[jj + of.o[k]];
       }
     }
   };
@@ -254,14 +278,22 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a0, const T *__res
         a.P[j] = T(0);
         continue;
       }
-      if (!(cv & NB_BLACK)) continue;
+      if (!(cv & NB_BLACK)) {
+        if (DOTS) {
+          const double gh = (double)g0[v] * h0[v];
+          acc[0] += (double)g0[v] * gh;
+          acc[1] += (double)gp0[v] * gh;
+        }
+        continue;
+      }
       const double h = (double)d0[v] + beta * nb_deg(cv);
-      double sp = 0.0, sxv = 0.0;
+      double sp = 0.0, sxv = 0.0, syp = 0.0;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
         if (has_nb(cv, k)) {
           sp += hn[v][k];
           sxv += (double)gn[v][k] * hn[v][k];
+          if (DOTS) syp += (double)gpn[v][k < NGP ? k : 0] * hn[v][k];
         }
       const double piv = h - b2 * sp;
       double ip = 1.0 / piv;
@@ -270,16 +302,23 @@ __global__ __launch_bounds__(kNT) void k_rb_black(IterArgs<T> a0, const T *__res
         ip = 0.0;
       }
       if (a.store_piv) a.ipiv[j] = ip;
-      const T pj = (T)(((double)g0[v] + beta * sxv) * ip);
+      const double yb = (double)g0[v] + beta * sxv;
+      const T pj = (T)(yb * ip);
       a.P[j] = pj;
-      acc[0] += (double)g0[v] * (double)pj;
-      acc[1] += (double)gp0[v] * (double)pj;
+      if (DOTS) {
+        const double x = yb * ip;
+        acc[0] += yb * x;
+        acc[1] += ((double)gp0[v] + beta * syp) * x;
+      } else {
+        acc[0] += (double)g0[v] * (double)pj;
+        acc[1] += (double)gp0[v] * (double)pj;
+      }
     }
     if (base + stride < n) load(base + stride);
   }
   if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
-  put_state(st, a.sout, PK_DOTS_A, vw.nb, vw.leader);
+  put_state(st, a.sout, DOTS ? PK_DOTS : PK_DOTS_A, vw.nb, vw.leader);
 }
 
 template <typename T, bool BATCH>
@@ -338,6 +377,317 @@ __global__ __launch_bounds__(kNT) void k_rb_red(IterArgs<T> a0, const T *__restr
   if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
   put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
+}
+
+// Red pass of the iteration fused with the direction step (Sec. III Algorithm,
+// readings R6, R7): the incoming partials are the full dot products of
+// k_rb_black<DOTS = true>, so mu is known at entry, and every voxel forms
+//   z = -p + mu z_prev   (p_r from the red rule above, p_b from the black pass).
+// The line-search sums A = z^T C^T C f and B = ||C z||^2 are taken over the
+// edges of C: the 7-point stencil joins a red and a black voxel on every edge,
+// so each red voxel adds (z_r - z_k)(f_r - f_k) and (z_r - z_k)^2 over its
+// in-mask neighbours k, with z_k = -p_k + mu z_prev_k formed from their
+// loaded values.  d0 = sum z^2 D over all voxels.  Partial sums as k_dir.
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_rb_red_dir(IterArgs<T> a0) {
+  constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = a.Gc;
+  const T *__restrict__ zp = a.Zp;
+  T *__restrict__ zo = a.Zc;
+  const T *__restrict__ f = a.Fc;
+  const T *__restrict__ p = a.P;
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
+  uint32_t c[V];
+  T g0[V], p0[V], z0[V], f0[V], d0[V], pn[V][6], zn[V][6], fn[V][6];
+  double h0[V];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      g0[v] = gg[jj];
+      h0[v] = a.hinv[jj];
+      p0[v] = p[jj];
+      z0[v] = zp[jj];
+      f0[v] = f[jj];
+      d0[v] = a.D[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        pn[v][k] = p[jj + of.o[k]];
+        zn[v][k] = zp[jj + of.o[k]];
+        fn[v][k] = f[jj + of.o[k]];
+      }
+    }
+  };
+  int base = vw.bl * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  const T mu = (T)st.mu;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int bad = 0;
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        zo[j] = T(0);
+        continue;
+      }
+      T pj = p0[v];
+      const bool red = !(cv & NB_BLACK);
+      if (red) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (has_nb(cv, k)) s += (double)pn[v][k];
+        const double ip = h0[v];
+        if (!(ip > 0.0)) bad = 1;
+        pj = (T)((double)g0[v] * ip + beta * s * ip);
+      }
+      const T zj = -pj + mu * z0[v];
+      zo[j] = zj;
+      acc[2] += (double)zj * (double)zj * (double)d0[v];
+      if (red) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (has_nb(cv, k)) {
+            const double dz = (double)(zj - (-pn[v][k] + mu * zn[v][k]));
+            acc[0] += dz * (double)(f0[v] - fn[v][k]);
+            acc[1] += dz * dz;
+          }
+      }
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<3, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DIR, vw.nb, vw.leader);
+}
+
+// ---------------------------------------------------------------------------
+// Pair-mapped red-black passes of the iteration (used when every column has
+// an even length).  Then voxels 2q and 2q+1 lie in one column and have
+// opposite colours, so one thread per pair takes the pass's heavy voxel (the
+// one whose six neighbours it reads: black in the black pass, red in the red
+// pass) and the light one.  Compared with a voxel per lane, no lane loads
+// neighbours it then discards, which halves the neighbour loads; the pair's
+// own values move as one 2-element load or store.  Same arithmetic as
+// k_rb_black<DOTS = true> and k_rb_red_dir.
+#ifndef FM_VPAIR_B32
+#define FM_VPAIR_B32 1
+#endif
+#ifndef FM_VPAIR_R32
+#define FM_VPAIR_R32 2
+#endif
+template <typename T, int V32>
+struct Vpair {  // pairs per thread
+  static constexpr int v = sizeof(T) == 4 ? V32 : 1;
+};
+
+template <typename T>
+struct alignas(2 * sizeof(T)) Duo {
+  T v0, v1;
+};
+
+template <typename T>
+__device__ __forceinline__ Duo<T> ld_duo(const T *p, int j0) {
+  return *reinterpret_cast<const Duo<T> *>(p + j0);
+}
+
+// Colour of the pair from whichever code is in the mask (both out: either).
+__device__ __forceinline__ bool first_is_black(uint32_t cA, uint32_t cB) {
+  return (cA & NB_SELF) ? (cA & NB_BLACK) != 0 : (cB & NB_BLACK) == 0;
+}
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_rb_black_pair(IterArgs<T> a0) {
+  constexpr int V = Vpair<T, FM_VPAIR_B32>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = a.Gc;
+  const T *__restrict__ gp = a.Gp;
+  const double *__restrict__ hv = a.hinv;
+  const Offs of(g);
+  const int np = (int)(g.n >> 1), chunk = kNT * V, stride = vw.nb * chunk;
+  uint32_t cb[V], cr[V];
+  int jb[V];
+  T d0[V], g0[V], gp0[V], gr[V], gpr[V], gn[V][6], gpn[V][6];
+  double hr[V], hn[V][6];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int q = b + v * kNT + (int)threadIdx.x;
+      const int j0 = 2 * (q < np ? q : np - 1);
+      const uint32_t c2 = *reinterpret_cast<const uint16_t *>(a.code + j0);
+      const uint32_t cA = q < np ? (c2 & 0xffu) : 0u, cB = q < np ? (c2 >> 8) : 0u;
+      const bool fb = first_is_black(cA, cB);
+      const int jbv = fb ? j0 : j0 + 1, jrv = fb ? j0 + 1 : j0;
+      jb[v] = jbv;
+      cb[v] = fb ? cA : cB;
+      cr[v] = fb ? cB : cA;
+      const Duo<T> g2 = ld_duo(gg, j0), gp2 = ld_duo(gp, j0);
+      const Duo<double> h2 = ld_duo(hv, j0);
+      g0[v] = fb ? g2.v0 : g2.v1;
+      gr[v] = fb ? g2.v1 : g2.v0;
+      gp0[v] = fb ? gp2.v0 : gp2.v1;
+      gpr[v] = fb ? gp2.v1 : gp2.v0;
+      hr[v] = fb ? h2.v1 : h2.v0;
+      d0[v] = a.D[jbv];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        gn[v][k] = gg[jbv + of.o[k]];
+        gpn[v][k] = gp[jbv + of.o[k]];
+        hn[v][k] = hv[jbv + of.o[k]];
+      }
+    }
+  };
+  int base = vw.bl * chunk;
+  if (base < np) load(base);
+  const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta, b2 = a.beta * a.beta;
+  double acc[2] = {0.0, 0.0};
+  int bad = 0;
+  for (; base < np; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int q = base + v * kNT + (int)threadIdx.x;
+      if (q >= np) continue;
+      if (cr[v] & NB_SELF) {
+        const double gh = (double)gr[v] * hr[v];
+        acc[0] += (double)gr[v] * gh;
+        acc[1] += (double)gpr[v] * gh;
+      }
+      const uint32_t cv = cb[v];
+      if (!(cv & NB_SELF)) continue;
+      const double h = (double)d0[v] + beta * nb_deg(cv);
+      double sp = 0.0, sxv = 0.0, syp = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (has_nb(cv, k)) {
+          sp += hn[v][k];
+          sxv += (double)gn[v][k] * hn[v][k];
+          syp += (double)gpn[v][k] * hn[v][k];
+        }
+      const double piv = h - b2 * sp;
+      double ip = 1.0 / piv;
+      if (!(piv > 0.0)) {
+        bad = 1;
+        ip = 0.0;
+      }
+      const double yb = (double)g0[v] + beta * sxv;
+      const double x = yb * ip;
+      a.P[jb[v]] = (T)x;
+      acc[0] += yb * x;
+      acc[1] += ((double)gp0[v] + beta * syp) * x;
+    }
+    if (base + stride < np) load(base + stride);
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
+}
+
+template <typename T, bool BATCH>
+__global__ __launch_bounds__(kNT) void k_rb_red_dir_pair(IterArgs<T> a0) {
+  constexpr int V = Vpair<T, FM_VPAIR_R32>::v;
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = a.Gc;
+  const T *__restrict__ zp = a.Zp;
+  T *__restrict__ zo = a.Zc;
+  const T *__restrict__ f = a.Fc;
+  const T *__restrict__ p = a.P;
+  const Offs of(g);
+  const int np = (int)(g.n >> 1), chunk = kNT * V, stride = vw.nb * chunk;
+  uint32_t cb[V], cr[V];
+  bool fbk[V];
+  T gr[V], zr[V], fr[V], dr[V], pb[V], zb[V], db[V], pn[V][6], zn[V][6], fn[V][6];
+  double hr[V];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int q = b + v * kNT + (int)threadIdx.x;
+      const int j0 = 2 * (q < np ? q : np - 1);
+      const uint32_t c2 = *reinterpret_cast<const uint16_t *>(a.code + j0);
+      const uint32_t cA = q < np ? (c2 & 0xffu) : 0u, cB = q < np ? (c2 >> 8) : 0u;
+      const bool fb = first_is_black(cA, cB);
+      const int jrv = fb ? j0 + 1 : j0;
+      fbk[v] = fb;
+      cb[v] = fb ? cA : cB;
+      cr[v] = fb ? cB : cA;
+      const Duo<T> z2 = ld_duo(zp, j0), d2 = ld_duo(a.D, j0), p2 = ld_duo(p, j0);
+      zr[v] = fb ? z2.v1 : z2.v0;
+      zb[v] = fb ? z2.v0 : z2.v1;
+      dr[v] = fb ? d2.v1 : d2.v0;
+      db[v] = fb ? d2.v0 : d2.v1;
+      pb[v] = fb ? p2.v0 : p2.v1;
+      gr[v] = gg[jrv];
+      fr[v] = f[jrv];
+      hr[v] = a.hinv[jrv];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        pn[v][k] = p[jrv + of.o[k]];
+        zn[v][k] = zp[jrv + of.o[k]];
+        fn[v][k] = f[jrv + of.o[k]];
+      }
+    }
+  };
+  int base = vw.bl * chunk;
+  if (base < np) load(base);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  const T mu = (T)st.mu;
+  double acc[3] = {0.0, 0.0, 0.0};
+  int bad = 0;
+  for (; base < np; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int q = base + v * kNT + (int)threadIdx.x;
+      if (q >= np) continue;
+      T zrv = T(0), zbv = T(0);
+      const uint32_t cv = cr[v];
+      if (cv & NB_SELF) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (has_nb(cv, k)) s += (double)pn[v][k];
+        const double ip = hr[v];
+        if (!(ip > 0.0)) bad = 1;
+        const T pj = (T)((double)gr[v] * ip + beta * s * ip);
+        zrv = -pj + mu * zr[v];
+        acc[2] += (double)zrv * (double)zrv * (double)dr[v];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (has_nb(cv, k)) {
+            const double dz = (double)(zrv - (-pn[v][k] + mu * zn[v][k]));
+            acc[0] += dz * (double)(fr[v] - fn[v][k]);
+            acc[1] += dz * dz;
+          }
+      }
+      if (cb[v] & NB_SELF) {
+        zbv = -pb[v] + mu * zb[v];
+        acc[2] += (double)zbv * (double)zbv * (double)db[v];
+      }
+      Duo<T> out;
+      out.v0 = fbk[v] ? zbv : zrv;
+      out.v1 = fbk[v] ? zrv : zbv;
+      *reinterpret_cast<Duo<T> *>(zo + 2 * q) = out;
+    }
+    if (base + stride < np) load(base + stride);
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<3, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DIR, vw.nb, vw.leader);
 }
 
 // Diagonal (P = diag H) or identity preconditioner.
@@ -482,7 +832,7 @@ __global__ __launch_bounds__(kNT) void k_dir(IterArgs<T> a0) {
 // kernel applies alpha <- alpha - (S1 + beta A + alpha beta B) / (S2 + beta B).
 template <typename T, int LMAX, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a0) {
-  constexpr int V = Vpt<T>::v;
+  constexpr int V = Vk<T, FM_V_MLS>::v;
   const VolView vw = vol_view<BATCH>(a0);
   const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;

@@ -30,8 +30,7 @@ def _gpu():
 TE = [0.0, 1.5e-3, 4.0e-3]
 
 
-def uneven_volumes():
-    shapes = [(13, 9, 7), (20, 17, 11), (6, 5, 4), (24, 8, 16)]
+def uneven_volumes(shapes=((13, 9, 7), (20, 17, 11), (6, 5, 4), (24, 8, 16))):
     betas = [0.2, 0.05, 0.1, 2.0 ** -4]
     vols = []
     for k, (shp, b) in enumerate(zip(shapes, betas)):
@@ -76,6 +75,28 @@ def test_batch_matches_oracle_and_single(prec, precond):
         fs, ts = fmap.solve_volume(vol, P, fmap.REDBLACK, precond)
         if prec == "f64":
             assert rms(fb[v] - ref["f"], m) < 1e-3, v
+            np.testing.assert_array_equal(tb[v][:-1, 3], ref["trace"][:-1, 3])
+            assert np.abs(fb[v] - fs).max() < 1e-9, v
+            np.testing.assert_allclose(tb[v][:, 0], ts[:, 0], rtol=1e-12)
+        else:
+            assert rms(fb[v] - ref["f"], m) < 0.05, v
+            assert rms(fb[v] - fs, m) < 0.01, v
+        assert np.all(fb[v][~m] == 0)
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+def test_batch_even_columns(prec):
+    """Every column length even: the batch takes the pair-mapped red-black passes."""
+    vols = uneven_volumes(((12, 9, 8), (20, 17, 10), (6, 5, 4), (24, 8, 16)))
+    P = fmap.F64 if prec == "f64" else fmap.MIX
+    say("batch, even columns, %s" % prec)
+    fb, tb, _ = run_batch(vols, P)
+    for v, vol in enumerate(vols):
+        m = vol.mask.astype(bool)
+        ref = O.run_volume(vol, O.REDBLACK, O.IC0)
+        fs, ts = fmap.solve_volume(vol, P, fmap.REDBLACK)
+        if prec == "f64":
+            assert rms(fb[v] - ref["f"], m) < 1e-6, v
             np.testing.assert_array_equal(tb[v][:-1, 3], ref["trace"][:-1, 3])
             assert np.abs(fb[v] - fs).max() < 1e-9, v
             np.testing.assert_allclose(tb[v][:, 0], ts[:, 0], rtol=1e-12)
