@@ -55,7 +55,7 @@ typedef enum {
   FM_ERR_NOT_PD = 5,    /* an IC(0) pivot was not positive (singular Hessian model) */
   FM_ERR_NONFINITE = 6, /* NaN/Inf met in the iteration */
   FM_ERR_STATE = 7,     /* call out of order (e.g. fm_eval before fm_setup) */
-  FM_ERR_TIMEOUT = 8    /* a device-side wait of the wavefront sweep exceeded its bound */
+  FM_ERR_TIMEOUT = 8    /* a device-side wait (wavefront sweep, resident grid barrier) exceeded its bound */
 } fm_status;
 
 typedef enum { FM_FIELDMAP = 0, FM_WATERFAT = 1 } fm_model;
@@ -159,6 +159,26 @@ fm_status fm_iterate(fm_plan *plan, int32_t niter, double *f_out, hipStream_t st
  * the stream.  Also returns the device status word of the solve (FM_OK,
  * FM_ERR_NOT_PD or FM_ERR_NONFINITE). */
 fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
+
+/* Schedule of the iteration loop (Sec. III Algorithm; the arithmetic is the
+ * same in both).  STREAM: one launch per pass, the loop replayed from a HIP
+ * graph.  RESIDENT: one cooperative launch for all iterations of a call; each
+ * workgroup keeps the per-voxel state of a tile of whole columns in
+ * registers and the passes are separated by grid barriers.  RESIDENT needs
+ * MIX precision, red-black IC(0), 2 <= necho <= 4, and tiles of at most 2048
+ * voxels that can all be resident on the device at once (for example
+ * 128x128x64: 512 tiles of 8x4 columns), and an even nz.  AUTO (the default)
+ * takes RESIDENT when the plan qualifies and has at least 1024 voxels per
+ * compute unit (smaller volumes run faster streamed). */
+enum { FM_SCHED_AUTO = 0, FM_SCHED_STREAM = 1, FM_SCHED_RESIDENT = 2 };
+
+/* Select the schedule for later fm_solve / fm_iterate calls.  FM_ERR_ARG for
+ * an unknown value or RESIDENT on a plan that does not qualify. */
+fm_status fm_set_schedule(fm_plan *plan, int32_t sched);
+
+/* The schedule the next fm_solve will use (FM_SCHED_STREAM or
+ * FM_SCHED_RESIDENT), host int32. */
+fm_status fm_get_schedule(fm_plan *plan, int32_t *sched);
 
 /* Device status of the work enqueued so far on this plan (synchronises the
  * stream): FM_OK, or the first device-side error of the last solve
@@ -264,11 +284,13 @@ enum {
   FM_K_DOTS = 3,      /* conjugacy dot products                             */
   FM_K_DIR = 4,       /* direction and line-search setup                    */
   FM_K_MLS = 5,       /* further line-search passes                         */
-  FM_NK = 6
+  FM_K_RESIDENT = 6,  /* resident schedule: one launch for all the iterations */
+  FM_NK = 7
 };
 
 /* Measurement: run niter further iterations from the plan's current state
- * (as fm_iterate, but launching kernel by kernel instead of from the graph)
+ * (as fm_iterate, but launching kernel by kernel instead of from the graph;
+ * the resident schedule runs them as one launch of class FM_K_RESIDENT)
  * with a HIP event pair around every launch on the given stream, and return
  * per kernel class the summed duration in milliseconds and the number of
  * launches (host float64 ms[FM_NK], host int32 launches[FM_NK]).  The map is

@@ -19,6 +19,7 @@
 #include "fm_stream.hpp"
 #include "fm_natural.hpp"
 #include "fm_adjoint.hpp"
+#include "fm_resident.hpp"
 
 using fm::kBlock;
 using fm::kMaxGrid;
@@ -106,6 +107,14 @@ struct fm_plan {
   double *a_hinv = nullptr, *a_ipiv = nullptr, *a_part = nullptr;
   fm::State *aS = nullptr;
   int32_t *a_status = nullptr;
+  // resident schedule (one cooperative launch for many iterations)
+  int32_t sched = FM_SCHED_AUTO;
+  bool res_ok = false;         // the plan qualifies (MIX, red-black IC(0), <= 4 echoes, tiles fit)
+  bool res_auto = false;       // and FM_SCHED_AUTO takes it (large enough volume)
+  fm::ResTile res_tile{};
+  int res_grid = 0;
+  double *res_part = nullptr;  // [2][kMaxK][res_grid]
+  uint32_t *res_bar = nullptr; // barrier counters
 };
 
 namespace {
@@ -504,8 +513,110 @@ void free_plan(fm_plan *p) {
 // Run niter iterations as one graph launch.  The graph for the current chain
 // parity and niter is captured on first use and replayed afterwards (its
 // launches occupy the same chain positions modulo 2).
+bool use_resident(const fm_plan *p) {
+  return p->res_ok && (p->sched == FM_SCHED_RESIDENT || (p->sched == FM_SCHED_AUTO && p->res_auto));
+}
+
+size_t res_bar_bytes(const fm_plan *p) { return sizeof(uint32_t) * (fm::kResGroups * 32 + 32 + (size_t)p->res_grid); }
+
+template <int LR>
+void *resident_kernel() {
+  return (void *)fm::k_resident<LR>;
+}
+
+void *resident_kernel_for(int necho) {
+  return necho <= 2 ? resident_kernel<2>() : (necho == 3 ? resident_kernel<3>() : resident_kernel<4>());
+}
+
+// niter iterations in one cooperative launch of the resident schedule.
+fm_status run_resident(fm_plan *p, int niter, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  fm::ResArgs a{};
+  a.geo = p->geo;
+  a.tile = p->res_tile;
+  a.beta = p->prm.beta;
+  a.dat = (const fm::T2<float> *)p->dat;
+  a.code = p->code;
+  a.pairs = (const fm::PairC<float> *)p->pairs;
+  for (int i = 0; i < 2; ++i) {
+    a.F[i] = (float *)p->F[i];
+    a.Z[i] = (float *)p->Z[i];
+    a.G[i] = (float *)p->G[i];
+  }
+  a.P = (float *)p->P;
+  a.hinv = p->hinv;
+  a.par0 = (int32_t)(p->iter_host & 1);
+  a.niter = niter;
+  a.nparts_in = p->last_nparts;
+  a.nvals_in = p->last_nvals;
+  const uint64_t q = p->q;
+  a.sin = p->S + (q & 1);
+  a.sout = p->S + ((q + 1) & 1);
+  a.pin = p->part + (size_t)(q & 1) * p->part_rows * kMaxK;
+  a.part = p->res_part;
+  a.bar = p->res_bar;
+  a.status = p->status;
+  a.trace = p->trace;
+  FM_HIP(hipMemsetAsync(p->res_bar, 0, res_bar_bytes(p), s));
+  if (e0) FM_HIP(hipEventRecord(e0, s));
+  void *args[] = {&a};
+  hipError_t err = hipLaunchCooperativeKernel(resident_kernel_for(p->prm.necho), dim3(p->res_grid),
+                                              dim3(fm::kResNT), args, 0, s);
+  if (err != hipSuccess) return fail(FM_ERR_HIP, std::string("resident launch: ") + hipGetErrorString(err));
+  if (e1) FM_HIP(hipEventRecord(e1, s));
+  p->q += 1;
+  p->iter_host += niter;
+  set_parts(p, 0, 0);
+  return FM_OK;
+}
+
+// Tiles of whole columns for the resident schedule: at most kResTile voxels
+// each, all resident at once.  Every barrier waits for the most loaded CU, so
+// the tiling minimises the voxels of the busiest CU (tiles per CU rounded up
+// times voxels per tile), then the number of tiles.  False if the plan does
+// not qualify.  res_auto: the volume is large enough for the resident
+// schedule to beat streaming (measured: below about 1024 voxels per CU the
+// fixed cost of its grid barriers dominates).
+bool plan_resident(fm_plan *p) {
+  const fm_params &q = p->prm;
+  if (!p->mix || q.precond != FM_PRECOND_IC0 || q.ordering != FM_ORDER_REDBLACK || q.necho < 2 || q.necho > 4)
+    return false;
+  // voxel pairs (z even, z odd) of one column: one red and one black voxel
+  if (q.nz > fm::kResTile || q.nz % 2) return false;
+  int ncu = 0, per = 0, coop = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu < 1)
+    return false;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device) != hipSuccess || !coop) return false;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, resident_kernel_for(q.necho), fm::kResNT, 0) != hipSuccess ||
+      per < 1)
+    return false;
+  const long maxblocks = (long)per * ncu;
+  const int C = fm::kResTile / q.nz;  // columns per tile, at most
+  long best_cost = -1, best_nt = 0;
+  for (int tx = 1; tx <= C && tx <= q.nx; ++tx)
+    for (int ty = 1; tx * ty <= C && ty <= q.ny; ++ty) {
+      // at most one neighbour across a tile face per axis: tiles at least 2 wide (or the whole axis)
+      if ((tx < 2 && q.nx > 1) || (ty < 2 && q.ny > 1)) continue;
+      const long nt = (long)((q.nx + tx - 1) / tx) * ((q.ny + ty - 1) / ty);
+      if (nt > maxblocks) continue;
+      const long cost = ((nt + ncu - 1) / ncu) * (long)tx * ty * q.nz;
+      if (best_cost < 0 || cost < best_cost || (cost == best_cost && nt < best_nt)) {
+        best_cost = cost;
+        best_nt = nt;
+        p->res_tile.tx = tx;
+        p->res_tile.ty = ty;
+        p->res_tile.ntx = (q.nx + tx - 1) / tx;
+        p->res_tile.nty = (q.ny + ty - 1) / ty;
+      }
+    }
+  if (best_cost < 0) return false;
+  p->res_grid = (int)best_nt;
+  p->res_auto = p->n >= 1024L * ncu;
+  return true;
+}
+
 fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
   if (niter <= 0) return FM_OK;
+  if (use_resident(p)) return run_resident(p, niter, s);
   const std::vector<int64_t> key = {(int64_t)(p->q & 1), niter, p->iter_host & 1, p->last_nparts, p->last_nvals};
   auto it = p->graphs.find(key);
   if (it == p->graphs.end()) {
@@ -858,6 +969,11 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   FM_ALLOC(p->status, sizeof(int32_t));
   FM_ALLOC(p->trace, trace_bytes);
   FM_ALLOC(p->f0buf, sizeof(double) * n);
+  p->res_ok = plan_resident(p);
+  if (p->res_ok) {
+    FM_ALLOC(p->res_part, sizeof(double) * fm::kResSlots * kMaxK * (size_t)p->res_grid);
+    FM_ALLOC(p->res_bar, res_bar_bytes(p));
+  }
   if (prm->model == FM_WATERFAT) {
     FM_ALLOC(p->rho, sizeof(double) * n);
     FM_ALLOC(p->gabs, sizeof(double) * L * L);
@@ -1056,8 +1172,14 @@ fm_status fm_time_kernels(fm_plan *p, int32_t niter, double *ms, int32_t *launch
     launches[k] = 0;
   }
   Recorder rec;
-
-  for (int i = 0; i < niter; ++i) {
+  if (use_resident(p) && niter > 0) {
+    hipEvent_t e0, e1;
+    rec.pair(FM_K_RESIDENT, &e0, &e1);
+    if (rec.err != hipSuccess) return fail(FM_ERR_HIP, std::string("event create: ") + hipGetErrorString(rec.err));
+    fm_status st = run_resident(p, niter, s, e0, e1);
+    if (st) return st;
+  }
+  for (int i = 0; i < niter && !use_resident(p); ++i) {
     fm_status st = dispatch<OpIterationTimed>(p, s, &rec);
     if (st) return st;
     if (rec.err != hipSuccess) return fail(FM_ERR_HIP, std::string("event record: ") + hipGetErrorString(rec.err));
@@ -1140,6 +1262,25 @@ fm_status fm_plan_status(fm_plan *p, hipStream_t s) {
   fm_status rs = read_status(p, s, &status);
   if (rs) return rs;
   if (status) return fail((fm_status)status, "the last solve reported a device-side error");
+  return FM_OK;
+}
+
+fm_status fm_set_schedule(fm_plan *p, int32_t sched) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (sched != FM_SCHED_AUTO && sched != FM_SCHED_STREAM && sched != FM_SCHED_RESIDENT)
+    return fail(FM_ERR_ARG, "unknown schedule");
+  if (sched == FM_SCHED_RESIDENT && !p->res_ok)
+    return fail(FM_ERR_ARG, "the plan does not qualify for the resident schedule");
+  p->sched = sched;
+  return FM_OK;
+}
+
+fm_status fm_get_schedule(fm_plan *p, int32_t *sched) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!sched) return fail(FM_ERR_ARG, "sched must not be NULL");
+  *sched = use_resident(p) ? FM_SCHED_RESIDENT : FM_SCHED_STREAM;
   return FM_OK;
 }
 

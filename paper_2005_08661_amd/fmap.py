@@ -30,9 +30,11 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "invalid shape", 3: "device allocat
 
 EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval", "fm_precondition",
             "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
-            "fm_adjoint", "fm_set_beta", "fm_components", "fm_plan_status", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
+            "fm_adjoint", "fm_set_beta", "fm_components", "fm_plan_status", "fm_set_schedule",
+            "fm_get_schedule", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
             "fm_batch_get_trace", "fm_batch_set_grid", "fm_batch_autotune", "fm_status_string", "fm_last_error"]
-KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls"]
+KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls", "resident"]
+SCHED_AUTO, SCHED_STREAM, SCHED_RESIDENT = 0, 1, 2
 
 
 class FmapError(RuntimeError):
@@ -77,6 +79,8 @@ def lib():
         L.fm_set_beta.argtypes = [vp, C.c_double]
         L.fm_components.argtypes = [vp, vp, vp, vp, vp, vp]
         L.fm_plan_status.argtypes = [vp, vp]
+        L.fm_set_schedule.argtypes = [vp, C.c_int32]
+        L.fm_get_schedule.argtypes = [vp, C.POINTER(C.c_int32)]
         L.fm_batch_create.argtypes = [C.c_int32, vp, C.POINTER(vp)]
         L.fm_batch_destroy.argtypes = [vp]
         L.fm_batch_solve.argtypes = [vp, vp, vp, vp, vp, vp, vp]
@@ -262,6 +266,16 @@ class Plan:
     def status(self):
         """Raise FmapError if the work enqueued on this plan reported a device-side error."""
         _check(lib().fm_plan_status(self._h, _stream()))
+
+    def set_schedule(self, sched):
+        """SCHED_AUTO, SCHED_STREAM or SCHED_RESIDENT for later solves (the arithmetic is the same)."""
+        _check(lib().fm_set_schedule(self._h, C.c_int32(int(sched))))
+
+    def schedule(self):
+        """The schedule the next solve uses: SCHED_STREAM or SCHED_RESIDENT."""
+        v = C.c_int32(0)
+        _check(lib().fm_get_schedule(self._h, C.byref(v)))
+        return v.value
 
     def time_kernels(self, niter):
         """Per kernel class: (total ms, launches) over niter event-timed iterations."""
