@@ -3,7 +3,9 @@
 A step is one full solve of the 128x128x64, 8-coil, 3-echo field-map problem
 (coil combination, the initial map of eq. (w0) and 100 NCG iterations with
 IC(0) and three line-search steps each) on inputs already resident in device
-memory.  value = in-mask voxels x iterations / second, whole job.
+memory, with the plan's default schedule (resident at this size; the
+streaming schedule is timed beside it).  value = in-mask voxels x iterations
+/ second, whole job.
 
 Progress goes to stderr; stdout carries exactly one JSON line.
 """
@@ -56,7 +58,21 @@ def bytes_per_voxel(kclass, precision, L, ordering, precond):
     return 0
 
 
-KERNEL_SYMBOL = {"grad": "k_grad", "mls": "k_mls", "dir": "k_dir", "precond_a": None, "precond_b": None}
+def iteration_bytes_per_voxel(precision, L, ordering, precond, nmls):
+    """Algorithmic bytes per voxel of one whole iteration: the passes of the
+    streaming schedule (the resident schedule computes the same passes)."""
+    rb = precond == "ic0" and ordering == "redblack"
+    b = bytes_per_voxel("grad", precision, L, ordering, precond) + bytes_per_voxel("precond_a", precision, L, ordering,
+                                                                                  precond)
+    if precond == "ic0":
+        b += bytes_per_voxel("precond_b", precision, L, ordering, precond)
+    if not rb:
+        b += bytes_per_voxel("dir", precision, L, ordering, precond)
+    return b + (nmls - 1) * bytes_per_voxel("mls", precision, L, ordering, precond)
+
+
+KERNEL_SYMBOL = {"grad": "k_grad", "mls": "k_mls", "dir": "k_dir", "precond_a": None, "precond_b": None,
+                 "resident": "k_resident"}
 
 
 def kernel_symbol(kclass, ordering, precond, nz):
@@ -291,7 +307,7 @@ def main():
     y, s, m = fmap.to_device(vol)
     plan = fmap.Plan(fmap.params_for(vol, precision=prec, ordering=order, precond=pc))
     out = torch.zeros(shape, dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
+    stream_h = torch.cuda.current_stream()
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
@@ -309,32 +325,59 @@ def main():
     log("step %.3f ms (wall %.3f ms), %.3e voxel-iterations/s" % (ms_step, wall * 1e3 / args.steps, value))
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    # iteration loop alone (graph replays), from the solved state
-    ev0.record(stream)
+    # iteration loop alone (graph replays or one resident launch), from the solved state
+    ev0.record(stream_h)
     plan.iterate(niter, out=out)
-    ev1.record(stream)
+    ev1.record(stream_h)
     torch.cuda.synchronize()
     ms_loop = ev0.elapsed_time(ev1)
     loop_rate = nmask * niter / (ms_loop * 1e-3)
 
     # per-kernel durations from HIP events on the launch stream
-    kt = plan.time_kernels(args.kernel_iters)
     L = vol.necho
-    kinfo = {}
-    for k, (ms, nl) in kt.items():
-        if nl == 0:
-            continue
-        b = bytes_per_voxel(k, args.precision, L, args.ordering, args.precond) * nmask
-        avg = ms / nl
-        kinfo[k] = dict(avg_us=avg * 1e3, launches=nl, total_ms=ms, bytes=b,
-                        gbs=b / (avg * 1e-3) / 1e9 if avg > 0 else 0.0)
+    it_bytes_vox = iteration_bytes_per_voxel(args.precision, L, args.ordering, args.precond, vol.nmls)
+
+    def kernel_table(kt, iters):
+        kinfo = {}
+        for k, (ms, nl) in kt.items():
+            if nl == 0:
+                continue
+            if k == "resident":  # one launch runs all the iterations of the call
+                b = it_bytes_vox * nmask * iters / nl
+            else:
+                b = bytes_per_voxel(k, args.precision, L, args.ordering, args.precond) * nmask
+            avg = ms / nl
+            kinfo[k] = dict(avg_us=avg * 1e3, launches=nl, total_ms=ms, bytes=b,
+                            gbs=b / (avg * 1e-3) / 1e9 if avg > 0 else 0.0)
+        return kinfo
+
+    schedule = "resident" if plan.schedule() == fmap.SCHED_RESIDENT else "stream"
+    # the resident kernel is timed over a whole solve's iteration count, like the launches of the solves
+    kiters = niter if schedule == "resident" else args.kernel_iters
+    kinfo = kernel_table(plan.time_kernels(kiters), kiters)
     dom = max(kinfo, key=lambda k: kinfo[k]["total_ms"])
-    iter_bytes = sum(bytes_per_voxel(k, args.precision, L, args.ordering, args.precond) * kinfo[k]["launches"]
-                     for k in kinfo) / args.kernel_iters * nmask
+    iter_bytes = it_bytes_vox * nmask
     iter_frac = iter_bytes / (ms_loop * 1e-3 / niter) / (HBM_PEAK_GBS * 1e9)
     for k, v in kinfo.items():
         log("  %-10s %9.2f us/launch  %8.1f GB/s  (%d launches)" % (k, v["avg_us"], v["gbs"], v["launches"]))
-    log("loop %.3f ms for %d iterations; whole-iteration %.1f%% of HBM peak" % (ms_loop, niter, 100 * iter_frac))
+    log("%s schedule: loop %.3f ms for %d iterations; whole-iteration %.1f%% of HBM peak (algorithmic bytes)" % (
+        schedule, ms_loop, niter, 100 * iter_frac))
+    stream = None
+    if schedule == "resident":
+        # the streaming schedule on the same plan, for comparison
+        plan.set_schedule(fmap.SCHED_STREAM)
+        ms_s = time_solve(plan, fmap, y, s, m, out, max(1, args.steps // 2), torch)
+        ev0.record(stream_h)
+        plan.iterate(niter, out=out)
+        ev1.record(stream_h)
+        torch.cuda.synchronize()
+        ms_loop_s = ev0.elapsed_time(ev1)
+        ks = kernel_table(plan.time_kernels(args.kernel_iters), args.kernel_iters)
+        plan.set_schedule(fmap.SCHED_AUTO)
+        stream = {"ms_per_step": ms_s, "loop_ms": ms_loop_s, "value": nmask * niter / (ms_s * 1e-3),
+                  "hbm_frac": iter_bytes / (ms_loop_s * 1e-3 / niter) / (HBM_PEAK_GBS * 1e9),
+                  "kernels_us": {k: round(v["avg_us"], 3) for k, v in ks.items()}}
+        log("stream schedule: %.3f ms per step, loop %.3f ms" % (ms_s, ms_loop_s))
 
     natural = None
     if not args.no_natural and args.ordering == "redblack" and args.precond == "ic0":
@@ -421,11 +464,13 @@ def main():
             "traffic": measured_traffic(dom, args),
         },
         "iteration": {
+            "schedule": schedule,
             "loop_ms": ms_loop,
             "loop_voxel_iterations_per_s": loop_rate,
             "bytes_per_iteration": iter_bytes,
             "hbm_frac": iter_frac,
             "kernels_us": {k: round(v["avg_us"], 3) for k, v in kinfo.items()},
+            "stream_schedule": stream,
         },
         "final_cost": float(tr[-1, 0]),
         "natural_order": natural,

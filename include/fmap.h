@@ -167,7 +167,7 @@ fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
  * registers and the passes are separated by grid barriers.  RESIDENT needs
  * MIX precision, red-black IC(0), 2 <= necho <= 4, and tiles of at most 2048
  * voxels that can all be resident on the device at once (for example
- * 128x128x64: 512 tiles of 8x4 columns), and an even nz.  AUTO (the default)
+ * 128x128x64: 512 tiles of 4x8 columns), and an even nz.  AUTO (the default)
  * takes RESIDENT when the plan qualifies and has at least 1024 voxels per
  * compute unit (smaller volumes run faster streamed). */
 enum { FM_SCHED_AUTO = 0, FM_SCHED_STREAM = 1, FM_SCHED_RESIDENT = 2 };

@@ -572,7 +572,7 @@ fm_status run_resident(fm_plan *p, int niter, hipStream_t s, hipEvent_t e0 = nul
 // Tiles of whole columns for the resident schedule: at most kResTile voxels
 // each, all resident at once.  Every barrier waits for the most loaded CU, so
 // the tiling minimises the voxels of the busiest CU (tiles per CU rounded up
-// times voxels per tile), then the number of tiles.  False if the plan does
+// times voxels per tile), then the number of tiles, then the tile perimeter.  False if the plan does
 // not qualify.  res_auto: the volume is large enough for the resident
 // schedule to beat streaming (measured: below about 1024 voxels per CU the
 // fixed cost of its grid barriers dominates).
@@ -599,7 +599,8 @@ bool plan_resident(fm_plan *p) {
       const long nt = (long)((q.nx + tx - 1) / tx) * ((q.ny + ty - 1) / ty);
       if (nt > maxblocks) continue;
       const long cost = ((nt + ncu - 1) / ncu) * (long)tx * ty * q.nz;
-      if (best_cost < 0 || cost < best_cost || (cost == best_cost && nt < best_nt)) {
+      const bool squarer = tx + ty < p->res_tile.tx + p->res_tile.ty;  // shorter perimeter: less halo
+      if (best_cost < 0 || cost < best_cost || (cost == best_cost && (nt < best_nt || (nt == best_nt && squarer)))) {
         best_cost = cost;
         best_nt = nt;
         p->res_tile.tx = tx;

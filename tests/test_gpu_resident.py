@@ -180,7 +180,7 @@ def test_resident_reports_not_pd():
 
 
 def test_resident_full_size_and_kernel_timing():
-    """128x128x64, 8 coils: 512 tiles of 8x4 columns, two per CU; 20 iterations against streaming, then
+    """128x128x64, 8 coils: 512 tiles of 4x8 columns, two per CU; 20 iterations against streaming, then
     the timing entry reports one resident launch."""
     vol = synth.mid_fieldmap()
     say("resident full size 128x128x64")
