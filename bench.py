@@ -58,9 +58,21 @@ def bytes_per_voxel(kclass, precision, L, ordering, precond):
     return 0
 
 
+def alg_bytes_per_voxel(precision, L, nmls):
+    """B_alg: the minimum global sweeps the method's data dependencies force per
+    voxel and NCG iteration, independent of how the kernels are split: forward
+    sweep (echo data, f, z_prev in; f, g, D, pivot (FP64), x out), backward
+    sweep (x, pivot, g, g_prev, z_prev in; p out), direction and line-search
+    setup (p, z_prev, f, D in; z out), and nmls - 1 line-search passes (echo
+    data, f, z).  MIX, L = 3, nmls = 3: 168 B."""
+    if precision == "mix":
+        return (8 * L + 32) + 28 + 20 + (nmls - 1) * (8 * L + 8)
+    return (16 * L + 56) + 48 + 40 + (nmls - 1) * (16 * L + 16)
+
+
 def iteration_bytes_per_voxel(precision, L, ordering, precond, nmls):
-    """Algorithmic bytes per voxel of one whole iteration: the passes of the
-    streaming schedule (the resident schedule computes the same passes)."""
+    """Bytes per voxel of one whole iteration as this implementation's passes
+    move them (sum of the per-pass model above)."""
     rb = precond == "ic0" and ordering == "redblack"
     b = bytes_per_voxel("grad", precision, L, ordering, precond) + bytes_per_voxel("precond_a", precision, L, ordering,
                                                                                   precond)
@@ -247,6 +259,38 @@ def bench_waterfat(args, fmap, synth, torch):
     return res
 
 
+def bench_large(args, fmap, synth, torch, prec):
+    """256x256x128 (8.4 M voxels, working set well above the 256 MB Infinity Cache): the field-map
+    problem of the benchmark at eight times the size, a true HBM measurement.  2 coils (the coil
+    count only changes the setup, not the iteration)."""
+    shape = (256, 256, 128)
+    log("large: generating %s" % (shape,))
+    vol = synth.fieldmap_volume(shape, 2, [0.0, 2.2e-3, 4.4e-3], 2.0 ** -4, 100, synth.SEED_BASE + 1, 8, 250.0,
+                                True, 30.0, mask="full", name="fieldmap 256x256x128 2 coils 3 echoes")
+    y, s, m = fmap.to_device(vol)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=fmap.REDBLACK)) as plan:
+        sched = "resident" if plan.schedule() == fmap.SCHED_RESIDENT else "stream"
+        plan.solve(y, s, m, out=out)
+        torch.cuda.synchronize()
+        ms_solve = time_solve(plan, fmap, y, s, m, out, 1, torch)
+        ev0.record(stream)
+        plan.iterate(vol.niter, out=out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_loop = ev0.elapsed_time(ev1)
+        n = plan.mask_count()
+    b = alg_bytes_per_voxel(args.precision, vol.necho, vol.nmls) * n
+    res = {"grid": list(shape), "voxels": n, "schedule": sched, "ms_per_solve": ms_solve, "loop_ms": ms_loop,
+           "loop_voxel_iterations_per_s": n * vol.niter / (ms_loop * 1e-3),
+           "hbm_frac": b / (ms_loop * 1e-3 / vol.niter) / (HBM_PEAK_GBS * 1e9)}
+    log("large: %s schedule, solve %.2f ms, loop %.2f ms (%.3e voxel-iterations/s, %.1f%% of HBM peak)" % (
+        sched, ms_solve, ms_loop, res["loop_voxel_iterations_per_s"], 100 * res["hbm_frac"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,6 +310,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-volume batched comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the implicit-adjoint timing")
     ap.add_argument("--no-waterfat", action="store_true", help="skip the 192x192x64 water-fat solve")
+    ap.add_argument("--no-large", action="store_true", help="skip the 256x256x128 HBM-sized field-map loop")
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the time-to-accuracy comparison of the preconditioners")
     args = ap.parse_args()
@@ -335,7 +380,10 @@ def main():
 
     # per-kernel durations from HIP events on the launch stream
     L = vol.necho
-    it_bytes_vox = iteration_bytes_per_voxel(args.precision, L, args.ordering, args.precond, vol.nmls)
+    # the roofline of the whole iteration and of the resident kernel uses B_alg; the per-pass model
+    # (slightly smaller for red-black IC(0), whose fused passes skip some sweeps) is reported beside it
+    it_bytes_vox = alg_bytes_per_voxel(args.precision, L, vol.nmls)
+    pass_bytes_vox = iteration_bytes_per_voxel(args.precision, L, args.ordering, args.precond, vol.nmls)
 
     def kernel_table(kt, iters):
         kinfo = {}
@@ -418,6 +466,10 @@ def main():
     if not args.no_waterfat:
         waterfat = bench_waterfat(args, fmap, synth, torch)
 
+    large = None
+    if not args.no_large and args.shape == "128,128,64":
+        large = bench_large(args, fmap, synth, torch, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -468,12 +520,15 @@ def main():
             "loop_ms": ms_loop,
             "loop_voxel_iterations_per_s": loop_rate,
             "bytes_per_iteration": iter_bytes,
+            "alg_bytes_per_voxel": it_bytes_vox,
+            "pass_model_bytes_per_voxel": pass_bytes_vox,
             "hbm_frac": iter_frac,
             "kernels_us": {k: round(v["avg_us"], 3) for k, v in kinfo.items()},
             "stream_schedule": stream,
         },
         "final_cost": float(tr[-1, 0]),
         "natural_order": natural,
+        "large_256x256x128": large,
         "convergence": convergence,
         "adjoint": adjoint,
         "batched": batched,
