@@ -14,7 +14,8 @@
  *     (the ordered-pair sum counts each unordered pair twice because Gamma
  *     is Hermitian, hence the weight 2|R_mn|) (Sec. III-B eqs. (ls_grad),
  *     (ls_huber), (inner_funs));
- *   - the first-order finite-difference regulariser (Sec. II eq. (cost));
+ *   - the first- or second-order finite-difference regulariser (Sec. II
+ *     eq. (cost));
  *   - IC(0) of H = D + beta C^T C and the two triangular solves
  *     (Sec. III-B eqs. (precon_hess), (precon));
  *   - preconditioned NCG with Polak-Ribiere conjugacy and the monotone line
@@ -36,6 +37,9 @@
  *   R11 water-fat sweep over [-|df|/2, |df|/2], 100 values, first minimum.
  *   R12 PWLS by plain CG from the voxelwise estimate.
  *   R14 angle(0) = 0; zero data gives a zero data term.
+ *   R20 second-order C: a row f_{j-e} - 2 f_j + f_{j+e} for every voxel j and
+ *      axis e whose three voxels are inside the volume and the mask (R5 for
+ *      second differences); no spatial weights.
  */
 #include "fmo.h"
 
@@ -69,6 +73,31 @@ static int neighbours(const fmo_problem *pb, const uint8_t *mask, int64_t j, int
   if (z > 0 && mask[j - 1]) nb[c++] = j - 1;
   if (z < nz - 1 && mask[j + 1]) nb[c++] = j + 1;
   return c;
+}
+
+static int second_order(const fmo_problem *pb) { return pb->reg_order == 2; }
+
+/* Coordinates and strides. */
+static void coords(const fmo_problem *pb, int64_t j, int64_t c[3]) {
+  const int64_t nz = pb->nz, ny = pb->ny;
+  c[2] = j % nz;
+  c[1] = (j / nz) % ny;
+  c[0] = j / (ny * nz);
+}
+
+static int64_t stride(const fmo_problem *pb, int a) {
+  return a == 0 ? (int64_t)pb->ny * pb->nz : (a == 1 ? (int64_t)pb->nz : 1);
+}
+
+static int64_t extent(const fmo_problem *pb, int a) { return a == 0 ? pb->nx : (a == 1 ? pb->ny : pb->nz); }
+
+/* Second order: does the row centred at voxel j along axis a exist? */
+static int row2(const fmo_problem *pb, const uint8_t *mask, int64_t j, int a) {
+  int64_t c[3];
+  coords(pb, j, c);
+  if (c[a] < 1 || c[a] > extent(pb, a) - 2) return 0;
+  const int64_t s = stride(pb, a);
+  return mask[j] && mask[j - s] && mask[j + s];
 }
 
 /* Position of voxel j in the elimination order. */
@@ -287,6 +316,20 @@ int fmo_data_term(const fmo_problem *pb, const double *zhat, const uint8_t *mask
 int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, double *out) {
   if (check_pb(pb) || !mask || !f || !out) return FMO_ERR_ARG;
   const int64_t n = nvox(pb);
+  if (second_order(pb)) {
+    /* scatter every row's value back through its three coefficients 1, -2, 1 */
+    for (int64_t j = 0; j < n; ++j) out[j] = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+      for (int a = 0; a < 3; ++a)
+        if (row2(pb, mask, j, a)) {
+          const int64_t s = stride(pb, a);
+          const double v = f[j - s] - 2.0 * f[j] + f[j + s];
+          out[j - s] += v;
+          out[j] -= 2.0 * v;
+          out[j + s] += v;
+        }
+    return FMO_OK;
+  }
   int64_t nb[6];
   for (int64_t j = 0; j < n; ++j) {
     double s = 0.0;
@@ -362,6 +405,145 @@ int fmo_apply(const fmo_problem *pb, const uint8_t *mask, const double *piv, con
   return FMO_OK;
 }
 
+/* (C^T C)_jj: first order the in-mask neighbour count; second order the sum of
+ * squared coefficients of the rows through j (4 as centre, 1 as an end). */
+static double reg_diag1(const fmo_problem *pb, const uint8_t *mask, int64_t j) {
+  if (!mask[j]) return 0.0;
+  if (!second_order(pb)) {
+    int64_t nb[6];
+    return (double)neighbours(pb, mask, j, nb);
+  }
+  double d = 0.0;
+  int64_t c[3];
+  coords(pb, j, c);
+  for (int a = 0; a < 3; ++a) {
+    const int64_t s = stride(pb, a);
+    d += 4.0 * row2(pb, mask, j, a);
+    if (c[a] > 0) d += row2(pb, mask, j - s, a);
+    if (c[a] < extent(pb, a) - 1) d += row2(pb, mask, j + s, a);
+  }
+  return d;
+}
+
+int fmo_reg_diag(const fmo_problem *pb, const uint8_t *mask, double *out) {
+  if (check_pb(pb) || !mask || !out) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  for (int64_t j = 0; j < n; ++j) out[j] = reg_diag1(pb, mask, j);
+  return FMO_OK;
+}
+
+/* Pattern of H: slot q < 6 is the neighbour at +-1 along axis q/2 (sign by q%2),
+ * slot q >= 6 (second order only) the one at +-2.  Returns the neighbour's
+ * index, or -1 if it is outside the volume or the mask. */
+static int npat(const fmo_problem *pb) { return second_order(pb) ? 12 : 6; }
+
+static int64_t pat_nb(const fmo_problem *pb, const uint8_t *mask, int64_t j, int q) {
+  const int a = (q % 6) / 2, dist = q < 6 ? 1 : 2, sgn = (q % 2) ? 1 : -1;
+  int64_t c[3];
+  coords(pb, j, c);
+  const int64_t t = c[a] + sgn * dist;
+  if (t < 0 || t >= extent(pb, a)) return -1;
+  const int64_t k = j + sgn * dist * stride(pb, a);
+  return mask[k] ? k : -1;
+}
+
+/* The slot of neighbour k in j's pattern, or -1. */
+static int pat_slot(const fmo_problem *pb, const uint8_t *mask, int64_t j, int64_t k) {
+  for (int q = 0; q < npat(pb); ++q)
+    if (pat_nb(pb, mask, j, q) == k) return q;
+  return -1;
+}
+
+/* (C^T C)_jk for a pattern neighbour k = j +- dist along axis a. */
+static double reg_off(const fmo_problem *pb, const uint8_t *mask, int64_t j, int q) {
+  if (!second_order(pb)) return -1.0;
+  const int a = (q % 6) / 2, sgn = (q % 2) ? 1 : -1;
+  const int64_t s = stride(pb, a);
+  if (q < 6) /* rows centred at j and at the neighbour each give (-2)(1) */
+    return -2.0 * row2(pb, mask, j, a) - 2.0 * row2(pb, mask, j + sgn * s, a);
+  return (double)row2(pb, mask, j + sgn * s, a); /* the row centred between them: (1)(1) */
+}
+
+int fmo_ic_general(const fmo_problem *pb, const uint8_t *mask, const double *curv, const double *g,
+                   double *p, double *piv) {
+  if (check_pb(pb) || !mask || !curv || !g || !p) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  const int np = npat(pb);
+  const double b = pb->beta;
+  int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+  double *D = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  double *L = (double *)calloc((size_t)(n ? n : 1) * 12, sizeof(double)); /* L[j][slot of k], k earlier */
+  double *y = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  if (!order || !D || !L || !y) return FMO_ERR_ARG;
+  const int64_t cnt = build_order(pb, mask, order);
+  int st = FMO_OK;
+  for (int64_t t = 0; t < cnt && st == FMO_OK; ++t) {
+    const int64_t j = order[t];
+    const int64_t rj = rank_of(pb, j);
+    /* earlier pattern neighbours of j, in elimination order */
+    int64_t lk[12];
+    int lq[12], m = 0;
+    for (int q = 0; q < np; ++q) {
+      const int64_t k = pat_nb(pb, mask, j, q);
+      if (k >= 0 && rank_of(pb, k) < rj) {
+        int i = m++;
+        while (i > 0 && rank_of(pb, lk[i - 1]) > rank_of(pb, k)) {
+          lk[i] = lk[i - 1];
+          lq[i] = lq[i - 1];
+          --i;
+        }
+        lk[i] = k;
+        lq[i] = q;
+      }
+    }
+    double dj = curv[j] + b * reg_diag1(pb, mask, j);
+    for (int u = 0; u < m; ++u) {
+      const int64_t k = lk[u];
+      double s = b * reg_off(pb, mask, j, lq[u]);
+      for (int w = 0; w < u; ++w) { /* m = lk[w] precedes k: is it also in k's pattern? */
+        const int qk = pat_slot(pb, mask, k, lk[w]);
+        if (qk >= 0) s -= L[j * 12 + lq[w]] * L[k * 12 + qk] * D[lk[w]];
+      }
+      const double ljk = s / D[k];
+      L[j * 12 + lq[u]] = ljk;
+      dj -= ljk * ljk * D[k];
+    }
+    D[j] = dj;
+    if (!(dj > 0.0)) st = isfinite(dj) ? FMO_ERR_NOT_PD : FMO_ERR_NONFINITE;
+  }
+  if (st == FMO_OK) {
+    /* forward L y = g, then backward L^T p = D^{-1} y */
+    for (int64_t t = 0; t < cnt; ++t) {
+      const int64_t j = order[t];
+      const int64_t rj = rank_of(pb, j);
+      double s = g[j];
+      for (int q = 0; q < np; ++q) {
+        const int64_t k = pat_nb(pb, mask, j, q);
+        if (k >= 0 && rank_of(pb, k) < rj) s -= L[j * 12 + q] * y[k];
+      }
+      y[j] = s;
+    }
+    for (int64_t j = 0; j < n; ++j) p[j] = 0.0;
+    for (int64_t t = cnt - 1; t >= 0; --t) {
+      const int64_t j = order[t];
+      const int64_t rj = rank_of(pb, j);
+      double s = y[j] / D[j];
+      for (int q = 0; q < np; ++q) {
+        const int64_t k = pat_nb(pb, mask, j, q);
+        if (k >= 0 && rank_of(pb, k) > rj) s -= L[k * 12 + pat_slot(pb, mask, k, j)] * p[k];
+      }
+      p[j] = s;
+    }
+  }
+  if (piv)
+    for (int64_t j = 0; j < n; ++j) piv[j] = D[j];
+  free(order);
+  free(D);
+  free(L);
+  free(y);
+  return st;
+}
+
 static double dot_mask(const uint8_t *mask, int64_t n, const double *a, const double *b) {
   double s = 0.0;
   for (int64_t j = 0; j < n; ++j)
@@ -418,7 +600,6 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
   int st = FMO_OK;
   for (int64_t j = 0; j < n; ++j) f[j] = mask[j] ? f0[j] : 0.0;
   double gtp_prev = 0.0;
-  int64_t nbr[6];
 
   for (int it = 0; it < pb->niter; ++it) {
     /* gradient g = grad Phi + beta C^T C f, and the Huber curvature D */
@@ -435,7 +616,10 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
     const double cost = phi_sum + 0.5 * beta * dot_mask(mask, n, f, lap);
 
     /* precondition p = P^{-1} g */
-    if (pb->precond == FMO_PRECOND_IC0) {
+    if (pb->precond == FMO_PRECOND_IC0 && second_order(pb)) {
+      st = fmo_ic_general(pb, mask, curv, g, p, NULL);
+      if (st) break;
+    } else if (pb->precond == FMO_PRECOND_IC0) {
       st = fmo_factor(pb, mask, curv, piv);
       if (st) break;
       fmo_apply(pb, mask, piv, g, p);
@@ -445,7 +629,7 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
           p[j] = 0.0;
           continue;
         }
-        const double h = curv[j] + beta * neighbours(pb, mask, j, nbr);
+        const double h = curv[j] + beta * reg_diag1(pb, mask, j);
         if (!(h > 0.0)) {
           st = FMO_ERR_NOT_PD;
           break;
@@ -685,7 +869,7 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
     h[j] = voxel_hess(&pr, n, j, fhat[j]);
   }
   /* preconditioner: IC(0) (or the chosen variant) of the Huber model */
-  if (pb->precond == FMO_PRECOND_IC0) st = fmo_factor(pb, mask, curv, piv);
+  if (pb->precond == FMO_PRECOND_IC0 && !second_order(pb)) st = fmo_factor(pb, mask, curv, piv);
   int it = 0;
   if (st == FMO_OK) {
     for (int64_t j = 0; j < n; ++j) {
@@ -695,14 +879,16 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
     }
     const double bnorm = sqrt(dot_mask(mask, n, r, r));
     double rho_prev = 0.0;
-    int64_t nbr[6];
     for (it = 0; it < maxit; ++it) {
       if (sqrt(dot_mask(mask, n, r, r)) <= rtol * bnorm) break;
-      if (pb->precond == FMO_PRECOND_IC0) {
+      if (pb->precond == FMO_PRECOND_IC0 && second_order(pb)) {
+        st = fmo_ic_general(pb, mask, curv, r, z, NULL);
+        if (st) break;
+      } else if (pb->precond == FMO_PRECOND_IC0) {
         fmo_apply(pb, mask, piv, r, z);
       } else {
         for (int64_t j = 0; j < n; ++j) {
-          const double hh = curv[j] + beta * neighbours(pb, mask, j, nbr);
+          const double hh = curv[j] + beta * reg_diag1(pb, mask, j);
           z[j] = mask[j] ? (pb->precond == FMO_PRECOND_DIAG ? r[j] / hh : r[j]) : 0.0;
         }
       }

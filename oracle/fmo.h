@@ -60,7 +60,20 @@ typedef struct {
   int32_t nmls;         /* line-search steps per outer iteration, >= 1 */
   int32_t ordering;     /* FMO_ORDER_* (IC(0) ordering) */
   int32_t precond;      /* FMO_PRECOND_* */
+  int32_t reg_order;    /* finite differences of C: 1 (also when 0) or 2 (Sec. II eq. (cost)) */
 } fmo_problem;
+
+/* IC(0) of H = diag(curv) + beta C^T C on the pattern of H, in the problem's
+ * elimination order, by the general recurrence of incomplete LDL^T (an entry
+ * L_jk of an earlier pattern neighbour k gets the products L_jm L_km D_m of
+ * the pattern neighbours m that both share and that precede k), then
+ * p = (L D L^T)^{-1} g.  Works for either regulariser order; piv gets D
+ * (may be NULL).  FMO_ERR_NOT_PD if a pivot is not positive. */
+int fmo_ic_general(const fmo_problem *pb, const uint8_t *mask, const double *curv, const double *g,
+                   double *p, double *piv);
+
+/* Diagonal of C^T C per voxel (0 outside the mask). */
+int fmo_reg_diag(const fmo_problem *pb, const uint8_t *mask, double *out);
 
 /* Gamma = gamma (gamma^H gamma)^{-1} gamma^H, Sec. II eq. (gamma).
  * Field-map case: gamma = 1 (Gamma_mn = 1/L). */
@@ -85,7 +98,9 @@ int fmo_init_fieldmap(int64_t n, int32_t L, const double *zhat, const double *te
 int fmo_data_term(const fmo_problem *pb, const double *zhat, const uint8_t *mask,
                   const double *f, double *phi, double *dphi, double *curv);
 
-/* (C^T C f)_j over the mask graph. */
+/* (C^T C f)_j.  First order: one row f_k - f_j per in-mask neighbour pair.
+ * Second order: one row f_{j-e} - 2 f_j + f_{j+e} per voxel j and axis e
+ * with j - e, j and j + e all inside the volume and the mask. */
 int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, double *out);
 
 /* Incomplete Cholesky IC(0) of H = diag(curv) + beta C^T C in the problem's

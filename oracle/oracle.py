@@ -30,7 +30,7 @@ class _Problem(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("necho", C.c_int32),
                 ("te", C.c_void_p), ("gam", C.c_void_p), ("beta", C.c_double),
                 ("niter", C.c_int32), ("nmls", C.c_int32), ("ordering", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("reg_order", C.c_int32)]
 
 
 def lib():
@@ -67,7 +67,7 @@ def _check(st):
 class Problem:
     """Geometry and parameters of one solve (mirrors fmo_problem)."""
 
-    def __init__(self, shape, te, gamma, beta, niter=10, nmls=3, ordering=NATURAL, precond=IC0):
+    def __init__(self, shape, te, gamma, beta, niter=10, nmls=3, ordering=NATURAL, precond=IC0, reg_order=1):
         self.shape = tuple(int(s) for s in shape)
         self.te = _f64(te)
         self.gamma = _c128(gamma)
@@ -76,11 +76,12 @@ class Problem:
         self.nmls = int(nmls)
         self.ordering = int(ordering)
         self.precond = int(precond)
+        self.reg_order = int(reg_order)  # finite differences of C: 1 or 2
 
     def c(self):
         nx, ny, nz = self.shape
         s = _Problem(nx, ny, nz, len(self.te), _p(self.te).value, _p(self.gamma).value, self.beta,
-                     self.niter, self.nmls, self.ordering, self.precond)
+                     self.niter, self.nmls, self.ordering, self.precond, self.reg_order)
         return s
 
 
@@ -132,6 +133,25 @@ def laplacian(pb, mask, f):
     c = pb.c()
     _check(lib().fmo_laplacian(C.byref(c), _p(mask), _p(f), _p(out)))
     return out
+
+
+def reg_diag(pb, mask):
+    """Diagonal of C^T C."""
+    mask = _u8(mask)
+    out = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_reg_diag(C.byref(c), _p(mask), _p(out)))
+    return out
+
+
+def ic_general(pb, mask, curv, g):
+    """p = (L D L^T)^{-1} g with the general IC(0) recurrence (either regulariser order); returns (p, D)."""
+    mask, curv, g = _u8(mask), _f64(curv), _f64(g)
+    p = np.zeros(pb.shape)
+    d = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_ic_general(C.byref(c), _p(mask), _p(curv), _p(g), _p(p), _p(d)))
+    return p, d
 
 
 def factor(pb, mask, curv):
@@ -247,7 +267,7 @@ def problem_for(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, beta=
         gam = gamma_fieldmap(vol.necho)
     return Problem(vol.shape, vol.te, gam, vol.beta if beta is None else beta,
                    vol.niter if niter is None else niter, vol.nmls if nmls is None else nmls,
-                   ordering, precond)
+                   ordering, precond, getattr(vol, "reg_order", 1))
 
 
 def largest_fat_offset(vol):

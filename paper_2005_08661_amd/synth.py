@@ -50,6 +50,7 @@ class Volume:
     water: Optional[np.ndarray] = None
     fat: Optional[np.ndarray] = None
     name: str = ""
+    reg_order: int = 1       # finite differences of the regulariser C: 1 or 2
 
     @property
     def shape(self):
