@@ -99,6 +99,11 @@ typedef struct {
   int32_t precision;             /* fm_precision */
   int32_t ordering;              /* fm_ordering */
   int32_t precond;               /* fm_precond */
+  int32_t reg_order;             /* C of eq. (cost): 1 (also when 0) first-order finite differences,
+                                    2 second-order (rows f_{j-e} - 2 f_j + f_{j+e} with all three voxels
+                                    in the volume and the mask); 2 needs the field-map model and the
+                                    diagonal or identity preconditioner (FM_ERR_ARG otherwise), and is
+                                    not available to batches or fm_adjoint */
 } fm_params;
 
 typedef struct fm_plan fm_plan;

@@ -20,6 +20,7 @@
 #include "fm_natural.hpp"
 #include "fm_adjoint.hpp"
 #include "fm_resident.hpp"
+#include "fm_order2.hpp"
 
 using fm::kBlock;
 using fm::kMaxGrid;
@@ -108,6 +109,7 @@ struct fm_plan {
   fm::State *aS = nullptr;
   int32_t *a_status = nullptr;
   // resident schedule (one cooperative launch for many iterations)
+  bool reg2 = false;           // second-order regulariser
   int32_t sched = FM_SCHED_AUTO;
   bool res_ok = false;         // the plan qualifies (MIX, red-black IC(0), <= 4 echoes, tiles fit)
   bool res_auto = false;       // and FM_SCHED_AUTO takes it (large enough volume)
@@ -249,6 +251,7 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.trace = p->trace;
   a.fout = nullptr;
   a.final_pass = 0;
+  a.reg2 = p->reg2 ? 1 : 0;
   return a;
 }
 
@@ -314,6 +317,11 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
       FM_LAUNCH_CHECK();
       set_parts(p, p->sgrid, 2);
     }
+  } else if (p->reg2) {
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_diag2<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc,
+              p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
+    FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
   } else {
     FM_LAUNCH(FM_K_PRECOND_A, (fm::k_diag<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc,
                        p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
@@ -342,7 +350,11 @@ int tail_nvals(const fm_plan *p) { return p->prm.nmls > 1 ? 2 : 3; }
 // iteration's gradient pass (or by the final pass).
 template <typename T, int LMAX>
 fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) {
-  FM_LAUNCH(FM_K_GRAD, (fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+  if (p->reg2) {
+    FM_LAUNCH(FM_K_GRAD, (fm::k_grad2<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+  } else {
+    FM_LAUNCH(FM_K_GRAD, (fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+  }
   FM_LAUNCH_CHECK();
   set_parts(p, p->sgrid, 4);
   if (fused_red_dir(p) && p->geo.nz % 2 == 0) {
@@ -362,7 +374,11 @@ fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) 
   } else {
     fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
     if (st) return st;
-    FM_LAUNCH(FM_K_DIR, (fm::k_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    if (p->reg2) {
+      FM_LAUNCH(FM_K_DIR, (fm::k_dir2<T>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    } else {
+      FM_LAUNCH(FM_K_DIR, (fm::k_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    }
     FM_LAUNCH_CHECK();
   }
   set_parts(p, p->sgrid, 3);
@@ -381,7 +397,10 @@ fm_status enqueue_final(fm_plan *p, double *f_out, hipStream_t s) {
   fm::IterArgs<T> a = iter_args<T>(p, p->q++);
   a.final_pass = 1;
   a.fout = f_out;
-  hipLaunchKernelGGL((fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
+  if (p->reg2)
+    hipLaunchKernelGGL((fm::k_grad2<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
+  else
+    hipLaunchKernelGGL((fm::k_grad<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), 0, s, a);
   FM_LAUNCH_CHECK();
   set_parts(p, p->sgrid, 4);
   const uint64_t q = p->q++;
@@ -458,6 +477,11 @@ fm_status validate(const fm_params *p) {
   if (p->precision != FM_PREC_F64 && p->precision != FM_PREC_MIX) return fail(FM_ERR_ARG, "bad precision");
   if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK) return fail(FM_ERR_ARG, "bad ordering");
   if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_NONE) return fail(FM_ERR_ARG, "bad preconditioner");
+  if (p->reg_order < 0 || p->reg_order > 2) return fail(FM_ERR_ARG, "reg_order must be 1 or 2");
+  if (p->reg_order == 2 && p->model != FM_FIELDMAP)
+    return fail(FM_ERR_ARG, "second-order differences are built for the field-map model only");
+  if (p->reg_order == 2 && p->precond == FM_PRECOND_IC0)
+    return fail(FM_ERR_ARG, "IC(0) with second-order differences is not built: use the diagonal or identity preconditioner");
   if (p->model == FM_FIELDMAP && p->te[1] == p->te[0])
     return fail(FM_ERR_ARG, "field-map initialisation needs t_2 != t_1");
   if (p->model == FM_WATERFAT) {
@@ -897,7 +921,9 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   p->geo.n = p->n;
   p->geo.sy = prm->nz;
   p->geo.sx = (int64_t)prm->ny * prm->nz;
-  p->pad = ((p->geo.sx + 63) / 64) * 64;
+  p->reg2 = prm->reg_order == 2;
+  // one x-plane of guard entries on each side (two for the second-order stencil's +-2 neighbours)
+  p->pad = (((p->reg2 ? 2 : 1) * p->geo.sx + 63) / 64) * 64;
   if (p->n + 2 * p->pad >= ((int64_t)1 << 31)) {
     delete p;
     return fail(FM_ERR_SHAPE, "volume too large for 32-bit voxel indices");
@@ -1203,6 +1229,7 @@ fm_status fm_adjoint(fm_plan *p, const double *dldf, const void *sens, void *dld
   if (!sens && p->prm.ncoil != 1 && dldy) return fail(FM_ERR_ARG, "sens may be NULL only when ncoil == 1");
   if (maxit < 0 || !(rtol >= 0.0) || !std::isfinite(rtol)) return fail(FM_ERR_ARG, "maxit must be >= 0 and rtol finite, >= 0");
   if (!p->solved) return fail(FM_ERR_STATE, "fm_adjoint needs a converged map from fm_solve or fm_iterate");
+  if (p->reg2) return fail(FM_ERR_ARG, "fm_adjoint is built for the first-order regulariser only");
   fm_status st = adj_alloc(p);
   if (st) return st;
   FM_HIP(hipMemsetAsync(p->a_status, 0, sizeof(int32_t), s));

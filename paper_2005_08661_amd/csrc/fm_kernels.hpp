@@ -279,6 +279,7 @@ struct IterArgs {
   double *trace;       // [trace_cap + 1][8]
   double *fout;        // final pass: user output (double) or nullptr
   int32_t final_pass;
+  int32_t reg2;        // second-order regulariser (fm_eval only; the passes have their own kernels)
   Batch bt;            // batched launches only
 };
 
@@ -385,6 +386,10 @@ __global__ __launch_bounds__(kBlock) void k_hinv(Geo g, double beta, const uint8
 
 // ---------------------------------------------------------------------------
 // Evaluation at a user-supplied map (row-level checks and the adjoint).
+// The second-difference row centred at a voxel along axis ax exists when both
+// of its ax-neighbours are in the mask (both code bits set).
+__device__ __forceinline__ bool row2_code(uint32_t c, int ax) { return ((c >> (2 * ax + 1)) & 3u) == 3u; }
+
 template <typename T, int LMAX>
 __global__ __launch_bounds__(kBlock) void k_eval(IterArgs<T> a, const double *__restrict__ fu,
                                                   double *phi_o, double *dphi_o, double *curv_o,
@@ -401,12 +406,27 @@ __global__ __launch_bounds__(kBlock) void k_eval(IterArgs<T> a, const double *__
     }
     const T fj = (T)fu[j];
     T lap = T(0);
-    if (c & NB_XM) lap += fj - (T)fu[j - g.sx];
-    if (c & NB_XP) lap += fj - (T)fu[j + g.sx];
-    if (c & NB_YM) lap += fj - (T)fu[j - g.sy];
-    if (c & NB_YP) lap += fj - (T)fu[j + g.sy];
-    if (c & NB_ZM) lap += fj - (T)fu[j - 1];
-    if (c & NB_ZP) lap += fj - (T)fu[j + 1];
+    if (a.reg2) {
+      // second-order C^T C (13-point): rows centred at j and at its axis neighbours
+      const int64_t s3[3] = {g.sx, g.sy, 1};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int64_t s = s3[ax];
+        const bool hm = (c >> (2 * ax + 1)) & 1u, hp = (c >> (2 * ax + 2)) & 1u;
+        const bool r = hm && hp;
+        const bool rm = hm && row2_code(a.code[j - s], ax), rp = hp && row2_code(a.code[j + s], ax);
+        if (r) lap += T(-2) * ((T)fu[j - s] - T(2) * fj + (T)fu[j + s]);
+        if (rp) lap += fj - T(2) * (T)fu[j + s] + (T)fu[j + 2 * s];
+        if (rm) lap += (T)fu[j - 2 * s] - T(2) * (T)fu[j - s] + fj;
+      }
+    } else {
+      if (c & NB_XM) lap += fj - (T)fu[j - g.sx];
+      if (c & NB_XP) lap += fj - (T)fu[j + g.sx];
+      if (c & NB_YM) lap += fj - (T)fu[j - g.sy];
+      if (c & NB_YP) lap += fj - (T)fu[j + g.sy];
+      if (c & NB_ZM) lap += fj - (T)fu[j - 1];
+      if (c & NB_ZP) lap += fj - (T)fu[j + 1];
+    }
     T rho[LMAX], tau[LMAX];
     load_echoes<T, LMAX>(a.dat, g.n, (int)j, a.L, rho, tau);
     T phi, dphi, curv;

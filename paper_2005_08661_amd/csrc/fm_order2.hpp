@@ -1,0 +1,280 @@
+// Second-order finite-difference regulariser (Sec. II eq. (cost) with C the
+// second-order operator): one row f_{j-e} - 2 f_j + f_{j+e} per voxel j and
+// axis e whose three voxels are inside the volume and the mask.  The row
+// centred at j along axis a exists exactly when both a-neighbours of j are in
+// the mask, i.e. when the neighbour code has both bits of the axis, so no
+// extra per-voxel array is needed.  C^T C is a 13-point stencil:
+//   (C^T C f)_j = sum_a [ -2 r_j (f_{j-e} - 2 f_j + f_{j+e})
+//                         + r_{j+e} (f_j - 2 f_{j+e} + f_{j+2e})
+//                         + r_{j-e} (f_{j-2e} - 2 f_{j-e} + f_j) ],
+//   (C^T C)_jj  = sum_a [ 4 r_j + r_{j-e} + r_{j+e} ],
+// with r the row indicators.  Passes for the diagonal and identity
+// preconditioners (single volumes); arrays are padded by two x-planes so that
+// the +-2 neighbour addresses stay in bounds.
+#pragma once
+
+#include "fm_stream.hpp"
+
+namespace fm {
+
+__device__ __forceinline__ bool row2(uint32_t c, int a) { return has_nb(c, 2 * a) && has_nb(c, 2 * a + 1); }
+
+// Row indicators of j and of its two neighbours along each axis (a neighbour
+// row counts only if that neighbour is j's in-mask neighbour).
+struct Rows2 {
+  bool r[3], rm[3], rp[3];
+  __device__ __forceinline__ Rows2(uint32_t c, const uint32_t (&cn)[6]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      r[a] = row2(c, a);
+      rm[a] = has_nb(c, 2 * a) && row2(cn[2 * a], a);
+      rp[a] = has_nb(c, 2 * a + 1) && row2(cn[2 * a + 1], a);
+    }
+  }
+  __device__ __forceinline__ int diag() const {
+    int d = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d += 4 * (int)r[a] + (int)rm[a] + (int)rp[a];
+    return d;
+  }
+};
+
+// (C^T C f)_j from the values at j, j -+ e (v1[2a], v1[2a+1]) and j -+ 2e (v2).
+template <typename T>
+__device__ __forceinline__ T ctc2(const Rows2 &R, T fj, const T (&v1)[6], const T (&v2)[6]) {
+  T s = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const T fm1 = v1[2 * a], fp1 = v1[2 * a + 1], fm2 = v2[2 * a], fp2 = v2[2 * a + 1];
+    if (R.r[a]) s += T(-2) * (fm1 - T(2) * fj + fp1);
+    if (R.rp[a]) s += fj - T(2) * fp1 + fp2;
+    if (R.rm[a]) s += fm2 - T(2) * fm1 + fj;
+  }
+  return s;
+}
+
+// Gradient pass with the second-order regulariser (as k_grad): also loads the
+// +-2 neighbours of f and z and the neighbour codes.
+template <typename T, int LMAX>
+__global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
+  constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ fin = a.Fp;
+  const T *__restrict__ zp = a.Zp;
+  T *__restrict__ fo = a.Fc;
+  T *__restrict__ gg = a.Gc;
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
+  uint32_t c[V], cn[V][6];
+  T f0[V], z0[V], fn[V][6], zn[V][6], fn2[V][6], zn2[V][6], rho[V][LMAX], tau[V][LMAX];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      f0[v] = fin[jj];
+      z0[v] = zp[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        cn[v][k] = a.code[jj + of.o[k]];
+        fn[v][k] = fin[jj + of.o[k]];
+        zn[v][k] = zp[jj + of.o[k]];
+        fn2[v][k] = fin[jj + 2 * of.o[k]];
+        zn2[v][k] = zp[jj + 2 * of.o[k]];
+      }
+      load_echoes<T, LMAX>(a.dat, vw.es, jj, a.L, rho[v], tau[v]);
+    }
+  };
+  int base = vw.bl * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT, 3>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const T alpha = (T)st.alpha;
+  const T beta = (T)a.beta;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        fo[j] = T(0);
+        if (a.fout) a.fout[j] = 0.0;
+        if (!a.final_pass) {
+          gg[j] = T(0);
+          a.D[j] = T(0);
+        }
+        continue;
+      }
+      const T fj = f0[v] + alpha * z0[v];
+      T v1[6], v2[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        v1[k] = fn[v][k] + alpha * zn[v][k];
+        v2[k] = fn2[v][k] + alpha * zn2[v][k];
+      }
+      const Rows2 R(cv, cn[v]);
+      const T lap = ctc2(R, fj, v1, v2);
+      T phi, dphi, curv;
+      voxel_terms<T, LMAX>(rho[v], tau[v], a.L, a.pairs, fj, phi, dphi, curv);
+      const T gj = dphi + beta * lap;
+      fo[j] = fj;
+      if (a.fout) a.fout[j] = (double)fj;
+      if (!a.final_pass) {
+        gg[j] = gj;
+        a.D[j] = curv;
+      }
+      acc[0] += (double)phi;
+      acc[1] += (double)fj * (double)lap;
+      acc[2] += (double)gj * (double)gj;
+      acc[3] += (double)z0[v] * (double)gj;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  store_partials<4, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_GRAD, vw.nb, vw.leader);
+}
+
+// Diagonal (P = diag H with diag(C^T C) of the second-order operator) or
+// identity preconditioner (as k_diag).
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_diag2(IterArgs<T> a0, const T *__restrict__ gsrc, int identity) {
+  constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
+  const T *__restrict__ gp = a.Gp;
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
+  uint32_t c[V], cn[V][6];
+  T d0[V], g0[V], gp0[V];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      d0[v] = a.D[jj];
+      g0[v] = gg[jj];
+      gp0[v] = gp[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) cn[v][k] = a.code[jj + of.o[k]];
+    }
+  };
+  int base = vw.bl * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  double acc[2] = {0.0, 0.0};
+  int bad = 0;
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        a.ipiv[j] = 0.0;
+        a.P[j] = T(0);
+        continue;
+      }
+      T pj;
+      if (identity) {
+        a.ipiv[j] = 1.0;
+        pj = g0[v];
+      } else {
+        const Rows2 R(cv, cn[v]);
+        const double h = (double)d0[v] + beta * R.diag();
+        double ip = 1.0 / h;
+        if (!(h > 0.0)) {
+          bad = 1;
+          ip = 0.0;
+        }
+        a.ipiv[j] = ip;
+        pj = (T)((double)g0[v] * ip);
+      }
+      a.P[j] = pj;
+      acc[0] += (double)g0[v] * (double)pj;
+      acc[1] += (double)gp0[v] * (double)pj;
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
+}
+
+// Direction and line-search setup with the second-order regulariser (as
+// k_dir): z = -p + mu z_prev, and over the rows of C (each row taken at its
+// centre voxel) A = sum (Cz)(Cf) = z^T C^T C f and B = sum (Cz)^2; d0 = sum z^2 D.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
+  constexpr int V = Vpt<T>::v;
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ zp = a.Zp;
+  T *__restrict__ zo = a.Zc;
+  const T *__restrict__ f = a.Fc;
+  const T *__restrict__ p = a.P;
+  const Offs of(g);
+  const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
+  uint32_t c[V];
+  T p0[V], z0[V], f0[V], d0[V], pn[V][6], zn[V][6], fn[V][6];
+  auto load = [&](int b) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = b + v * kNT + (int)threadIdx.x;
+      const int jj = j < n ? j : n - 1;
+      c[v] = j < n ? a.code[jj] : 0u;
+      p0[v] = p[jj];
+      z0[v] = zp[jj];
+      f0[v] = f[jj];
+      d0[v] = a.D[jj];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        pn[v][k] = p[jj + of.o[k]];
+        zn[v][k] = zp[jj + of.o[k]];
+        fn[v][k] = f[jj + of.o[k]];
+      }
+    }
+  };
+  int base = vw.bl * chunk;
+  if (base < n) load(base);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const T mu = (T)st.mu;
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (; base < n; base += stride) {
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const int j = base + v * kNT + (int)threadIdx.x;
+      if (j >= n) continue;
+      const uint32_t cv = c[v];
+      if (!(cv & NB_SELF)) {
+        zo[j] = T(0);
+        continue;
+      }
+      const T zj = -p0[v] + mu * z0[v];
+      zo[j] = zj;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax)
+        if (row2(cv, ax)) {
+          const T zm = -pn[v][2 * ax] + mu * zn[v][2 * ax], zq = -pn[v][2 * ax + 1] + mu * zn[v][2 * ax + 1];
+          const double cz = (double)(zm - T(2) * zj + zq);
+          const double cf = (double)(fn[v][2 * ax] - T(2) * f0[v] + fn[v][2 * ax + 1]);
+          acc[0] += cz * cf;
+          acc[1] += cz * cz;
+        }
+      acc[2] += (double)zj * (double)zj * (double)d0[v];
+    }
+    if (base + stride < n) load(base + stride);
+  }
+  store_partials<3, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DIR, vw.nb, vw.leader);
+}
+
+}  // namespace fm

@@ -49,7 +49,7 @@ class Params(C.Structure):
                 ("niter", C.c_int32), ("nmls", C.c_int32), ("model", C.c_int32), ("npeak", C.c_int32),
                 ("fat_hz", C.c_double * FM_MAX_PEAK), ("fat_amp", C.c_double * FM_MAX_PEAK),
                 ("nsweep", C.c_int32), ("pwls_iters", C.c_int32), ("precision", C.c_int32),
-                ("ordering", C.c_int32), ("precond", C.c_int32)]
+                ("ordering", C.c_int32), ("precond", C.c_int32), ("reg_order", C.c_int32)]
 
 
 _lib = None
@@ -112,7 +112,7 @@ def _stream():
 
 
 def make_params(shape, ncoil, te, beta, niter=100, nmls=3, model=FIELDMAP, fat_hz=None, fat_amp=None,
-                nsweep=100, pwls_iters=10, precision=F64, ordering=NATURAL, precond=IC0):
+                nsweep=100, pwls_iters=10, precision=F64, ordering=NATURAL, precond=IC0, reg_order=1):
     p = Params()
     p.nx, p.ny, p.nz = (int(s) for s in shape)
     p.ncoil = int(ncoil)
@@ -138,6 +138,7 @@ def make_params(shape, ncoil, te, beta, niter=100, nmls=3, model=FIELDMAP, fat_h
     p.precision = int(precision)
     p.ordering = int(ordering)
     p.precond = int(precond)
+    p.reg_order = int(reg_order)
     return p
 
 
@@ -146,7 +147,8 @@ def params_for(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, nm
     return make_params(vol.shape, vol.ncoil, vol.te, vol.beta, vol.niter if niter is None else niter,
                        vol.nmls if nmls is None else nmls,
                        WATERFAT if vol.model == "waterfat" else FIELDMAP, vol.fat_hz, vol.fat_amp,
-                       precision=precision, ordering=ordering, precond=precond)
+                       precision=precision, ordering=ordering, precond=precond,
+                       reg_order=getattr(vol, "reg_order", 1))
 
 
 class Plan:

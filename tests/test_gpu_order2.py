@@ -1,0 +1,161 @@
+"""Second-order finite-difference regulariser on the GPU against the FP64 oracle.
+
+The GPU builds it for the field-map model with the diagonal and identity
+preconditioners (IC(0) of the 13-point pattern is in the oracle only).  Bars as
+in the first-order parity tests: F64 within 1e-3 Hz RMS (in practice round-off)
+with identical restart decisions, MIX within 0.05 Hz RMS; the stencil and the
+diagonal preconditioner element by element; refusals for what is not built.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_08661_amd import fmap, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    fmap.lib()
+
+
+def rms(a, m):
+    return float(np.sqrt(np.mean(a[m] ** 2))) if m.any() else 0.0
+
+
+def vol2(shape=(13, 9, 10), seed=0, frac=None, beta=0.05, niter=15, ncoil=2):
+    vol = synth.fieldmap_volume(shape, ncoil, [0.0, 1.5e-3, 4.0e-3], beta, niter, synth.SEED_BASE + 980 + seed, 3,
+                                120.0, False, 25.0, mask="paper", name="second order %s" % (shape,))
+    if frac is not None:
+        rng = np.random.default_rng(seed)
+        vol.mask = (rng.uniform(size=shape) < frac).astype(np.uint8)
+    vol.reg_order = 2
+    return vol
+
+
+VOLS = {"ragged_paper_mask": lambda: vol2(), "random_mask": lambda: vol2((20, 17, 11), 1, frac=0.85),
+        "tiny_line_y": lambda: vol2((2, 19, 3), 2)}
+PREC = {"f64": fmap.F64, "mix": fmap.MIX}
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", list(VOLS))
+def test_stencil_matches_oracle(vname, prec):
+    vol = VOLS[vname]()
+    say("order-2 stencil %s %s" % (vname, prec))
+    rng = np.random.default_rng(11)
+    f = (synth.smooth_field(rng, vol.shape, 3, 200.0) + rng.normal(size=vol.shape)) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec], precond=fmap.DIAG)) as plan:
+        plan.setup(y, s, m)
+        lap = plan.eval(torch.from_numpy(f).cuda())[3].cpu().numpy()
+    ref = O.laplacian(O.problem_for(vol, precond=O.DIAG), vol.mask, f)
+    tol = 1e-10 if prec == "f64" else 2e-5
+    assert np.abs(lap - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+def test_diagonal_preconditioner_matches_oracle(prec):
+    vol = VOLS["random_mask"]()
+    rng = np.random.default_rng(12)
+    curv = rng.uniform(0, 0.1, vol.shape) * vol.mask
+    g = rng.normal(size=vol.shape) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec], precond=fmap.DIAG)) as plan:
+        plan.setup(y, s, m)
+        piv, p = (t.cpu().numpy() for t in plan.precondition(torch.from_numpy(curv).cuda(), torch.from_numpy(g).cuda()))
+    pb = O.problem_for(vol, precond=O.DIAG)
+    cref = curv if prec == "f64" else curv.astype(np.float32).astype(np.float64)
+    h = cref + pb.beta * O.reg_diag(pb, vol.mask)
+    msk = vol.mask.astype(bool)
+    np.testing.assert_allclose(piv[msk], h[msk], rtol=1e-12)  # the pivots of P = diag(H)
+    tol = 1e-12 if prec == "f64" else 1e-6
+    assert np.abs(p - np.where(msk, g / np.where(msk, h, 1.0), 0.0)).max() <= tol * np.abs(g).max() / h[msk].min()
+
+
+@pytest.mark.parametrize("precond", ["diag", "none"])
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", ["ragged_paper_mask", "random_mask"])
+def test_solve_matches_oracle(vname, prec, precond):
+    vol = VOLS[vname]()
+    pc, opc = (fmap.DIAG, O.DIAG) if precond == "diag" else (fmap.NONE, O.NONE)
+    say("order-2 solve %s %s %s" % (vname, prec, precond))
+    f, tr = fmap.solve_volume(vol, precision=PREC[prec], precond=pc)
+    ref = O.run_volume(vol, precond=opc)
+    msk = vol.mask.astype(bool)
+    err = rms(f - ref["f"], msk)
+    say("  rms vs oracle %.3e Hz" % err)
+    assert np.all(f[~msk] == 0)
+    rt = ref["trace"]
+    if prec == "f64":
+        assert err < 1e-3
+        np.testing.assert_array_equal(tr[:-1, 3], rt[:-1, O.TR["restart"]])
+        np.testing.assert_allclose(tr[:, 0], rt[:, O.TR["cost"]], rtol=1e-9)
+        np.testing.assert_allclose(tr[:-1, 6], rt[:-1, O.TR["B"]], rtol=1e-8)  # ||C z||^2 of the row form
+    else:
+        assert err < 0.05
+        np.testing.assert_allclose(tr[:, 0], rt[:, O.TR["cost"]], rtol=1e-4)
+
+
+def test_noise_free_affine_field_recovered_and_differs_from_first_order():
+    shape = (12, 10, 8)
+    te = [0.0, 1.5e-3, 4.0e-3]
+    x, y, z = np.meshgrid(*[np.arange(s, dtype=float) for s in shape], indexing="ij")
+    f_true = 5.0 + 3.0 * x - 2.0 * y + 1.5 * z
+    y_img = np.stack([np.exp(2j * np.pi * f_true * t) for t in te])[None]
+    vol = synth.Volume(y=y_img.astype(np.complex64), sens=None, te=np.array(te), mask=np.ones(shape, np.uint8),
+                       f_true=f_true, beta=0.5, niter=80, reg_order=2)
+    f2, _ = fmap.solve_volume(vol, precision=fmap.F64, precond=fmap.DIAG)
+    assert np.abs(f2 - f_true).max() < 1e-4
+    # the same data with the first-order penalty: the affine field is not in its null space, so the
+    # estimate is pulled away from it (the two operators are really different on the GPU)
+    vol.reg_order = 1
+    vol.beta = 50.0
+    f1, _ = fmap.solve_volume(vol, precision=fmap.F64, precond=fmap.DIAG)
+    vol.reg_order = 2
+    f2b, _ = fmap.solve_volume(vol, precision=fmap.F64, precond=fmap.DIAG)
+    assert np.abs(f1 - f_true).max() > 100 * max(np.abs(f2b - f_true).max(), 1e-9)
+
+
+def test_large_volume_precisions_agree():
+    vol = vol2((64, 64, 32), 3, beta=2.0 ** -4, niter=40, ncoil=4)
+    vol.mask[:] = 1
+    say("order-2 64x64x32 MIX vs F64")
+    f64, tr64 = fmap.solve_volume(vol, precision=fmap.F64, precond=fmap.DIAG)
+    fmix, _ = fmap.solve_volume(vol, precision=fmap.MIX, precond=fmap.DIAG)
+    d = rms(f64 - fmix, vol.mask.astype(bool))
+    say("  rms MIX - F64 %.3e Hz" % d)
+    assert d < 0.01
+    assert np.all(np.diff(tr64[:, 0]) <= 1e-12 * tr64[0, 0])
+
+
+def test_what_is_not_built_is_refused():
+    vol = vol2()
+    with pytest.raises(fmap.FmapError) as ei:
+        fmap.Plan(fmap.params_for(vol, precision=fmap.F64, precond=fmap.IC0))
+    assert ei.value.status == 1
+    p = fmap.params_for(vol, precision=fmap.MIX, precond=fmap.DIAG)
+    with pytest.raises(fmap.FmapError):
+        fmap.Batch([p, p])
+    wf = fmap.make_params((8, 8, 8), 1, 1e-3 * (1.2 + np.arange(6)), 0.1, model=fmap.WATERFAT,
+                          fat_hz=[-434.0, -332.0], fat_amp=[0.7, 0.3], precond=fmap.DIAG, reg_order=2)
+    with pytest.raises(fmap.FmapError):
+        fmap.Plan(wf)
+    bad = fmap.params_for(vol, precision=fmap.F64, precond=fmap.DIAG)
+    bad.reg_order = 3
+    with pytest.raises(fmap.FmapError):
+        fmap.Plan(bad)
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, precond=fmap.DIAG, niter=3)) as plan:
+        f = plan.solve(y, s, m)
+        with pytest.raises(fmap.FmapError):
+            plan.adjoint(2.0 * f * m)
