@@ -28,7 +28,13 @@
 
 namespace fm {
 
-constexpr int kResNT = 512;                // threads per workgroup
+#ifndef FM_RES_NT
+#define FM_RES_NT 512
+#endif
+#ifndef FM_RES_LB
+#define FM_RES_LB 4
+#endif
+constexpr int kResNT = FM_RES_NT;          // threads per workgroup
 constexpr int kResV = 4;                   // voxel slots per thread
 constexpr int kResTile = kResNT * kResV;   // voxels per tile, at most
 constexpr int kResGroups = 8;              // first level of the barrier
@@ -143,9 +149,40 @@ __device__ __forceinline__ bool res_nbwait(uint32_t *flags, const ResTile &t, in
   return okn_s != 0;
 }
 
+// Block-wide sum of K values with the same rounding as block_sum (waves
+// first, then the waves' sums in wave order); the totals go to thread 0 only
+// (the one that publishes or applies them).  Thread k sums value k over the
+// waves, so no thread holds more than the K totals (block_sum's every-thread
+// loop over K x waves would).
+template <int K>
+__device__ __forceinline__ void res_block_sum(double (&v)[K]) {
+  constexpr int NW = kResNT / kWave;
+  __shared__ double red[K][NW];
+  __shared__ double tot[K];
+  wave_reduce<K>(v);
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k][wid] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s += red[threadIdx.x][w];
+    tot[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = tot[k];
+  }
+}
+
 template <int K>
 __device__ __forceinline__ void res_put(double (&v)[K], double *part, int slot) {
-  block_sum<K, kResNT>(v);
+  res_block_sum<K>(v);
   if (threadIdx.x == 0) {
     const int nb = (int)gridDim.x;
 #pragma unroll
@@ -186,7 +223,7 @@ __device__ __forceinline__ T res_nb(const T *l, int li, int lo, bool in_tile, T 
 }
 
 template <int LR>
-__global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
+__global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
   // Thread t owns the voxel pairs (2q, 2q+1) of the tile's z-fastest order
   // with q = t and q = t + kResNT: with an even column length each pair is one
   // red and one black voxel of a column, so in the black and the red pass
@@ -243,8 +280,25 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
     }
   }
   {
-    const State s0 = take_state<kResNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
-    if (threadIdx.x == 0) ls = s0;
+    // the incoming state and the partial sums the previous launch left (as take_state)
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < a.nparts_in; b += kResNT) {
+      double x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = a.pin[(size_t)k * a.nparts_in + b];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) t[k] += k < a.nvals_in ? x[k] : 0.0;
+    }
+    res_block_sum<4>(t);
+    if (threadIdx.x == 0) {
+      State s0 = *a.sin;
+      if (s0.kind != PK_NONE) {
+        if ((s0.nparts != a.nparts_in || a.nvals_in > 4) && blockIdx.x == 0) set_status(a.status, 7);
+        const double tt[kMaxK] = {t[0], t[1], t[2], t[3]};
+        consume(s0, tt, a.beta, a.trace, a.status, blockIdx.x == 0);
+      }
+      ls = s0;
+    }
   }
   __syncthreads();
   const double beta = a.beta, b2 = a.beta * a.beta;
@@ -261,10 +315,15 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
     for (int k = 0; k < K; ++k) t[k] = 0.0;
     const int nb = (int)gridDim.x;
     for (int b = threadIdx.x; b < nb; b += kResNT) {
+      // all K loads first: the compiler keeps coherent loads in program order
+      // and would wait for each one before issuing the next
+      double x[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) t[k] += ld_coh(a.part + ((size_t)slot * kMaxK + k) * nb + b);
+      for (int k = 0; k < K; ++k) x[k] = ld_coh(a.part + ((size_t)slot * kMaxK + k) * nb + b);
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[k] += x[k];
     }
-    block_sum<K, kResNT>(t);
+    res_block_sum<K>(t);
   };
   auto apply = [&](auto &t, int kind) {  // thread 0 updates the shared state in place
     constexpr int K = sizeof(t) / sizeof(double);

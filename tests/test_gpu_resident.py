@@ -82,6 +82,7 @@ def test_resident_matches_streaming_and_oracle(case):
     n = tr.shape[0] - 1
     np.testing.assert_array_equal(tr[:n, 3], ts[:n, 3])
     np.testing.assert_allclose(tr[:, 0], ts[:, 0], rtol=1e-6)
+    np.testing.assert_allclose(tr[:n, 6], ts[:n, 6], rtol=1e-6)  # ||C z||^2
     assert np.all(fr[~m] == 0)
 
 
