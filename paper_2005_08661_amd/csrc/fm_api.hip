@@ -541,7 +541,7 @@ bool use_resident(const fm_plan *p) {
   return p->res_ok && (p->sched == FM_SCHED_RESIDENT || (p->sched == FM_SCHED_AUTO && p->res_auto));
 }
 
-size_t res_bar_bytes(const fm_plan *p) { return sizeof(uint32_t) * (fm::kResGroups * 32 + 32 + (size_t)p->res_grid); }
+size_t res_bar_bytes(const fm_plan *p) { return sizeof(uint32_t) * (fm::kResBarHead + (size_t)p->res_grid); }
 
 template <int LR>
 void *resident_kernel() {

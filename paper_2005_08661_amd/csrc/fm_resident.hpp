@@ -20,35 +20,28 @@
 // continue from them unchanged.
 //
 // The grid barrier is a two-level arrival count (one counter per group of
-// workgroups, then one global counter) with bounded waits: a wait that runs
-// out sets FM_ERR_TIMEOUT (status 8) and every workgroup leaves the launch.
+// workgroups, then one global counter); the last arrival releases each group
+// through a word of its own, so no word is polled by every workgroup.  Waits
+// are bounded: one that runs out sets FM_ERR_TIMEOUT (status 8) and every
+// workgroup leaves the launch.
 #pragma once
 
 #include "fm_stream.hpp"
 
 namespace fm {
 
-#ifndef FM_RES_NT
-#define FM_RES_NT 512
-#endif
-#ifndef FM_RES_LB
-#define FM_RES_LB 4
-#endif
-constexpr int kResNT = FM_RES_NT;          // threads per workgroup
+constexpr int kResNT = 512;                // threads per workgroup
 constexpr int kResV = 4;                   // voxel slots per thread
 constexpr int kResTile = kResNT * kResV;   // voxels per tile, at most
-constexpr int kResGroups = 8;              // first level of the barrier
+constexpr int kResGroups = 16;             // first level of the barrier
+// barrier words before the tile flags: group counters, the global counter and
+// the per-group release words, each on a 128-byte line of its own
+constexpr int kResBarHead = (2 * kResGroups + 1) * 32;
 constexpr int kResSpin = 1 << 20;          // polls (about 1 us each) before a wait gives up
 // The gradient pass hands its results only to the four face-neighbour tiles
 // (the black pass needs nothing global from it), so it ends with a wait on
 // their progress flags instead of a grid barrier; its partial sums are taken
 // at the next barrier.
-#ifndef FM_RES_NBSYNC
-#define FM_RES_NBSYNC 1
-#endif
-#ifndef FM_RES_GRAD_SEL
-#define FM_RES_GRAD_SEL 0
-#endif
 // Partial-sum slots, one per pass kind, so that a slot is only rewritten
 // after every workgroup has passed the barrier following its last read:
 // gradient, dot products, direction, then two alternating line-search slots.
@@ -77,7 +70,7 @@ struct ResArgs {
   State *sout;
   const double *pin;
   double *part;        // [kResSlots][kMaxK][grid] partial sums of the passes
-  uint32_t *bar;       // [kResGroups * 32 + 32 + grid] counters and tile flags, zeroed before the launch
+  uint32_t *bar;       // [kResBarHead + grid] counters, release words and tile flags, zeroed before the launch
   int32_t *status;
   double *trace;
 };
@@ -100,10 +93,18 @@ __device__ __forceinline__ bool res_barrier(uint32_t *bar, int32_t *status, uint
     const uint32_t gsize = (uint32_t)(nb / ngroups + (g < nb % ngroups ? 1 : 0));
     uint32_t *cnt = bar + kResGroups * 32;
     const uint32_t old = __hip_atomic_fetch_add(bar + g * 32, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old + 1 == gsize * e) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t target = (uint32_t)ngroups * e;
+    // the last arrival of the last group releases every group through its own
+    // word, so each word is polled by one group only
+    uint32_t *rel = bar + (kResGroups + 1) * 32;
+    if (old + 1 == gsize * e) {
+      const uint32_t og = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (og + 1 == (uint32_t)ngroups * e)
+        for (int gg = 0; gg < ngroups; ++gg) __hip_atomic_store(rel + gg * 32, e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const uint32_t *poll = rel + g * 32;
+    const uint32_t target = e;
     int spins = 0, ok = 1;
-    while (ld_coh_u32(cnt) < target) {
+    while (ld_coh_u32(poll) < target) {
       if (++spins > kResSpin || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 8) {
         ok = 0;
         atomicCAS(status, 0, 8);
@@ -223,7 +224,7 @@ __device__ __forceinline__ T res_nb(const T *l, int li, int lo, bool in_tile, T 
 }
 
 template <int LR>
-__global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
+__global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
   // Thread t owns the voxel pairs (2q, 2q+1) of the tile's z-fastest order
   // with q = t and q = t + kResNT: with an even column length each pair is one
   // red and one black voxel of a column, so in the black and the red pass
@@ -306,7 +307,7 @@ __global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
   const int nmls = ls.nmls;
   uint32_t e = 0;  // barriers passed
   int mslot = 0;   // alternating line-search slot
-  uint32_t *flags = a.bar + kResGroups * 32 + 32;
+  uint32_t *flags = a.bar + kResBarHead;
 
   // sum all workgroups' K partials of a slot (fixed order, identical everywhere)
   auto take = [&](auto &t, int slot) {
@@ -395,14 +396,6 @@ __global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
           continue;
         }
         float lap = 0.f;
-#if FM_RES_GRAD_SEL
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-          const float hv = k < 2 ? hfx[v] + alpha * hzx[v] : hfy[v] + alpha * hzy[v];
-          const float fn = res_nb(lf, li, loff[k], (c >> (8 + k)) & 1u, hv);
-          lap += has_nb(c, k) ? fj[v] - fn : 0.f;
-        }
-#else
 #pragma unroll
         for (int k = 0; k < 6; ++k)
           if (has_nb(c, k)) {
@@ -410,7 +403,6 @@ __global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
                                                   : (k < 2 ? hfx[v] + alpha * hzx[v] : hfy[v] + alpha * hzy[v]);
             lap += fj[v] - fn;
           }
-#endif
         float phi, dphi, curv;
         voxel_terms<float, LR>(rho[v], tau[v], LR, lpc, fj[v], phi, dphi, curv);
         const float gj = dphi + betaf * lap;
@@ -434,12 +426,8 @@ __global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
         st_coh(Gc + j, lgc[li]);
         st_coh(a.hinv + j, lh[li]);
       }
-#if FM_RES_NBSYNC
       res_put<4>(acc, a.part, kSlotG);
       if (!(live = res_nbwait(flags, a.tile, a.status, (uint32_t)it + 1))) break;
-#else
-      if (!(live = finish(acc, PK_GRAD, kSlotG, false))) break;
-#endif
     }
 
     // ---- black pass with both dot products (as k_rb_black_pair): per pair,
@@ -505,7 +493,7 @@ __global__ __launch_bounds__(kResNT, FM_RES_LB) void k_resident(ResArgs a) {
         const uint32_t cb = sb ? cv[2 * q + 1] : cv[2 * q];
         if (cb & NB_SELF) st_coh(a.P + (sb ? jv[2 * q + 1] : jv[2 * q]), lp[2 * (q * kResNT + tid) + (sb ? 1 : 0)]);
       }
-      if (!(live = finish(acc, PK_DOTS, kSlotD, FM_RES_NBSYNC != 0))) break;
+      if (!(live = finish(acc, PK_DOTS, kSlotD, true))) break;
     }
 
     // ---- red pass and direction (as k_rb_red_dir_pair): z_i = -p + mu z_{i-1};

@@ -62,6 +62,7 @@ def solve(vol, sched, nmls=None, niter=None):
         plan.set_schedule(sched)
         used = plan.schedule()
         f = plan.solve(y, s, m).cpu().numpy()
+        plan.status()  # raises on a time-out, a non-positive pivot or a non-finite value
         return f, plan.trace(), used
 
 
