@@ -28,7 +28,8 @@
  *   R3 the gradient carries (t_m - t_n), not its square (derivative of 1-cos).
  *   R4 "mod pi" is read as wrapping the phase to [-pi, pi]; sinc(0) = 1.
  *   R5 C has rows only for in-mask neighbour pairs; IC(0) in natural
- *      (lexicographic, z fastest) or red-black order.
+ *      (lexicographic, z fastest), red-black or three-colour order (the
+ *      last for the second-order C, whose stencil two colours do not split).
  *   R6 mu = (g - g_prev)^T p / (g_prev^T p_prev), mu = 0 at i = 0 or when the
  *      denominator is 0.
  *   R7 z = -p + mu z_prev, reset to -p when z^T g >= 0.
@@ -39,7 +40,9 @@
  *   R14 angle(0) = 0; zero data gives a zero data term.
  *   R20 second-order C: a row f_{j-e} - 2 f_j + f_{j+e} for every voxel j and
  *      axis e whose three voxels are inside the volume and the mask (R5 for
- *      second differences); no spatial weights.
+ *      second differences); no spatial weights.  IC(0) keeps L on the
+ *      13-point stencil (in-mask voxels 1 or 2 steps along an axis), also
+ *      where C^T C is 0 there.
  */
 #include "fmo.h"
 
@@ -100,28 +103,28 @@ static int row2(const fmo_problem *pb, const uint8_t *mask, int64_t j, int a) {
   return mask[j] && mask[j - s] && mask[j + s];
 }
 
-/* Position of voxel j in the elimination order. */
+/* Colours of the elimination order (natural order: one). */
+static int ncolours(const fmo_problem *pb) {
+  return pb->ordering == FMO_ORDER_REDBLACK ? 2 : (pb->ordering == FMO_ORDER_COLOR3 ? 3 : 1);
+}
+
+/* Position of voxel j in the elimination order: colour (x+y+z) mod ncolours
+ * first, natural index within a colour. */
 static int64_t rank_of(const fmo_problem *pb, int64_t j) {
-  if (pb->ordering == FMO_ORDER_REDBLACK) {
-    const int64_t nz = pb->nz, ny = pb->ny;
-    const int64_t z = j % nz, y = (j / nz) % ny, x = j / (ny * nz);
-    return ((x + y + z) & 1) * nvox(pb) + j;
-  }
-  return j;
+  const int nc = ncolours(pb);
+  if (nc == 1) return j;
+  const int64_t nz = pb->nz, ny = pb->ny;
+  const int64_t z = j % nz, y = (j / nz) % ny, x = j / (ny * nz);
+  return ((x + y + z) % nc) * nvox(pb) + j;
 }
 
 /* Voxels in elimination order (in-mask only); returns the count. */
 static int64_t build_order(const fmo_problem *pb, const uint8_t *mask, int64_t *order) {
   const int64_t n = nvox(pb);
   int64_t c = 0;
-  if (pb->ordering == FMO_ORDER_REDBLACK) {
-    for (int colour = 0; colour < 2; ++colour)
-      for (int64_t j = 0; j < n; ++j)
-        if (mask[j] && rank_of(pb, j) / n == colour) order[c++] = j;
-  } else {
+  for (int colour = 0; colour < ncolours(pb); ++colour)
     for (int64_t j = 0; j < n; ++j)
-      if (mask[j]) order[c++] = j;
-  }
+      if (mask[j] && rank_of(pb, j) / n == colour) order[c++] = j;
   return c;
 }
 
@@ -291,7 +294,8 @@ int fmo_init_fieldmap(int64_t n, int32_t L, const double *zhat, const double *te
 
 static int check_pb(const fmo_problem *pb) {
   if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 1 || pb->necho < 2 || !pb->te || !pb->gam ||
-      !(pb->beta >= 0) || pb->nmls < 1 || pb->niter < 0)
+      !(pb->beta >= 0) || pb->nmls < 1 || pb->niter < 0 || pb->ordering < FMO_ORDER_NATURAL ||
+      pb->ordering > FMO_ORDER_COLOR3)
     return FMO_ERR_ARG;
   return FMO_OK;
 }

@@ -34,7 +34,11 @@ extern "C" {
 #endif
 
 enum { FMO_OK = 0, FMO_ERR_ARG = 1, FMO_ERR_NOT_PD = 5, FMO_ERR_NONFINITE = 6 };
-enum { FMO_ORDER_NATURAL = 0, FMO_ORDER_REDBLACK = 1 };
+/* Elimination orders of IC(0): natural (lexicographic, z fastest), red-black
+ * ((x+y+z) mod 2, then natural) and three-colour ((x+y+z) mod 3, then
+ * natural; no two voxels of a colour are pattern neighbours of the
+ * second-order C^T C, whose neighbours lie 1 or 2 steps along an axis). */
+enum { FMO_ORDER_NATURAL = 0, FMO_ORDER_REDBLACK = 1, FMO_ORDER_COLOR3 = 2 };
 enum { FMO_PRECOND_IC0 = 0, FMO_PRECOND_DIAG = 1, FMO_PRECOND_NONE = 2 };
 
 /* Columns of the per-iteration trace written by fmo_solve. */

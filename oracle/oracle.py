@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libfmo.so")
 _lib = None
 
-NATURAL, REDBLACK = 0, 1
+NATURAL, REDBLACK, COLOR3 = 0, 1, 2
 IC0, DIAG, NONE = 0, 1, 2
 TR = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)
 TR_W = 8

@@ -11,7 +11,10 @@ volume and the mask.  The pins:
   its trace is 6 per row, and the diagonal routine agrees with it;
 - the general IC(0) is exact on a line (banded, no fill outside the band), so
   it equals numpy's dense solve there; on 3D volumes L D L^T reproduces H on
-  H's pattern; for first-order C it equals the specialised IC(0);
+  the 13-point stencil in natural, red-black and three-colour order; in
+  three-colour order the first two colours' pivots have closed forms in H and
+  no colour couples to itself; for first-order C it equals the specialised
+  IC(0);
 - the gradient dphi + beta C^T C f is the derivative of the cost (central
   differences), and a noise-free affine field is recovered by the solve.
 """
@@ -105,7 +108,25 @@ def test_general_ic_exact_on_a_line():
     assert np.all(piv > 0)
 
 
-@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+def stencil_pattern(shape, mask):
+    """In-mask pairs (j, k) with k 0, 1 or 2 steps from j along one axis (the 13-point stencil)."""
+    n = int(np.prod(shape))
+    P = np.zeros((n, n), bool)
+    idx = np.arange(n).reshape(shape)
+    for j in range(n):
+        c = np.unravel_index(j, shape)
+        P[j, j] = True
+        for ax in range(3):
+            for d in (-2, -1, 1, 2):
+                t = list(c)
+                t[ax] += d
+                if 0 <= t[ax] < shape[ax]:
+                    P[j, idx[tuple(t)]] = True
+    m = mask.ravel().astype(bool)
+    return P[np.ix_(m, m)]
+
+
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK, O.COLOR3])
 def test_general_ic_reproduces_h_on_its_pattern(ordering):
     shape = (4, 4, 5)
     rng = np.random.default_rng(5)
@@ -120,11 +141,46 @@ def test_general_ic_reproduces_h_on_its_pattern(ordering):
     Hm = H[np.ix_(m, m)]
     pattern = np.abs(Hm) > 0
     np.testing.assert_allclose(M[pattern], Hm[pattern], rtol=1e-9, atol=1e-12)
+    # on the whole stencil, also where C^T C is 0 (L is kept on the stencil)
+    st = stencil_pattern(shape, mask)
+    np.testing.assert_allclose(M[st], Hm[st], rtol=1e-9, atol=1e-11)
     # and it is not H itself: IC(0) drops fill (so the pin is not vacuous)
     assert np.abs(M - Hm).max() > 1e-6
 
 
-@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+def test_three_colour_pivots_in_closed_form():
+    """In three-colour order the first colour has no earlier neighbours (pivot H_jj) and the
+    second only first-colour ones, whose pivots are their H_kk: pivot H_jj - sum_k H_jk^2 / H_kk.
+    Both come from the dense H here, not from the factorisation."""
+    shape = (5, 4, 6)
+    rng = np.random.default_rng(8)
+    mask = (rng.uniform(size=shape) < 0.85).astype(np.uint8)
+    beta = 0.3
+    pb = problem(shape, beta=beta, ordering=O.COLOR3)
+    curv = rng.uniform(0.05, 0.4, shape) * mask
+    H = matrix(lambda f: beta * O.laplacian(pb, mask, f), shape) + np.diag(curv.ravel())
+    _, piv = O.ic_general(pb, mask, curv, np.zeros(shape))
+    x, y, z = np.meshgrid(*[np.arange(s_) for s_ in shape], indexing="ij")
+    col = ((x + y + z) % 3).ravel()
+    m = mask.ravel().astype(bool)
+    piv = piv.ravel()
+    for j in np.flatnonzero(m & (col == 0)):
+        assert abs(piv[j] - H[j, j]) <= 1e-12 * H[j, j]
+    checked = 0
+    for j in np.flatnonzero(m & (col == 1)):
+        ks = [k for k in np.flatnonzero(H[j]) if k != j and col[k] == 0]
+        ref = H[j, j] - sum(H[j, k] ** 2 / H[k, k] for k in ks)
+        assert abs(piv[j] - ref) <= 1e-12 * H[j, j]
+        checked += len(ks) > 0
+    assert checked > 10
+    # no two voxels of one colour are coupled by H
+    for c in range(3):
+        sel = np.flatnonzero(m & (col == c))
+        blk = H[np.ix_(sel, sel)]
+        assert np.count_nonzero(blk - np.diag(np.diag(blk))) == 0
+
+
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK, O.COLOR3])
 def test_general_ic_equals_specialised_first_order(ordering):
     shape = (5, 6, 4)
     rng = np.random.default_rng(6)
@@ -156,8 +212,8 @@ def test_gradient_is_the_derivative_of_the_cost():
         assert abs(num - float(np.sum(g * d))) < 1e-6 * max(1.0, abs(num))
 
 
-@pytest.mark.parametrize("precond", [O.IC0, O.DIAG])
-def test_noise_free_affine_field_is_recovered(precond):
+@pytest.mark.parametrize("precond,ordering", [(O.IC0, O.NATURAL), (O.IC0, O.COLOR3), (O.DIAG, O.NATURAL)])
+def test_noise_free_affine_field_is_recovered(precond, ordering):
     shape = (8, 7, 6)
     te = [0.0, 1.5e-3, 4.0e-3]
     x, y, z = np.meshgrid(*[np.arange(s, dtype=float) for s in shape], indexing="ij")
@@ -165,7 +221,7 @@ def test_noise_free_affine_field_is_recovered(precond):
     y_img = np.stack([np.exp(2j * np.pi * f_true * t) for t in te])[None]
     vol = synth.Volume(y=y_img.astype(np.complex64), sens=None, te=np.array(te), mask=np.ones(shape, np.uint8),
                        f_true=f_true, beta=0.5, niter=60, reg_order=2)
-    ref = O.run_volume(vol, O.NATURAL, precond)
+    ref = O.run_volume(vol, ordering, precond)
     assert np.abs(ref["f"] - f_true).max() < 1e-6
     # monotone while the cost is above the rounding floor of its own evaluation (1 - cos of
     # phases near 0 over 336 voxels: about 1e-13 absolute)
