@@ -62,9 +62,13 @@ typedef enum { FM_FIELDMAP = 0, FM_WATERFAT = 1 } fm_model;
 /* F64: FP64 storage and arithmetic throughout.  MIX: FP32 per-voxel storage
  * and arithmetic with FP64 pivots, reductions and scalars. */
 typedef enum { FM_PREC_F64 = 0, FM_PREC_MIX = 1 } fm_precision;
-/* Elimination order of the IC(0) factor: natural (lexicographic, z fastest)
- * or red-black (voxels with x+y+z even first, each colour in natural order). */
-typedef enum { FM_ORDER_NATURAL = 0, FM_ORDER_REDBLACK = 1 } fm_ordering;
+/* Elimination order of the IC(0) factor (Sec. III-B eq. (precon)): natural
+ * (lexicographic, z fastest), red-black (voxels with x+y+z even first, each
+ * colour in natural order), or three-colour ((x+y+z) mod 3 = 0, 1, 2, each in
+ * natural order; the order for second-order differences, whose 13-point
+ * C^T C couples voxels 1 and 2 steps apart and so couples voxels of one
+ * red-black colour; built for reg_order 2 with IC(0) only). */
+typedef enum { FM_ORDER_NATURAL = 0, FM_ORDER_REDBLACK = 1, FM_ORDER_COLOR3 = 2 } fm_ordering;
 /* Preconditioner: IC(0) (the paper's), diag(H), or none. */
 typedef enum { FM_PRECOND_IC0 = 0, FM_PRECOND_DIAG = 1, FM_PRECOND_NONE = 2 } fm_precond;
 
@@ -101,9 +105,9 @@ typedef struct {
   int32_t precond;               /* fm_precond */
   int32_t reg_order;             /* C of eq. (cost): 1 (also when 0) first-order finite differences,
                                     2 second-order (rows f_{j-e} - 2 f_j + f_{j+e} with all three voxels
-                                    in the volume and the mask); 2 needs the field-map model and the
-                                    diagonal or identity preconditioner (FM_ERR_ARG otherwise), and is
-                                    not available to batches or fm_adjoint */
+                                    in the volume and the mask); 2 needs the field-map model and, with
+                                    IC(0), the three-colour order (FM_ERR_ARG otherwise), and is not
+                                    available to batches or fm_adjoint */
 } fm_params;
 
 typedef struct fm_plan fm_plan;

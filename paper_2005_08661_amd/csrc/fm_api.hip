@@ -68,6 +68,8 @@ struct fm_plan {
   void *Z[2] = {nullptr, nullptr};
   void *G[2] = {nullptr, nullptr};
   void *D = nullptr, *X = nullptr, *P = nullptr;
+  void *X2 = nullptr;          // three-colour IC(0): y' = L^{-1} g_prev of colour 1
+  uint8_t *rdiag = nullptr;    // three-colour IC(0): diag(C^T C) of the second-order operator
   double *ipiv = nullptr;
   double *hinv = nullptr;
   fm::State *S = nullptr;      // two ping-pong state copies
@@ -235,7 +237,9 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   }
   a.D = (T *)p->D;
   a.X = (T *)p->X;
+  a.X2 = (T *)p->X2;
   a.P = (T *)p->P;
+  a.rdiag = p->rdiag;
   a.ipiv = p->ipiv;
   a.hinv = p->hinv;
   a.write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? 1 : 0;
@@ -301,7 +305,21 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
     a.store_piv = gsrc ? 1 : 0;  // the standalone call reports the pivots
     return a;
   };
-  if (p->prm.precond == FM_PRECOND_IC0) {
+  if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_COLOR3) {
+    // second-order C: forward colours 0-1, forward colour 2 (+ its p), backward colours 1, 0
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_ic3_fwd1<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
+    FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_ic3_fwd2<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
+    FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_ic3_bwd1<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++));
+    FM_LAUNCH_CHECK();
+    set_parts(p, 0, 0);
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_ic3_bwd0<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
+    FM_LAUNCH_CHECK();
+    set_parts(p, 0, 0);
+  } else if (p->prm.precond == FM_PRECOND_IC0) {
     if (p->prm.ordering == FM_ORDER_NATURAL) {
       FM_LAUNCH(FM_K_PRECOND_A, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, pargs(p, p->q++), p->wf, gsrc);
       FM_LAUNCH_CHECK();
@@ -334,7 +352,9 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
 // Launches per iteration (must match enqueue_iteration).
 uint64_t launches_per_iteration(const fm_plan *p) {
   // preconditioner passes + direction; red-black IC(0) forms the direction in its red pass
-  const uint64_t precond_dir = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_NATURAL) ? 3 : 2;
+  uint64_t precond_dir = 2;
+  if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_NATURAL) precond_dir = 3;
+  if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_COLOR3) precond_dir = 5;
   return 1 + precond_dir + (uint64_t)(p->prm.nmls - 1);
 }
 
@@ -475,13 +495,16 @@ fm_status validate(const fm_params *p) {
   if (p->nmls < 1) return fail(FM_ERR_ARG, "nmls must be >= 1");
   if (p->model != FM_FIELDMAP && p->model != FM_WATERFAT) return fail(FM_ERR_ARG, "bad model");
   if (p->precision != FM_PREC_F64 && p->precision != FM_PREC_MIX) return fail(FM_ERR_ARG, "bad precision");
-  if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK) return fail(FM_ERR_ARG, "bad ordering");
+  if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK && p->ordering != FM_ORDER_COLOR3)
+    return fail(FM_ERR_ARG, "bad ordering");
   if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_NONE) return fail(FM_ERR_ARG, "bad preconditioner");
   if (p->reg_order < 0 || p->reg_order > 2) return fail(FM_ERR_ARG, "reg_order must be 1 or 2");
   if (p->reg_order == 2 && p->model != FM_FIELDMAP)
     return fail(FM_ERR_ARG, "second-order differences are built for the field-map model only");
-  if (p->reg_order == 2 && p->precond == FM_PRECOND_IC0)
-    return fail(FM_ERR_ARG, "IC(0) with second-order differences is not built: use the diagonal or identity preconditioner");
+  if (p->reg_order == 2 && p->precond == FM_PRECOND_IC0 && p->ordering != FM_ORDER_COLOR3)
+    return fail(FM_ERR_ARG, "IC(0) with second-order differences is built in three-colour order (FM_ORDER_COLOR3)");
+  if (p->ordering == FM_ORDER_COLOR3 && (p->reg_order != 2 || p->precond != FM_PRECOND_IC0))
+    return fail(FM_ERR_ARG, "three-colour order is built for IC(0) with second-order differences only");
   if (p->model == FM_FIELDMAP && p->te[1] == p->te[0])
     return fail(FM_ERR_ARG, "field-map initialisation needs t_2 != t_1");
   if (p->model == FM_WATERFAT) {
@@ -962,6 +985,10 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   FM_ALLOC_PAD(p->X, ts);
   FM_ALLOC_PAD(p->P, ts);
   FM_ALLOC_PAD(p->ipiv, sizeof(double));
+  if (p->reg2 && prm->precond == FM_PRECOND_IC0) {
+    FM_ALLOC_PAD(p->X2, ts);
+    FM_ALLOC_PAD(p->rdiag, 1);
+  }
   FM_ALLOC_PAD(p->hinv, sizeof(double));
   FM_ALLOC(p->S, sizeof(fm::State) * 2);
   {
@@ -1084,6 +1111,10 @@ fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *m
     FM_LAUNCH_CHECK();
     hipLaunchKernelGGL(fm::k_count, dim3(1), dim3(kBlock), 0, s, (const double *)p->setup_part, p->grid, p->nmask);
     FM_LAUNCH_CHECK();
+    if (p->rdiag) {
+      hipLaunchKernelGGL(fm::k_rdiag2, dim3(p->grid), dim3(kBlock), 0, s, p->geo, (const uint8_t *)p->code, p->rdiag);
+      FM_LAUNCH_CHECK();
+    }
     return FM_OK;
   };
   fm_status st = p->mix ? launch(float{}) : launch(double{});

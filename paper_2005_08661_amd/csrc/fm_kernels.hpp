@@ -263,7 +263,9 @@ struct IterArgs {
   T *G[2];
   T *D;
   T *X;
+  T *X2;         // second forward-solve vector (three-colour IC(0))
   T *P;
+  const uint8_t *rdiag;  // diag(C^T C) of the second-order operator (three-colour IC(0))
   double *ipiv;  // 1 / pivot
   double *hinv;  // 1 / (D + beta deg), written by the gradient pass when needed
   int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0))

@@ -277,4 +277,275 @@ __global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
   put_state(st, a.sout, PK_DIR, vw.nb, vw.leader);
 }
 
+// ---------------------------------------------------------------------------
+// IC(0) of H = diag(D) + beta C^T C in three-colour order (colour (x+y+z) mod
+// 3, then natural), Sec. III-B eqs. (precon_hess), (precon).  No two voxels
+// of a colour are coupled, and along an axis line through a voxel of colour c
+// the voxels at -1, +2 have colour c-1 and those at +1, -2 colour c+1.  So:
+//   colour 0: pivot H_jj, y_j = g_j;
+//   colour 1: earlier neighbours j-e, j+2e (colour 0), no fill terms;
+//   colour 2: earlier neighbours j+e, j-2e (colour 0) and j-e, j+2e
+//     (colour 1); the colour-1 entries carry the fill terms of incomplete
+//     L D L^T through their common colour-0 neighbours:
+//       L(j,j-e)  D(j-e)  = H(j,j-e)  - H(j,j-2e) H(j-e,j-2e)/D(j-2e)
+//                                     - H(j,j+e)  H(j-e,j+e)/D(j+e),
+//       L(j,j+2e) D(j+2e) = H(j,j+2e) - H(j,j+e)  H(j+2e,j+e)/D(j+e).
+// Forward L y = g over colours 0, 1, 2 and backward L^T p = D^{-1} y over
+// colours 2, 1, 0 take four passes; g^T p = sum y^2/D and g_prev^T p =
+// sum y' y / D with y' = L^{-1} g_prev come out of the forward passes.
+// Off-diagonal entries along axis a (rows r at the centre voxel):
+//   H(j,j+-e) = beta (-2 r_j - 2 r_{j+-e}),  H(j,j+-2e) = beta r_{j+-e}.
+
+__device__ __forceinline__ int colour3(const Geo &g, int j) {
+  const int z = j % g.nz, yx = j / g.nz, y = yx % g.ny, x = yx / g.ny;
+  return (x + y + z) % 3;
+}
+
+// In-mask flags and row indicators on the axis line through voxel j (in the
+// mask, code c): voxels j-e, j+e, j-2e, j+2e (the last two only reached
+// through an in-mask middle voxel: a +-2 neighbour behind a hole couples to
+// j through nothing) and the entries of H/beta among them.
+struct Line2 {
+  bool m1, p1, m2, p2;   // j-e, j+e, j-2e, j+2e in the mask
+  double hm1, hp1;       // H(j,j-e), H(j,j+e)
+  double hm2, hp2;       // H(j,j-2e), H(j,j+2e)
+  double hm1m2, hp1p2;   // H(j-e,j-2e), H(j+e,j+2e)
+  double hm1p1;          // H(j-e,j+e)
+  __device__ __forceinline__ Line2(const uint8_t *__restrict__ code, uint32_t c, int j, int a, int o, double beta) {
+    m1 = has_nb(c, 2 * a);
+    p1 = has_nb(c, 2 * a + 1);
+    const uint32_t cm1 = m1 ? code[j - o] : 0u, cp1 = p1 ? code[j + o] : 0u;
+    m2 = has_nb(cm1, 2 * a);
+    p2 = has_nb(cp1, 2 * a + 1);
+    const uint32_t cm2 = m2 ? code[j - 2 * o] : 0u, cp2 = p2 ? code[j + 2 * o] : 0u;
+    const double r0 = row2(c, a) ? 1.0 : 0.0, rm1 = row2(cm1, a) ? 1.0 : 0.0, rp1 = row2(cp1, a) ? 1.0 : 0.0;
+    const double rm2 = row2(cm2, a) ? 1.0 : 0.0, rp2 = row2(cp2, a) ? 1.0 : 0.0;
+    hm1 = beta * (-2.0 * r0 - 2.0 * rm1);
+    hp1 = beta * (-2.0 * r0 - 2.0 * rp1);
+    hm2 = beta * rm1;
+    hp2 = beta * rp1;
+    hm1m2 = beta * (-2.0 * rm1 - 2.0 * rm2);
+    hp1p2 = beta * (-2.0 * rp1 - 2.0 * rp2);
+    hm1p1 = beta * r0;
+  }
+};
+
+// diag(C^T C) per voxel (0 outside the mask), once per setup.
+__global__ __launch_bounds__(kBlock) void k_rdiag2(Geo g, const uint8_t *__restrict__ code, uint8_t *rdiag) {
+  const Offs of(g);
+  for (int j = (int)blockIdx.x * kBlock + (int)threadIdx.x; j < (int)g.n; j += (int)gridDim.x * kBlock) {
+    const uint32_t c = code[j];
+    uint32_t cn[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) cn[k] = has_nb(c, k) ? code[j + of.o[k]] : 0u;
+    rdiag[j] = (c & NB_SELF) ? (uint8_t)Rows2(c, cn).diag() : (uint8_t)0;
+  }
+}
+
+// Forward pass over colours 0 and 1: pivots (stored inverted), y and y' of
+// colour 1, and their terms of the two dot products.  gsrc: standalone call.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ic3_fwd1(IterArgs<T> a0, const T *__restrict__ gsrc) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
+  const T *__restrict__ gp = a.Gp;
+  const Offs of(g);
+  const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  double acc[2] = {0.0, 0.0};
+  int bad = 0;
+  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
+    const int col = colour3(g, j);
+    if (col == 2) continue;
+    const uint32_t c = a.code[j];
+    if (!(c & NB_SELF)) {
+      a.ipiv[j] = 0.0;
+      if (col == 1) {
+        a0.X[j] = T(0);
+        a0.X2[j] = T(0);
+      }
+      continue;
+    }
+    double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
+    double y = (double)gg[j], y2 = (double)gp[j];
+    if (col == 1) {
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int o = of.o[2 * ax + 1];
+        const Line2 l(a.code, c, j, ax, o, beta);
+        if (l.m1 && l.hm1 != 0.0) {
+          const int k = j - o;
+          const double lk = l.hm1 / ((double)a.D[k] + beta * (double)a0.rdiag[k]);
+          d -= l.hm1 * lk;
+          y -= lk * (double)gg[k];
+          y2 -= lk * (double)gp[k];
+        }
+        if (l.p2 && l.hp2 != 0.0) {
+          const int k = j + 2 * o;
+          const double lk = l.hp2 / ((double)a.D[k] + beta * (double)a0.rdiag[k]);
+          d -= l.hp2 * lk;
+          y -= lk * (double)gg[k];
+          y2 -= lk * (double)gp[k];
+        }
+      }
+    }
+    double ip = 1.0 / d;
+    if (!(d > 0.0)) {
+      bad = 1;
+      ip = 0.0;
+    }
+    a.ipiv[j] = ip;
+    if (col == 1) {
+      a0.X[j] = (T)y;
+      a0.X2[j] = (T)y2;
+    }
+    acc[0] += y * y * ip;
+    acc[1] += y2 * y * ip;
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS_A, vw.nb, vw.leader);
+}
+
+// Forward pass over colour 2 with the fill terms, its pivots, and the first
+// backward step p = y / D; the rest of the dot products.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ic3_fwd2(IterArgs<T> a0, const T *__restrict__ gsrc) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
+  const T *__restrict__ gp = a.Gp;
+  const Offs of(g);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  double acc[2] = {0.0, 0.0};
+  int bad = 0;
+  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
+    if (colour3(g, j) != 2) continue;
+    const uint32_t c = a.code[j];
+    if (!(c & NB_SELF)) {
+      a.ipiv[j] = 0.0;
+      a.P[j] = T(0);
+      continue;
+    }
+    double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
+    double y = (double)gg[j], y2 = (double)gp[j];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int o = of.o[2 * ax + 1];
+      const Line2 l(a.code, c, j, ax, o, beta);
+      const double ipm1 = l.m1 ? a.ipiv[j - o] : 0.0, ipp1 = l.p1 ? a.ipiv[j + o] : 0.0;
+      const double ipm2 = l.m2 ? a.ipiv[j - 2 * o] : 0.0, ipp2 = l.p2 ? a.ipiv[j + 2 * o] : 0.0;
+      // colour 0: j+e and j-2e; colour 1: j-e and j+2e (entries times the pivot of the neighbour)
+      const double np1 = l.hp1, nm2 = l.hm2;
+      const double nm1 = l.hm1 - l.hm2 * l.hm1m2 * ipm2 - l.hp1 * l.hm1p1 * ipp1;
+      const double np2 = l.hp2 - l.hp1 * l.hp1p2 * ipp1;
+      const double lp1 = np1 * ipp1, lm2 = nm2 * ipm2, lm1 = nm1 * ipm1, lp2 = np2 * ipp2;
+      d -= np1 * lp1 + nm2 * lm2 + nm1 * lm1 + np2 * lp2;
+      if (l.p1) {
+        y -= lp1 * (double)gg[j + o];
+        y2 -= lp1 * (double)gp[j + o];
+      }
+      if (l.m2) {
+        y -= lm2 * (double)gg[j - 2 * o];
+        y2 -= lm2 * (double)gp[j - 2 * o];
+      }
+      if (l.m1) {
+        y -= lm1 * (double)a0.X[j - o];
+        y2 -= lm1 * (double)a0.X2[j - o];
+      }
+      if (l.p2) {
+        y -= lp2 * (double)a0.X[j + 2 * o];
+        y2 -= lp2 * (double)a0.X2[j + 2 * o];
+      }
+    }
+    double ip = 1.0 / d;
+    if (!(d > 0.0)) {
+      bad = 1;
+      ip = 0.0;
+    }
+    a.ipiv[j] = ip;
+    a.P[j] = (T)(y * ip);
+    acc[0] += y * y * ip;
+    acc[1] += y2 * y * ip;
+  }
+  if (bad) set_status(a.status, 5);
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
+}
+
+// Backward pass over colour 1: p_j = y_j / D_j - L(j+e,j) p_{j+e} - L(j-2e,j) p_{j-2e}
+// (the colour-2 neighbours' entries, fill terms included, recomputed).
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ic3_bwd1(IterArgs<T> a0) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const Offs of(g);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
+    if (colour3(g, j) != 1) continue;
+    const uint32_t c = a.code[j];
+    if (!(c & NB_SELF)) {
+      a.P[j] = T(0);
+      continue;
+    }
+    const double ip = a.ipiv[j];
+    double s = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int o = of.o[2 * ax + 1];
+      const Line2 l(a.code, c, j, ax, o, beta);
+      const double ipm1 = l.m1 ? a.ipiv[j - o] : 0.0, ipp2 = l.p2 ? a.ipiv[j + 2 * o] : 0.0;
+      if (l.p1) {  // i = j+e: L(i,j) D_j = H(i,j) - H(i,j-e) H(j,j-e)/D(j-e) - H(i,j+2e) H(j,j+2e)/D(j+2e)
+        const double n = l.hp1 - l.hm1p1 * l.hm1 * ipm1 - l.hp1p2 * l.hp2 * ipp2;
+        s += n * (double)a.P[j + o];
+      }
+      if (l.m2) {  // i = j-2e: L(i,j) D_j = H(i,j) - H(i,j-e) H(j-e,j)/D(j-e)
+        const double n = l.hm2 - l.hm1m2 * l.hm1 * ipm1;
+        s += n * (double)a.P[j - 2 * o];
+      }
+    }
+    a.P[j] = (T)(((double)a0.X[j] - s) * ip);
+  }
+  put_state(st, a.sout, PK_NONE, 0, vw.leader);
+}
+
+// Backward pass over colour 0: p_j = (g_j - sum_i H(j,i) p_i) / D_j over the
+// stencil neighbours (colours 1 and 2).
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_ic3_bwd0(IterArgs<T> a0, const T *__restrict__ gsrc) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<T> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
+  const Offs of(g);
+  const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
+  const double beta = a.beta;
+  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
+    if (colour3(g, j) != 0) continue;
+    const uint32_t c = a.code[j];
+    if (!(c & NB_SELF)) {
+      a.P[j] = T(0);
+      continue;
+    }
+    double s = (double)gg[j];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int o = of.o[2 * ax + 1];
+      const Line2 l(a.code, c, j, ax, o, beta);
+      if (l.m1) s -= l.hm1 * (double)a.P[j - o];
+      if (l.p1) s -= l.hp1 * (double)a.P[j + o];
+      if (l.m2) s -= l.hm2 * (double)a.P[j - 2 * o];
+      if (l.p2) s -= l.hp2 * (double)a.P[j + 2 * o];
+    }
+    a.P[j] = (T)(s * a.ipiv[j]);
+  }
+  put_state(st, a.sout, PK_NONE, 0, vw.leader);
+}
+
 }  // namespace fm

@@ -1,10 +1,11 @@
 """Second-order finite-difference regulariser on the GPU against the FP64 oracle.
 
 The GPU builds it for the field-map model with the diagonal and identity
-preconditioners (IC(0) of the 13-point pattern is in the oracle only).  Bars as
-in the first-order parity tests: F64 within 1e-3 Hz RMS (in practice round-off)
-with identical restart decisions, MIX within 0.05 Hz RMS; the stencil and the
-diagonal preconditioner element by element; refusals for what is not built.
+preconditioners and with IC(0) in three-colour order.  Bars as in the
+first-order parity tests: F64 within 1e-3 Hz RMS (in practice round-off)
+with identical restart decisions, MIX within 0.05 Hz RMS; the stencil, the
+diagonal preconditioner and the IC(0) solve and pivots element by element;
+refusals for what is not built.
 """
 import numpy as np
 import pytest
@@ -82,6 +83,96 @@ def test_diagonal_preconditioner_matches_oracle(prec):
     assert np.abs(p - np.where(msk, g / np.where(msk, h, 1.0), 0.0)).max() <= tol * np.abs(g).max() / h[msk].min()
 
 
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", list(VOLS))
+def test_ic0_three_colour_matches_oracle(vname, prec):
+    """p = M^{-1} g and the pivots of IC(0) in three-colour order, fill terms included."""
+    vol = VOLS[vname]()
+    say("order-2 IC(0) three-colour %s %s" % (vname, prec))
+    rng = np.random.default_rng(13)
+    curv = rng.uniform(0, 0.1, vol.shape) * vol.mask
+    g = rng.normal(size=vol.shape) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=PREC[prec], ordering=fmap.COLOR3, precond=fmap.IC0)) as plan:
+        plan.setup(y, s, m)
+        piv, p = (t.cpu().numpy() for t in plan.precondition(torch.from_numpy(curv).cuda(), torch.from_numpy(g).cuda()))
+    pb = O.problem_for(vol, ordering=O.COLOR3, precond=O.IC0)
+    cref = curv if prec == "f64" else curv.astype(np.float32).astype(np.float64)
+    gref = g if prec == "f64" else g.astype(np.float32).astype(np.float64)
+    p_ref, piv_ref = O.ic_general(pb, vol.mask, cref, gref)
+    msk = vol.mask.astype(bool)
+    np.testing.assert_allclose(piv[msk], piv_ref[msk], rtol=1e-12)  # FP64 pivots in both precisions
+    assert np.all(piv[~msk] == 0) and np.all(p[~msk] == 0)
+    tol = 1e-11 if prec == "f64" else 2e-6
+    assert np.abs(p - p_ref).max() <= tol * np.abs(p_ref).max()
+
+
+def test_ic0_three_colour_has_fill_terms():
+    """The GPU result differs from the same factorisation without the colour-2 fill terms by far
+    more than its error: the fill terms are really applied (a pin against a plausible omission)."""
+    vol = VOLS["ragged_paper_mask"]()
+    vol.mask[:] = 1
+    rng = np.random.default_rng(14)
+    curv = rng.uniform(0.01, 0.05, vol.shape)
+    g = rng.normal(size=vol.shape)
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=fmap.COLOR3, precond=fmap.IC0)) as plan:
+        plan.setup(y, s, m)
+        piv, _ = (t.cpu().numpy() for t in plan.precondition(torch.from_numpy(curv).cuda(), torch.from_numpy(g).cuda()))
+    pb = O.problem_for(vol, ordering=O.COLOR3, precond=O.IC0)
+    # colour-2 pivots without fill: H_jj - sum over earlier stencil neighbours H_jk^2 / D_k
+    H = lambda f: pb.beta * O.laplacian(pb, vol.mask, f)
+    _, piv_ref = O.ic_general(pb, vol.mask, curv, np.zeros(vol.shape))
+    x, yy, z = np.meshgrid(*[np.arange(n_) for n_ in vol.shape], indexing="ij")
+    col = (x + yy + z) % 3
+    np.testing.assert_allclose(piv, piv_ref, rtol=1e-12)
+    nofill = []
+    for j in zip(*np.nonzero(col == 2)):
+        e = np.zeros(vol.shape)
+        e[j] = 1.0
+        h = H(e)
+        d = curv[j] + h[j]
+        for k in zip(*np.nonzero((h != 0) & (col != 2))):
+            d -= h[k] ** 2 / piv_ref[k]
+        nofill.append(abs(d - piv_ref[j]) / piv_ref[j])
+    assert max(nofill) > 1e-6
+
+
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+@pytest.mark.parametrize("vname", ["ragged_paper_mask", "random_mask"])
+def test_ic0_three_colour_solve_matches_oracle(vname, prec):
+    vol = VOLS[vname]()
+    say("order-2 IC(0) solve %s %s" % (vname, prec))
+    f, tr = fmap.solve_volume(vol, precision=PREC[prec], ordering=fmap.COLOR3, precond=fmap.IC0)
+    ref = O.run_volume(vol, O.COLOR3, O.IC0)
+    msk = vol.mask.astype(bool)
+    err = rms(f - ref["f"], msk)
+    say("  rms vs oracle %.3e Hz" % err)
+    assert np.all(f[~msk] == 0)
+    rt = ref["trace"]
+    if prec == "f64":
+        assert err < 1e-3
+        np.testing.assert_array_equal(tr[:-1, 3], rt[:-1, O.TR["restart"]])
+        np.testing.assert_allclose(tr[:, 0], rt[:, O.TR["cost"]], rtol=1e-9)
+        np.testing.assert_allclose(tr[:-1, 1], rt[:-1, O.TR["gtp"]], rtol=1e-8)  # g^T p = sum y^2 / D
+    else:
+        assert err < 0.05
+        np.testing.assert_allclose(tr[:, 0], rt[:, O.TR["cost"]], rtol=1e-4)
+
+
+def test_ic0_three_colour_converges_faster_than_diagonal():
+    vol = vol2((24, 20, 16), 4, beta=2.0 ** -2, niter=30, ncoil=2)
+    vol.mask[:] = 1
+    _, tr_ic = fmap.solve_volume(vol, precision=fmap.F64, ordering=fmap.COLOR3, precond=fmap.IC0)
+    _, tr_d = fmap.solve_volume(vol, precision=fmap.F64, precond=fmap.DIAG)
+    c_ic, c_d = tr_ic[:, 0], tr_d[:, 0]
+    final = min(c_ic[-1], c_d[-1])
+    gap = lambda c: np.argmax(c - final <= 1e-3 * (c[0] - final))
+    say("  iterations to a 1e-3 gap: IC(0) %d, diagonal %d" % (gap(c_ic), gap(c_d)))
+    assert gap(c_ic) < gap(c_d)
+    assert np.all(np.diff(c_ic) <= 1e-12 * c_ic[0])
+
+
 @pytest.mark.parametrize("precond", ["diag", "none"])
 @pytest.mark.parametrize("prec", ["f64", "mix"])
 @pytest.mark.parametrize("vname", ["ragged_paper_mask", "random_mask"])
@@ -140,9 +231,15 @@ def test_large_volume_precisions_agree():
 
 def test_what_is_not_built_is_refused():
     vol = vol2()
-    with pytest.raises(fmap.FmapError) as ei:
-        fmap.Plan(fmap.params_for(vol, precision=fmap.F64, precond=fmap.IC0))
-    assert ei.value.status == 1
+    for order in (fmap.NATURAL, fmap.REDBLACK):  # IC(0) of the second-order C: three-colour order only
+        with pytest.raises(fmap.FmapError) as ei:
+            fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=order, precond=fmap.IC0))
+        assert ei.value.status == 1
+    vol.reg_order = 1  # three-colour order: second-order C and IC(0) only
+    for pc in (fmap.IC0, fmap.DIAG):
+        with pytest.raises(fmap.FmapError):
+            fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=fmap.COLOR3, precond=pc))
+    vol.reg_order = 2
     p = fmap.params_for(vol, precision=fmap.MIX, precond=fmap.DIAG)
     with pytest.raises(fmap.FmapError):
         fmap.Batch([p, p])
