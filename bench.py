@@ -259,6 +259,91 @@ def bench_waterfat(args, fmap, synth, torch):
     return res
 
 
+def order2_bytes_per_voxel(kclass, precision, L):
+    """Algorithmic bytes per voxel of one launch of each kernel class of the
+    second-order regulariser with IC(0) in three-colour order (a third of the
+    voxels per colour; pivots FP64, stored inverted; the diag(C^T C) byte array
+    counted).  The two forward launches share a class, and so do the two
+    backward ones: the figure is their mean."""
+    t = 4 if precision == "mix" else 8
+    if kclass == "grad":       # read code, echoes, f, z_prev; write f, g, D
+        return 1 + 2 * L * t + 5 * t
+    if kclass == "mls":
+        return 1 + 2 * L * t + 2 * t
+    if kclass == "dir":
+        return 1 + 5 * t
+    if kclass == "precond_a":
+        # colours 0-1: read code, D, diag, g, g_prev; write 1/D of colours 0-1, y and y' of colour 1
+        fwd1 = 2 + 3 * t + 16 / 3 + 2 * t / 3
+        # colour 2: read code, 1/D of colours 0-1, D and diag of colour 2, g and g_prev of colours 0 and 2,
+        # y and y' of colour 1; write 1/D and p of colour 2
+        fwd2 = 1 + 16 / 3 + (t + 1) / 3 + 4 * t / 3 + 2 * t / 3 + (8 + t) / 3
+        return (fwd1 + fwd2) / 2
+    if kclass == "precond_b":
+        # colour 1: read code, 1/D of colours 0-1, y of colour 1, p of colour 2; write p of colour 1
+        bwd1 = 1 + 16 / 3 + t
+        # colour 0: read code, g and 1/D of colour 0, p of colours 1-2; write p of colour 0
+        bwd0 = 1 + 8 / 3 + 4 * t / 3
+        return (bwd1 + bwd0) / 2
+    return 0
+
+
+def bench_order2(args, fmap, synth, torch, prec):
+    """Second-order finite differences on the benchmark volume (128x128x64, 8 coils, full mask):
+    full solves with IC(0) in three-colour order and with the diagonal preconditioner, the IC(0)
+    iteration loop, its per-kernel rates against the byte model above, and the iterations each
+    preconditioner needs to a 1e-3 relative cost gap."""
+    log("order 2: generating 128x128x64")
+    vol = synth.mid_fieldmap()
+    vol.reg_order = 2
+    y, s, m = fmap.to_device(vol)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = torch.zeros(vol.shape, dtype=torch.float64, device="cuda")
+    res = {"grid": list(vol.shape), "niter": vol.niter}
+    traces = {}
+    for name, order, pc in (("ic0_color3", fmap.COLOR3, fmap.IC0), ("diag", fmap.NATURAL, fmap.DIAG)):
+        with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=order, precond=pc)) as plan:
+            plan.solve(y, s, m, out=out)
+            torch.cuda.synchronize()
+            ms_solve = time_solve(plan, fmap, y, s, m, out, max(1, args.steps // 2), torch)
+            traces[name] = plan.trace()
+            ev0.record(stream)
+            plan.iterate(vol.niter, out=out)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            ms_loop = ev0.elapsed_time(ev1)
+            n = plan.mask_count()
+            r = {"ms_per_solve": ms_solve, "loop_ms": ms_loop, "value": n * vol.niter / (ms_solve * 1e-3)}
+            if pc == fmap.IC0:
+                kt = plan.time_kernels(args.kernel_iters)
+                kinfo = {}
+                for k, (ms, nl) in kt.items():
+                    if nl == 0:
+                        continue
+                    b = order2_bytes_per_voxel(k, args.precision, vol.necho) * n
+                    avg = ms / nl
+                    kinfo[k] = {"avg_us": round(avg * 1e3, 3), "launches": nl, "gbs": round(b / (avg * 1e-3) / 1e9, 1)}
+                it_b = sum(order2_bytes_per_voxel(k, args.precision, vol.necho) * (2 if k.startswith("precond") else 1)
+                           for k in ("grad", "precond_a", "precond_b", "dir")) \
+                    + (vol.nmls - 1) * order2_bytes_per_voxel("mls", args.precision, vol.necho)
+                r.update(kernels=kinfo, bytes_per_voxel_iteration=round(it_b, 2),
+                         hbm_frac=it_b * n / (ms_loop * 1e-3 / vol.niter) / (HBM_PEAK_GBS * 1e9))
+                for k, v in kinfo.items():
+                    log("  order 2 %-10s %9.2f us/launch  %8.1f GB/s  (%d launches)" % (k, v["avg_us"], v["gbs"],
+                                                                                        v["launches"]))
+            res[name] = r
+            log("order 2 %s: solve %.3f ms (%.3e voxel-iterations/s), loop %.3f ms" % (name, ms_solve, r["value"],
+                                                                                      ms_loop))
+    c_ic, c_d = traces["ic0_color3"][:, 0], traces["diag"][:, 0]
+    final = min(c_ic[-1], c_d[-1])
+    gap = lambda c: int(np.argmax(c - final <= 1e-3 * (c[0] - final))) if np.any(c - final <= 1e-3 * (c[0] - final)) \
+        else None
+    res["iterations_to_1e-3_gap"] = {"ic0_color3": gap(c_ic), "diag": gap(c_d)}
+    log("order 2: iterations to a 1e-3 gap: IC(0) %s, diagonal %s" % (gap(c_ic), gap(c_d)))
+    return res
+
+
 def bench_large(args, fmap, synth, torch, prec):
     """256x256x128 (8.4 M voxels, working set well above the 256 MB Infinity Cache): the field-map
     problem of the benchmark at eight times the size, a true HBM measurement.  2 coils (the coil
@@ -301,8 +386,8 @@ def main():
     ap.add_argument("--precond", choices=["ic0", "diag", "none"], default="ic0")
     ap.add_argument("--mask", choices=["full", "paper"], default="full")
     ap.add_argument("--shape", default="128,128,64")
-    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat"], default="fieldmap",
-                    help="fieldmap: the headline line (default); batched / waterfat: only that workload")
+    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2"], default="fieldmap",
+                    help="fieldmap: the headline line (default); batched / waterfat / order2: only that workload")
     ap.add_argument("--kernel-iters", type=int, default=10)
     ap.add_argument("--cpu-iters", type=int, default=25)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -311,6 +396,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the implicit-adjoint timing")
     ap.add_argument("--no-waterfat", action="store_true", help="skip the 192x192x64 water-fat solve")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x256x128 HBM-sized field-map loop")
+    ap.add_argument("--no-order2", action="store_true", help="skip the second-order regulariser solves")
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the time-to-accuracy comparison of the preconditioners")
     args = ap.parse_args()
@@ -333,6 +419,11 @@ def main():
             value, ms = res["value"], res["ms_per_solve"]
             wl = "16 field-map volumes of 64-160 x 64-160 x 32-96 voxels (%d unknowns), 4 coils, TE 0/2/5 ms, " \
                  "100 NCG iterations, one batched solve, red-black IC(0), %s" % (res["voxels"], args.precision.upper())
+        elif args.workload == "order2":
+            res = bench_order2(args, fmap, synth, torch, prec)
+            value, ms = res["ic0_color3"]["value"], res["ic0_color3"]["ms_per_solve"]
+            wl = "field map 128x128x64, 8 coils, 3 echoes, second-order finite differences, 100 NCG iterations, " \
+                 "IC(0) in three-colour order, %s" % args.precision.upper()
         else:
             res = bench_waterfat(args, fmap, synth, torch)
             value, ms = res["loop_voxel_iterations_per_s"], res["ms_per_solve"]
@@ -470,6 +561,10 @@ def main():
     if not args.no_large and args.shape == "128,128,64":
         large = bench_large(args, fmap, synth, torch, prec)
 
+    order2 = None
+    if not args.no_order2 and args.shape == "128,128,64" and args.mask == "full":
+        order2 = bench_order2(args, fmap, synth, torch, prec)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -529,6 +624,7 @@ def main():
         "final_cost": float(tr[-1, 0]),
         "natural_order": natural,
         "large_256x256x128": large,
+        "second_order": order2,
         "convergence": convergence,
         "adjoint": adjoint,
         "batched": batched,

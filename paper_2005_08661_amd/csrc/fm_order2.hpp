@@ -302,24 +302,27 @@ __device__ __forceinline__ int colour3(const Geo &g, int j) {
 }
 
 // In-mask flags and row indicators on the axis line through voxel j (in the
-// mask, code c): voxels j-e, j+e, j-2e, j+2e (the last two only reached
-// through an in-mask middle voxel: a +-2 neighbour behind a hole couples to
-// j through nothing) and the entries of H/beta among them.
+// mask, code c), from the codes at j-+e (cm1, cp1) and j-+2e (cm2, cp2), all
+// loaded unconditionally (the arrays are padded by two x-planes; a code read
+// past the volume's edge is never trusted: j-2e counts only through an in-mask
+// j-e, whose own code then says whether j-2e is in the mask, and a +-2
+// neighbour behind a hole couples to j through nothing), and the entries of H
+// among them.
 struct Line2 {
   bool m1, p1, m2, p2;   // j-e, j+e, j-2e, j+2e in the mask
   double hm1, hp1;       // H(j,j-e), H(j,j+e)
   double hm2, hp2;       // H(j,j-2e), H(j,j+2e)
   double hm1m2, hp1p2;   // H(j-e,j-2e), H(j+e,j+2e)
   double hm1p1;          // H(j-e,j+e)
-  __device__ __forceinline__ Line2(const uint8_t *__restrict__ code, uint32_t c, int j, int a, int o, double beta) {
+  __device__ __forceinline__ Line2(uint32_t c, uint32_t cm1, uint32_t cp1, uint32_t cm2, uint32_t cp2, int a,
+                                   double beta) {
     m1 = has_nb(c, 2 * a);
     p1 = has_nb(c, 2 * a + 1);
-    const uint32_t cm1 = m1 ? code[j - o] : 0u, cp1 = p1 ? code[j + o] : 0u;
-    m2 = has_nb(cm1, 2 * a);
-    p2 = has_nb(cp1, 2 * a + 1);
-    const uint32_t cm2 = m2 ? code[j - 2 * o] : 0u, cp2 = p2 ? code[j + 2 * o] : 0u;
-    const double r0 = row2(c, a) ? 1.0 : 0.0, rm1 = row2(cm1, a) ? 1.0 : 0.0, rp1 = row2(cp1, a) ? 1.0 : 0.0;
-    const double rm2 = row2(cm2, a) ? 1.0 : 0.0, rp2 = row2(cp2, a) ? 1.0 : 0.0;
+    m2 = m1 && has_nb(cm1, 2 * a);
+    p2 = p1 && has_nb(cp1, 2 * a + 1);
+    const double r0 = row2(c, a) ? 1.0 : 0.0;
+    const double rm1 = (m1 && row2(cm1, a)) ? 1.0 : 0.0, rp1 = (p1 && row2(cp1, a)) ? 1.0 : 0.0;
+    const double rm2 = (m2 && row2(cm2, a)) ? 1.0 : 0.0, rp2 = (p2 && row2(cp2, a)) ? 1.0 : 0.0;
     hm1 = beta * (-2.0 * r0 - 2.0 * rm1);
     hp1 = beta * (-2.0 * r0 - 2.0 * rp1);
     hm2 = beta * rm1;
@@ -329,6 +332,36 @@ struct Line2 {
     hm1p1 = beta * r0;
   }
 };
+
+// The codes at j-+e and j-+2e of the three axes, issued together.
+struct Codes2 {
+  uint32_t m1[3], p1[3], m2[3], p2[3];
+  __device__ __forceinline__ Codes2(const uint8_t *__restrict__ code, int j, const Offs &of) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const int o = of.o[2 * a + 1];
+      m1[a] = code[j - o];
+      p1[a] = code[j + o];
+      m2[a] = code[j - 2 * o];
+      p2[a] = code[j + 2 * o];
+    }
+  }
+};
+
+// Visit the voxels of colour c of the volume (a third of each z-column: every
+// third z from the column's first voxel of that colour), workgroup-strided,
+// so that the lanes of a pass that concerns one colour all work.
+template <typename F>
+__device__ __forceinline__ void for_colour(const Geo &g, int c, int first, int step, F &&f) {
+  const int m = (g.nz + 2) / 3;  // slots per column
+  const int total = g.nx * g.ny * m;
+  for (int t = first; t < total; t += step) {
+    const int col = t / m, k = t - col * m;
+    const int x = col / g.ny, y = col - x * g.ny;
+    const int z = (c + 3 - (x + y) % 3) % 3 + 3 * k;
+    if (z < g.nz) f(col * g.nz + z);
+  }
+}
 
 // diag(C^T C) per voxel (0 outside the mask), once per setup.
 __global__ __launch_bounds__(kBlock) void k_rdiag2(Geo g, const uint8_t *__restrict__ code, uint8_t *rdiag) {
@@ -354,56 +387,66 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd1(IterArgs<T> a0, const T *__res
   const Offs of(g);
   const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
+  const int first = vw.bl * kNT + (int)threadIdx.x, step = vw.nb * kNT;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
-  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
-    const int col = colour3(g, j);
-    if (col == 2) continue;
+  for_colour(g, 0, first, step, [&](int j) {
     const uint32_t c = a.code[j];
-    if (!(c & NB_SELF)) {
-      a.ipiv[j] = 0.0;
-      if (col == 1) {
-        a0.X[j] = T(0);
-        a0.X2[j] = T(0);
-      }
-      continue;
-    }
-    double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
-    double y = (double)gg[j], y2 = (double)gp[j];
-    if (col == 1) {
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const int o = of.o[2 * ax + 1];
-        const Line2 l(a.code, c, j, ax, o, beta);
-        if (l.m1 && l.hm1 != 0.0) {
-          const int k = j - o;
-          const double lk = l.hm1 / ((double)a.D[k] + beta * (double)a0.rdiag[k]);
-          d -= l.hm1 * lk;
-          y -= lk * (double)gg[k];
-          y2 -= lk * (double)gp[k];
-        }
-        if (l.p2 && l.hp2 != 0.0) {
-          const int k = j + 2 * o;
-          const double lk = l.hp2 / ((double)a.D[k] + beta * (double)a0.rdiag[k]);
-          d -= l.hp2 * lk;
-          y -= lk * (double)gg[k];
-          y2 -= lk * (double)gp[k];
-        }
-      }
-    }
+    const double d = (double)a.D[j] + beta * (double)a0.rdiag[j], y = (double)gg[j], y2 = (double)gp[j];
     double ip = 1.0 / d;
-    if (!(d > 0.0)) {
+    if (!(c & NB_SELF)) {
+      ip = 0.0;
+    } else if (!(d > 0.0)) {
       bad = 1;
       ip = 0.0;
     }
     a.ipiv[j] = ip;
-    if (col == 1) {
-      a0.X[j] = (T)y;
-      a0.X2[j] = (T)y2;
-    }
     acc[0] += y * y * ip;
     acc[1] += y2 * y * ip;
-  }
+  });
+  // colour 1: earlier neighbours j-e and j+2e (colour 0, pivots D + beta diag(C^T C))
+  for_colour(g, 1, first, step, [&](int j) {
+    const uint32_t c = a.code[j];
+    const Codes2 cs(a.code, j, of);
+    double dk[6], hk[6], gk[6], gpk[6];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int o = of.o[2 * ax + 1];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = u ? j + 2 * o : j - o;
+        dk[2 * ax + u] = (double)a.D[k] + beta * (double)a0.rdiag[k];
+        gk[2 * ax + u] = (double)gg[k];
+        gpk[2 * ax + u] = (double)gp[k];
+      }
+      const Line2 l(c, cs.m1[ax], cs.p1[ax], cs.m2[ax], cs.p2[ax], ax, beta);
+      hk[2 * ax] = l.m1 ? l.hm1 : 0.0;
+      hk[2 * ax + 1] = l.p2 ? l.hp2 : 0.0;
+    }
+    double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
+    double y = (double)gg[j], y2 = (double)gp[j];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double lk = hk[q] != 0.0 ? hk[q] / dk[q] : 0.0;
+      d -= hk[q] * lk;
+      y -= hk[q] != 0.0 ? lk * gk[q] : 0.0;
+      y2 -= hk[q] != 0.0 ? lk * gpk[q] : 0.0;
+    }
+    double ip = 1.0 / d;
+    if (!(c & NB_SELF)) {
+      ip = 0.0;
+      y = 0.0;
+      y2 = 0.0;
+    } else if (!(d > 0.0)) {
+      bad = 1;
+      ip = 0.0;
+    }
+    a.ipiv[j] = ip;
+    a0.X[j] = (T)y;
+    a0.X2[j] = (T)y2;
+    acc[0] += y * y * ip;
+    acc[1] += y2 * y * ip;
+  });
   if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
   put_state(st, a.sout, PK_DOTS_A, vw.nb, vw.leader);
@@ -423,47 +466,51 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd2(IterArgs<T> a0, const T *__res
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
-  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
-    if (colour3(g, j) != 2) continue;
+  for_colour(g, 2, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int j) {
     const uint32_t c = a.code[j];
-    if (!(c & NB_SELF)) {
-      a.ipiv[j] = 0.0;
-      a.P[j] = T(0);
-      continue;
+    const Codes2 cs(a.code, j, of);
+    // per axis: 1/D at j-e, j+e, j-2e, j+2e; g, g_prev at j+e, j-2e (colour 0); y, y' at j-e, j+2e (colour 1)
+    double ip4[3][4], g2[3][2], gp2[3][2], x2[3][2], xp2[3][2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int o = of.o[2 * ax + 1];
+      ip4[ax][0] = a.ipiv[j - o];
+      ip4[ax][1] = a.ipiv[j + o];
+      ip4[ax][2] = a.ipiv[j - 2 * o];
+      ip4[ax][3] = a.ipiv[j + 2 * o];
+      g2[ax][0] = (double)gg[j + o];
+      g2[ax][1] = (double)gg[j - 2 * o];
+      gp2[ax][0] = (double)gp[j + o];
+      gp2[ax][1] = (double)gp[j - 2 * o];
+      x2[ax][0] = (double)a0.X[j - o];
+      x2[ax][1] = (double)a0.X[j + 2 * o];
+      xp2[ax][0] = (double)a0.X2[j - o];
+      xp2[ax][1] = (double)a0.X2[j + 2 * o];
     }
     double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
     double y = (double)gg[j], y2 = (double)gp[j];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int o = of.o[2 * ax + 1];
-      const Line2 l(a.code, c, j, ax, o, beta);
-      const double ipm1 = l.m1 ? a.ipiv[j - o] : 0.0, ipp1 = l.p1 ? a.ipiv[j + o] : 0.0;
-      const double ipm2 = l.m2 ? a.ipiv[j - 2 * o] : 0.0, ipp2 = l.p2 ? a.ipiv[j + 2 * o] : 0.0;
+      const Line2 l(c, cs.m1[ax], cs.p1[ax], cs.m2[ax], cs.p2[ax], ax, beta);
+      const double ipm1 = l.m1 ? ip4[ax][0] : 0.0, ipp1 = l.p1 ? ip4[ax][1] : 0.0;
+      const double ipm2 = l.m2 ? ip4[ax][2] : 0.0, ipp2 = l.p2 ? ip4[ax][3] : 0.0;
       // colour 0: j+e and j-2e; colour 1: j-e and j+2e (entries times the pivot of the neighbour)
       const double np1 = l.hp1, nm2 = l.hm2;
       const double nm1 = l.hm1 - l.hm2 * l.hm1m2 * ipm2 - l.hp1 * l.hm1p1 * ipp1;
       const double np2 = l.hp2 - l.hp1 * l.hp1p2 * ipp1;
       const double lp1 = np1 * ipp1, lm2 = nm2 * ipm2, lm1 = nm1 * ipm1, lp2 = np2 * ipp2;
       d -= np1 * lp1 + nm2 * lm2 + nm1 * lm1 + np2 * lp2;
-      if (l.p1) {
-        y -= lp1 * (double)gg[j + o];
-        y2 -= lp1 * (double)gp[j + o];
-      }
-      if (l.m2) {
-        y -= lm2 * (double)gg[j - 2 * o];
-        y2 -= lm2 * (double)gp[j - 2 * o];
-      }
-      if (l.m1) {
-        y -= lm1 * (double)a0.X[j - o];
-        y2 -= lm1 * (double)a0.X2[j - o];
-      }
-      if (l.p2) {
-        y -= lp2 * (double)a0.X[j + 2 * o];
-        y2 -= lp2 * (double)a0.X2[j + 2 * o];
-      }
+      y -= (l.p1 ? lp1 * g2[ax][0] : 0.0) + (l.m2 ? lm2 * g2[ax][1] : 0.0) + (l.m1 ? lm1 * x2[ax][0] : 0.0) +
+           (l.p2 ? lp2 * x2[ax][1] : 0.0);
+      y2 -= (l.p1 ? lp1 * gp2[ax][0] : 0.0) + (l.m2 ? lm2 * gp2[ax][1] : 0.0) + (l.m1 ? lm1 * xp2[ax][0] : 0.0) +
+            (l.p2 ? lp2 * xp2[ax][1] : 0.0);
     }
     double ip = 1.0 / d;
-    if (!(d > 0.0)) {
+    if (!(c & NB_SELF)) {
+      ip = 0.0;
+      y = 0.0;
+      y2 = 0.0;
+    } else if (!(d > 0.0)) {
       bad = 1;
       ip = 0.0;
     }
@@ -471,7 +518,7 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd2(IterArgs<T> a0, const T *__res
     a.P[j] = (T)(y * ip);
     acc[0] += y * y * ip;
     acc[1] += y2 * y * ip;
-  }
+  });
   if (bad) set_status(a.status, 5);
   store_partials<2, kNT>(acc, a.pout);
   put_state(st, a.sout, PK_DOTS, vw.nb, vw.leader);
@@ -487,31 +534,32 @@ __global__ __launch_bounds__(kNT) void k_ic3_bwd1(IterArgs<T> a0) {
   const Offs of(g);
   const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
-  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
-    if (colour3(g, j) != 1) continue;
+  for_colour(g, 1, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int j) {
     const uint32_t c = a.code[j];
-    if (!(c & NB_SELF)) {
-      a.P[j] = T(0);
-      continue;
-    }
-    const double ip = a.ipiv[j];
-    double s = 0.0;
+    const Codes2 cs(a.code, j, of);
+    double ipm1[3], ipp2[3], pp1[3], pm2[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const int o = of.o[2 * ax + 1];
-      const Line2 l(a.code, c, j, ax, o, beta);
-      const double ipm1 = l.m1 ? a.ipiv[j - o] : 0.0, ipp2 = l.p2 ? a.ipiv[j + 2 * o] : 0.0;
-      if (l.p1) {  // i = j+e: L(i,j) D_j = H(i,j) - H(i,j-e) H(j,j-e)/D(j-e) - H(i,j+2e) H(j,j+2e)/D(j+2e)
-        const double n = l.hp1 - l.hm1p1 * l.hm1 * ipm1 - l.hp1p2 * l.hp2 * ipp2;
-        s += n * (double)a.P[j + o];
-      }
-      if (l.m2) {  // i = j-2e: L(i,j) D_j = H(i,j) - H(i,j-e) H(j-e,j)/D(j-e)
-        const double n = l.hm2 - l.hm1m2 * l.hm1 * ipm1;
-        s += n * (double)a.P[j - 2 * o];
-      }
+      ipm1[ax] = a.ipiv[j - o];
+      ipp2[ax] = a.ipiv[j + 2 * o];
+      pp1[ax] = (double)a.P[j + o];
+      pm2[ax] = (double)a.P[j - 2 * o];
     }
-    a.P[j] = (T)(((double)a0.X[j] - s) * ip);
-  }
+    const double ip = a.ipiv[j], yj = (double)a0.X[j];
+    double s = 0.0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const Line2 l(c, cs.m1[ax], cs.p1[ax], cs.m2[ax], cs.p2[ax], ax, beta);
+      const double im1 = l.m1 ? ipm1[ax] : 0.0, ip2 = l.p2 ? ipp2[ax] : 0.0;
+      // i = j+e: L(i,j) D_j = H(i,j) - H(i,j-e) H(j,j-e)/D(j-e) - H(i,j+2e) H(j,j+2e)/D(j+2e)
+      const double n1 = l.hp1 - l.hm1p1 * l.hm1 * im1 - l.hp1p2 * l.hp2 * ip2;
+      // i = j-2e: L(i,j) D_j = H(i,j) - H(i,j-e) H(j-e,j)/D(j-e)
+      const double n2 = l.hm2 - l.hm1m2 * l.hm1 * im1;
+      s += (l.p1 ? n1 * pp1[ax] : 0.0) + (l.m2 ? n2 * pm2[ax] : 0.0);
+    }
+    a.P[j] = (c & NB_SELF) ? (T)((yj - s) * ip) : T(0);
+  });
   put_state(st, a.sout, PK_NONE, 0, vw.leader);
 }
 
@@ -526,25 +574,27 @@ __global__ __launch_bounds__(kNT) void k_ic3_bwd0(IterArgs<T> a0, const T *__res
   const Offs of(g);
   const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
-  for (int j = vw.bl * kNT + (int)threadIdx.x; j < (int)g.n; j += vw.nb * kNT) {
-    if (colour3(g, j) != 0) continue;
+  for_colour(g, 0, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int j) {
     const uint32_t c = a.code[j];
-    if (!(c & NB_SELF)) {
-      a.P[j] = T(0);
-      continue;
+    const Codes2 cs(a.code, j, of);
+    double pn[3][4];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const int o = of.o[2 * ax + 1];
+      pn[ax][0] = (double)a.P[j - o];
+      pn[ax][1] = (double)a.P[j + o];
+      pn[ax][2] = (double)a.P[j - 2 * o];
+      pn[ax][3] = (double)a.P[j + 2 * o];
     }
     double s = (double)gg[j];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int o = of.o[2 * ax + 1];
-      const Line2 l(a.code, c, j, ax, o, beta);
-      if (l.m1) s -= l.hm1 * (double)a.P[j - o];
-      if (l.p1) s -= l.hp1 * (double)a.P[j + o];
-      if (l.m2) s -= l.hm2 * (double)a.P[j - 2 * o];
-      if (l.p2) s -= l.hp2 * (double)a.P[j + 2 * o];
+      const Line2 l(c, cs.m1[ax], cs.p1[ax], cs.m2[ax], cs.p2[ax], ax, beta);
+      s -= (l.m1 ? l.hm1 * pn[ax][0] : 0.0) + (l.p1 ? l.hp1 * pn[ax][1] : 0.0) + (l.m2 ? l.hm2 * pn[ax][2] : 0.0) +
+           (l.p2 ? l.hp2 * pn[ax][3] : 0.0);
     }
-    a.P[j] = (T)(s * a.ipiv[j]);
-  }
+    a.P[j] = (c & NB_SELF) ? (T)(s * a.ipiv[j]) : T(0);
+  });
   put_state(st, a.sout, PK_NONE, 0, vw.leader);
 }
 
