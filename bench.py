@@ -389,7 +389,7 @@ def main():
     ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2"], default="fieldmap",
                     help="fieldmap: the headline line (default); batched / waterfat / order2: only that workload")
     ap.add_argument("--kernel-iters", type=int, default=10)
-    ap.add_argument("--cpu-iters", type=int, default=25)
+    ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-natural", action="store_true", help="skip the natural-order comparison line")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-volume batched comparison")
