@@ -35,8 +35,8 @@ def bytes_per_voxel(kclass, precision, L, ordering, precond):
     1/h are FP64."""
     t = 4 if precision == "mix" else 8
     rb = precond == "ic0" and ordering == "redblack"
-    if kclass == "grad":       # read code, echoes, f, z_prev; write f, g, D (+ 1/h)
-        return 1 + 2 * L * t + 5 * t + (8 if rb else 0)
+    if kclass == "grad":       # read code, echoes, f, z_prev; write f, g, D (+ 1/h of red voxels)
+        return 1 + 2 * L * t + 5 * t + (4 if rb else 0)
     if kclass == "mls":        # read code, echoes, f, z
         return 1 + 2 * L * t + 2 * t
     if kclass == "dir":        # read code, p, z_prev, f, D; write z

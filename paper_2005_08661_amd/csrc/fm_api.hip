@@ -242,7 +242,8 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.rdiag = p->rdiag;
   a.ipiv = p->ipiv;
   a.hinv = p->hinv;
-  a.write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? 1 : 0;
+  // the pair-mapped passes (even column length) keep 1/h of red and p of black voxels at the pair's index
+  a.write_hinv = (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_REDBLACK) ? (p->geo.nz % 2 ? 1 : 2) : 0;
   a.store_piv = 0;
   a.par = (int32_t)(p->iter_host & 1);
   a.nparts_in = p->last_nparts;

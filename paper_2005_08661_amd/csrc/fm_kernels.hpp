@@ -268,7 +268,8 @@ struct IterArgs {
   const uint8_t *rdiag;  // diag(C^T C) of the second-order operator (three-colour IC(0))
   double *ipiv;  // 1 / pivot
   double *hinv;  // 1 / (D + beta deg), written by the gradient pass when needed
-  int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0))
+  int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0)): 1 for every voxel at j;
+                       // 2 for the pair-mapped passes: of red voxels only, at their pair j >> 1
   int32_t store_piv;   // preconditioner passes also store every pivot
   int32_t par;         // parity of the iteration this launch belongs to
   int32_t nparts_in;   // partial sums left by the previous launch (blocks)

@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a0) {
         if (!a.final_pass) {
           gg[j] = T(0);
           a.D[j] = T(0);
-          if (a.write_hinv) a.hinv[j] = 0.0;
+          if (a.write_hinv == 1) a.hinv[j] = 0.0;
         }
         continue;
       }
@@ -194,9 +194,9 @@ __global__ __launch_bounds__(kNT) void k_grad(IterArgs<T> a0) {
       if (!a.final_pass) {
         gg[j] = gj;
         a.D[j] = curv;
-        if (a.write_hinv) {
+        if (a.write_hinv == 1 || (a.write_hinv == 2 && !(cv & NB_BLACK))) {
           const double h = (double)curv + a.beta * nb_deg(cv);
-          a.hinv[j] = h > 0.0 ? 1.0 / h : 0.0;
+          a.hinv[a.write_hinv == 2 ? j >> 1 : j] = h > 0.0 ? 1.0 / h : 0.0;
         }
       }
       acc[0] += (double)phi;
@@ -535,18 +535,17 @@ __global__ __launch_bounds__(kNT) void k_rb_black_pair(IterArgs<T> a0) {
       cb[v] = fb ? cA : cB;
       cr[v] = fb ? cB : cA;
       const Duo<T> g2 = ld_duo(gg, j0), gp2 = ld_duo(gp, j0);
-      const Duo<double> h2 = ld_duo(hv, j0);
       g0[v] = fb ? g2.v0 : g2.v1;
       gr[v] = fb ? g2.v1 : g2.v0;
       gp0[v] = fb ? gp2.v0 : gp2.v1;
       gpr[v] = fb ? gp2.v1 : gp2.v0;
-      hr[v] = fb ? h2.v1 : h2.v0;
+      hr[v] = hv[j0 >> 1];
       d0[v] = a.D[jbv];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
         gn[v][k] = gg[jbv + of.o[k]];
         gpn[v][k] = gp[jbv + of.o[k]];
-        hn[v][k] = hv[jbv + of.o[k]];
+        hn[v][k] = hv[(jbv + of.o[k]) >> 1];  // a red neighbour: its pair's entry
       }
     }
   };
@@ -585,7 +584,7 @@ __global__ __launch_bounds__(kNT) void k_rb_black_pair(IterArgs<T> a0) {
       }
       const double yb = (double)g0[v] + beta * sxv;
       const double x = yb * ip;
-      a.P[jb[v]] = (T)x;
+      a.P[jb[v] >> 1] = (T)x;
       acc[0] += yb * x;
       acc[1] += ((double)gp0[v] + beta * syp) * x;
     }
@@ -625,18 +624,18 @@ __global__ __launch_bounds__(kNT) void k_rb_red_dir_pair(IterArgs<T> a0) {
       fbk[v] = fb;
       cb[v] = fb ? cA : cB;
       cr[v] = fb ? cB : cA;
-      const Duo<T> z2 = ld_duo(zp, j0), d2 = ld_duo(a.D, j0), p2 = ld_duo(p, j0);
+      const Duo<T> z2 = ld_duo(zp, j0), d2 = ld_duo(a.D, j0);
       zr[v] = fb ? z2.v1 : z2.v0;
       zb[v] = fb ? z2.v0 : z2.v1;
       dr[v] = fb ? d2.v1 : d2.v0;
       db[v] = fb ? d2.v0 : d2.v1;
-      pb[v] = fb ? p2.v0 : p2.v1;
+      pb[v] = p[j0 >> 1];
       gr[v] = gg[jrv];
       fr[v] = f[jrv];
-      hr[v] = a.hinv[jrv];
+      hr[v] = a.hinv[j0 >> 1];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        pn[v][k] = p[jrv + of.o[k]];
+        pn[v][k] = p[(jrv + of.o[k]) >> 1];  // a black neighbour: its pair's entry
         zn[v][k] = zp[jrv + of.o[k]];
         fn[v][k] = f[jrv + of.o[k]];
       }
