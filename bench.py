@@ -117,6 +117,26 @@ def measured_traffic(kclass, args):
     return None
 
 
+def copy_rate_gbs(torch, mbytes=1024, reps=10):
+    """Read + write rate of a plain device copy of mbytes MB (torch's copy kernel): the
+    practical streaming ceiling of the HBM, measured beside the published peak."""
+    n = mbytes * 1048576 // 4
+    a = torch.ones(n, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del a, b
+    return 2 * mbytes * 1048576 / (ms * 1e-3) / 1e9
+
+
 def time_solve(plan, fmap, y, s, m, out, steps, torch):
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -565,6 +585,9 @@ def main():
     if not args.no_order2 and args.shape == "128,128,64" and args.mask == "full":
         order2 = bench_order2(args, fmap, synth, torch, prec)
 
+    copy_gbs = copy_rate_gbs(torch)
+    log("device copy of 1 GB: %.0f GB/s (read + write)" % copy_gbs)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -601,6 +624,7 @@ def main():
             "grid": list(shape), "coils": 8, "echoes": L, "niter": niter, "nmls": vol.nmls,
             "precision": args.precision, "ordering": args.ordering, "precond": args.precond,
         },
+        "hbm_copy_gbs": copy_gbs,
         "roofline": {
             "bound": "hbm",
             "kernel": dom,
