@@ -1,0 +1,85 @@
+"""Host-side parts of bench.py: the byte models its roofline uses and the refusal of
+more than one GPU (no GPU needed).
+
+The algorithmic bytes per voxel-iteration are pinned against the sweep counts of
+the method (forward sweep, backward sweep, direction, further line-search
+passes), written out here term by term for MIX and F64, and against the three
+values the roofline is quoted with (L = 3 MIX: 168 B, L = 3 F64: 320 B,
+L = 6 MIX: 240 B).
+"""
+import importlib.util
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("L", [2, 3, 4, 6])
+@pytest.mark.parametrize("nmls", [1, 2, 3, 5])
+def test_alg_bytes_by_sweep(bench, L, nmls):
+    # MIX: echo data 8L (complex64), f/z/g/D/x 4 B, pivots 8 B
+    fwd = 8 * L + 4 + 4 + (4 + 4 + 4 + 8 + 4)          # in: echoes, f, z_prev; out: f, g, D, pivot, x
+    bwd = 4 + 8 + 4 + 4 + 4 + 4                          # in: x, pivot, g, g_prev, z_prev; out: p
+    dirn = 4 + 4 + 4 + 4 + 4                             # in: p, z_prev, f, D; out: z
+    mls = 8 * L + 4 + 4                                  # in: echoes, f, z
+    assert bench.alg_bytes_per_voxel("mix", L, nmls) == fwd + bwd + dirn + (nmls - 1) * mls
+    # F64: every per-voxel value 8 B, echoes 16L
+    fwd = 16 * L + 8 + 8 + (8 + 8 + 8 + 8 + 8)
+    bwd = 6 * 8
+    dirn = 5 * 8
+    mls = 16 * L + 16
+    assert bench.alg_bytes_per_voxel("f64", L, nmls) == fwd + bwd + dirn + (nmls - 1) * mls
+
+
+def test_alg_bytes_quoted_values(bench):
+    assert bench.alg_bytes_per_voxel("mix", 3, 3) == 168
+    assert bench.alg_bytes_per_voxel("f64", 3, 3) == 320
+    assert bench.alg_bytes_per_voxel("mix", 6, 3) == 240
+
+
+def test_pass_model_of_the_red_black_iteration(bench):
+    # gradient 49 (code, echoes, f, z_prev / f, g, D, 1/h of red voxels), black 17, red + direction 23,
+    # two line-search passes 33 each
+    assert bench.bytes_per_voxel("grad", "mix", 3, "redblack", "ic0") == 49
+    assert bench.bytes_per_voxel("precond_a", "mix", 3, "redblack", "ic0") == 17
+    assert bench.bytes_per_voxel("precond_b", "mix", 3, "redblack", "ic0") == 23
+    assert bench.bytes_per_voxel("mls", "mix", 3, "redblack", "ic0") == 33
+    assert bench.iteration_bytes_per_voxel("mix", 3, "redblack", "ic0", 3) == 155
+    # the direction pass is separate for the other preconditioners
+    assert bench.iteration_bytes_per_voxel("mix", 3, "natural", "diag", 3) == \
+        45 + bench.bytes_per_voxel("precond_a", "mix", 3, "natural", "diag") + 21 + 2 * 33
+
+
+def test_second_order_model(bench):
+    for prec in ("mix", "f64"):
+        vals = {k: bench.order2_bytes_per_voxel(k, prec, 3) for k in ("grad", "precond_a", "precond_b", "dir", "mls")}
+        assert all(v > 0 for v in vals.values())
+    # MIX, t = 4: forward passes (22 + 20) / 2, backward (10.33 + 9) / 2
+    assert abs(bench.order2_bytes_per_voxel("precond_a", "mix", 3) - 21.0) < 1e-9
+    assert abs(bench.order2_bytes_per_voxel("precond_b", "mix", 3) - (31 / 3 + 9) / 2) < 1e-9
+
+
+def test_kernel_symbols(bench):
+    assert bench.kernel_symbol("precond_a", "redblack", "ic0", 64) == "k_rb_black_pair"
+    assert bench.kernel_symbol("precond_b", "redblack", "ic0", 63) == "k_rb_red_dir"
+    assert bench.kernel_symbol("precond_a", "natural", "ic0", 64) == "k_ic_fwd_wave"
+    assert bench.kernel_symbol("grad", "redblack", "ic0", 64) == "k_grad"
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "single" in r.stderr
+    assert r.stdout.strip() == ""
