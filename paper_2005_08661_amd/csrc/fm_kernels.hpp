@@ -76,15 +76,40 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
       cnt[0] += 1.0;
     }
     a.code[j] = (uint8_t)c;
-    // sum of squares of the coil maps
-    double ss = 0.0;
-    if (a.sens) {
-      for (int cc = 0; cc < a.ncoil; ++cc) {
-        const float2 s = a.sens[(int64_t)cc * g.n + j];
-        ss += (double)s.x * s.x + (double)s.y * s.y;
+    // coil sums, a chunk of CU coils at a time with all of the chunk's loads
+    // issued together (the coil map of a coil is loaded once for all echoes);
+    // each sum still runs over the coils in order
+    constexpr int CU = LMAX <= 4 ? 8 : (LMAX <= 8 ? 4 : 2);
+    double ss = a.sens ? 0.0 : 1.0;
+    double sre[LMAX], sim[LMAX];
+#pragma unroll
+    for (int l = 0; l < LMAX; ++l) sre[l] = sim[l] = 0.0;
+    for (int c0 = 0; c0 < a.ncoil; c0 += CU) {
+      float2 sv[CU], yv[CU][LMAX];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const int cc = c0 + u < a.ncoil ? c0 + u : c0;
+        sv[u] = a.sens ? a.sens[(int64_t)cc * g.n + j] : make_float2(1.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) yv[u][l] = a.y[((int64_t)cc * a.L + (l < a.L ? l : 0)) * g.n + j];
       }
-    } else {
-      ss = 1.0;
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        if (c0 + u >= a.ncoil) break;
+        const float2 sc = sv[u];
+        if (a.sens) ss += (double)sc.x * sc.x + (double)sc.y * sc.y;
+#pragma unroll
+        for (int l = 0; l < LMAX; ++l) {
+          const float2 yl = yv[u][l];
+          if (a.sens) {
+            sre[l] += (double)sc.x * yl.x + (double)sc.y * yl.y;
+            sim[l] += (double)sc.x * yl.y - (double)sc.y * yl.x;
+          } else {
+            sre[l] += yl.x;
+            sim[l] += yl.y;
+          }
+        }
+      }
     }
     const double scale = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
     double z1r = 0, z1i = 0, z2r = 0, z2i = 0;
@@ -93,20 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
     for (int l = 0; l < LMAX; ++l) {
       mag[l] = ph[l] = 0.0;
       if (l >= a.L) continue;
-      double re = 0.0, im = 0.0;
-      for (int cc = 0; cc < a.ncoil; ++cc) {
-        const float2 yv = a.y[((int64_t)cc * a.L + l) * g.n + j];
-        if (a.sens) {
-          const float2 s = a.sens[(int64_t)cc * g.n + j];
-          re += (double)s.x * yv.x + (double)s.y * yv.y;
-          im += (double)s.x * yv.y - (double)s.y * yv.x;
-        } else {
-          re += yv.x;
-          im += yv.y;
-        }
-      }
-      re *= scale;
-      im *= scale;
+      const double re = sre[l] * scale, im = sim[l] * scale;
       if (l == 0) { z1r = re; z1i = im; }
       if (l == 1) { z2r = re; z2i = im; }
       mag[l] = sqrt(re * re + im * im);
