@@ -659,7 +659,7 @@ bool plan_resident(fm_plan *p) {
     }
   if (best_cost < 0) return false;
   p->res_grid = (int)best_nt;
-  p->res_auto = p->n >= 1024L * ncu;
+  p->res_auto = p->n >= 512L * ncu;
   return true;
 }
 

@@ -159,7 +159,7 @@ def test_schedule_selection_and_fallback():
     big = fmap.make_params((320, 320, 160), 1, TE3, 0.1, niter=1, precision=fmap.MIX, ordering=fmap.REDBLACK)
     with fmap.Plan(big) as plan:
         assert plan.schedule() == fmap.SCHED_STREAM
-    for shape in [(128, 128, 64), (128, 128, 32), (96, 96, 64)]:
+    for shape in [(128, 128, 64), (128, 128, 32), (96, 96, 64), (64, 64, 32)]:
         big_enough = fmap.make_params(shape, 8, TE3, 0.1, niter=1, precision=fmap.MIX, ordering=fmap.REDBLACK)
         with fmap.Plan(big_enough) as plan:
             assert plan.schedule() == fmap.SCHED_RESIDENT, shape
