@@ -31,7 +31,9 @@
  *      (lexicographic, z fastest), red-black or three-colour order (the
  *      last for the second-order C, whose stencil two colours do not split).
  *   R6 mu = (g - g_prev)^T p / (g_prev^T p_prev), mu = 0 at i = 0 or when the
- *      denominator is 0.
+ *      denominator is 0.  Pinned only in the quadratic limit (exact line
+ *      search: the linear-CG coefficient); beyond it the conjugacy formula is
+ *      parity unpinned.
  *   R7 z = -p + mu z_prev, reset to -p when z^T g >= 0.
  *   R8 the step size restarts from 0 at every outer iteration.
  *   R9 a fixed number nmls of line-search steps.
