@@ -85,3 +85,42 @@ def test_size_and_batch_validation_before_any_device_work():
     assert batch_status([a, wf]) == 1
     assert L.fm_batch_create(C.c_int32(0), None, C.byref(h)) == 1
     assert L.fm_batch_destroy(None) == 0
+
+
+def header_enums():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    vals = {}
+    for body in re.findall(r"enum\s*(?:\w+\s*)?\{([^}]*)\}", text):
+        for name, val in re.findall(r"\b(FM_[A-Z0-9_]+)\s*=\s*(-?\d+)", body):
+            vals[name] = int(val)
+    return vals
+
+
+def test_binding_constants_match_the_header():
+    e = header_enums()
+    pairs = {"FM_ORDER_NATURAL": fmap.NATURAL, "FM_ORDER_REDBLACK": fmap.REDBLACK, "FM_ORDER_COLOR3": fmap.COLOR3,
+             "FM_PREC_F64": fmap.F64, "FM_PREC_MIX": fmap.MIX, "FM_FIELDMAP": fmap.FIELDMAP,
+             "FM_WATERFAT": fmap.WATERFAT, "FM_SCHED_AUTO": fmap.SCHED_AUTO, "FM_SCHED_STREAM": fmap.SCHED_STREAM,
+             "FM_SCHED_RESIDENT": fmap.SCHED_RESIDENT}
+    for name, val in pairs.items():
+        assert e[name] == val, name
+
+
+def test_three_colour_order_validation_on_the_host():
+    """IC(0) of the second-order C needs the three-colour order, which is built for nothing else;
+    both are refused before any device work."""
+    if not os.path.exists(fmap.LIBPATH):
+        pytest.skip("libfmap.so not built")
+    L = fmap.lib()
+    h = C.c_void_p()
+    te = [0, 1e-3, 2e-3]
+    refused = [
+        fmap.make_params((8, 8, 8), 1, te, 0.1, ordering=fmap.NATURAL, precond=fmap.IC0, reg_order=2),
+        fmap.make_params((8, 8, 8), 1, te, 0.1, ordering=fmap.REDBLACK, precond=fmap.IC0, reg_order=2),
+        fmap.make_params((8, 8, 8), 1, te, 0.1, ordering=fmap.COLOR3, precond=fmap.IC0, reg_order=1),
+        fmap.make_params((8, 8, 8), 1, te, 0.1, ordering=fmap.COLOR3, precond=fmap.DIAG, reg_order=2),
+        fmap.make_params((8, 8, 8), 1, te, 0.1, ordering=3, precond=fmap.IC0, reg_order=2),
+    ]
+    for p in refused:
+        assert L.fm_plan_create(C.byref(p), C.byref(h)) == 1 and not h.value
+        assert len(L.fm_last_error()) > 0
