@@ -2,13 +2,15 @@
 //
 // One cooperative launch runs many iterations.  Each workgroup owns a tile of
 // tx x ty whole columns (at most kResNT * kResV voxels) and keeps every
-// per-voxel quantity of its voxels in registers for the whole launch: the echo
-// data, f, z, g, g_prev, D, 1/h and p.  Per iteration the passes are those of
-// the streaming schedule (gradient, black, red + direction, line-search
-// steps), each followed by a grid barrier at which every workgroup sums all
-// workgroups' partial sums in the same fixed order and applies them to its own
-// copy of the scalar state (same consume() as the streaming kernels, so the
-// scalars, the trace and the status are those of the streaming chain).
+// per-voxel quantity of its voxels on chip for the whole launch: the echo data
+// in registers; f, z, g, g_prev, D, 1/h and p in LDS.  Per iteration the
+// passes are those of the streaming schedule (gradient, black, red +
+// direction, line-search steps).  The gradient pass ends with a wait on the
+// four face-neighbour tiles only; each later pass ends with a grid barrier at
+// which every workgroup sums all workgroups' partial sums in the same fixed
+// order and applies them to its own copy of the scalar state (same consume()
+// as the streaming kernels, so the scalars, the trace and the status are those
+// of the streaming chain).
 //
 // Neighbour values inside a tile come from LDS; across tile faces they come
 // from the plan's global arrays, which every workgroup publishes with

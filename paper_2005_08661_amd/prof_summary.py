@@ -6,7 +6,8 @@
 
 The counter summary scales FETCH_SIZE / WRITE_SIZE (KiB per dispatch) by what
 the same counters read for a plain device copy of known size, and records a
-hash of the HIP sources so that stale counters can be recognised.
+hash of the HIP sources' code (comments ignored) so that stale counters can be
+recognised.
 """
 import csv
 import glob
@@ -18,13 +19,40 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def _code_only(text):
+    """C++ source without comments and blank or trailing whitespace (string and
+    character literals kept as they are), so that the hash changes with the code
+    the compiler sees and not with its commentary."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        else:
+            out.append(c)
+            i += 1
+    lines = (ln.rstrip() for ln in "".join(out).split("\n"))
+    return "\n".join(ln for ln in lines if ln)
+
+
 def source_hash():
+    """Hash of the HIP sources' code (comments and blank lines ignored)."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")) + glob.glob(os.path.join(HERE, "csrc", "*.hpp")) +
                     glob.glob(os.path.join(HERE, "csrc", "*.inc"))):
-        with open(p, "rb") as fh:
+        with open(p, encoding="utf-8") as fh:
             h.update(os.path.basename(p).encode())
-            h.update(fh.read())
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -83,3 +83,12 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "single" in r.stderr
     assert r.stdout.strip() == ""
+
+
+def test_source_hash_ignores_comments_only():
+    from paper_2005_08661_amd.prof_summary import _code_only
+    a = 'int a = 1; // one\n/* block\n comment */ const char *s = "x // not a comment /* nor this */";\n\n'
+    b = 'int a = 1;\n const char *s = "x // not a comment /* nor this */";'
+    assert _code_only(a) == _code_only(b)
+    assert _code_only("char q = '\"'; int b; // tail") == "char q = '\"'; int b;"
+    assert _code_only("int a = 1;") != _code_only("int a = 2;")
