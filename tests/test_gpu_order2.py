@@ -48,6 +48,24 @@ VOLS = {"ragged_paper_mask": lambda: vol2(), "random_mask": lambda: vol2((20, 17
 PREC = {"f64": fmap.F64, "mix": fmap.MIX}
 
 
+def unit_volume(shape, seed, beta=1e-4, niter=15):
+    """Unit-magnitude echoes of a smooth random field, full mask, second-order C.  With f in Hz the
+    data curvature per voxel is about (2 pi dt)^2 ~ 1e-4 per echo pair, so beta = 1e-4 keeps H far
+    from the affine null space of C^T C (with beta much larger a colour-ordered IC(0) of a line
+    breaks down; see the breakdown test)."""
+    rng = np.random.default_rng(seed)
+    te = [0.0, 1.5e-3, 4.0e-3]
+    f_true = synth.smooth_field(rng, shape, 2, 40.0) + 20.0
+    y_img = np.stack([np.exp(2j * np.pi * f_true * t) for t in te])[None] * (1 + 0.05 * rng.normal(size=(1, 3) + shape))
+    return synth.Volume(y=y_img.astype(np.complex64), sens=None, te=np.array(te), mask=np.ones(shape, np.uint8),
+                        f_true=f_true, beta=beta, niter=niter, reg_order=2)
+
+
+# degenerate shapes for the three-colour factorisation: one z-line, one plane, a slab two voxels thick
+EDGE = {"line_z": lambda: unit_volume((1, 1, 17), 5), "plane_xy": lambda: unit_volume((9, 7, 1), 6),
+        "slab_nz2": lambda: unit_volume((6, 5, 2), 7)}
+
+
 @pytest.mark.parametrize("prec", ["f64", "mix"])
 @pytest.mark.parametrize("vname", list(VOLS))
 def test_stencil_matches_oracle(vname, prec):
@@ -105,6 +123,46 @@ def test_ic0_three_colour_matches_oracle(vname, prec):
     assert np.all(piv[~msk] == 0) and np.all(p[~msk] == 0)
     tol = 1e-11 if prec == "f64" else 2e-6
     assert np.abs(p - p_ref).max() <= tol * np.abs(p_ref).max()
+
+
+@pytest.mark.parametrize("vname", list(EDGE))
+def test_ic0_three_colour_degenerate_shapes(vname):
+    vol = EDGE[vname]()
+    say("order-2 IC(0) three-colour, %s %s" % (vname, vol.shape))
+    rng = np.random.default_rng(15)
+    curv = rng.uniform(0.01, 0.1, vol.shape) * vol.mask
+    g = rng.normal(size=vol.shape) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=fmap.COLOR3, precond=fmap.IC0)) as plan:
+        plan.setup(y, s, m)
+        piv, p = (t.cpu().numpy() for t in plan.precondition(torch.from_numpy(curv).cuda(), torch.from_numpy(g).cuda()))
+    p_ref, piv_ref = O.ic_general(O.problem_for(vol, ordering=O.COLOR3, precond=O.IC0), vol.mask, curv, g)
+    msk = vol.mask.astype(bool)
+    np.testing.assert_allclose(piv[msk], piv_ref[msk], rtol=1e-12)
+    assert np.abs(p - p_ref).max() <= 1e-11 * max(np.abs(p_ref).max(), 1e-300)
+    f, tr = fmap.solve_volume(vol, precision=fmap.F64, ordering=fmap.COLOR3, precond=fmap.IC0)
+    ref = O.run_volume(vol, O.COLOR3, O.IC0)
+    assert rms(f - ref["f"], msk) < 1e-3
+    np.testing.assert_allclose(tr[:, 0], ref["trace"][:, O.TR["cost"]], rtol=1e-9)
+
+
+def test_ic0_three_colour_breakdown_reported_like_the_oracle():
+    """IC(0) of the second-order H can lose positivity: C^T C is not an M-matrix and is singular on
+    affine fields, so with little data curvature against beta a colour-ordered incomplete factor
+    breaks down (natural order is exact on a line and does not).  The GPU reports
+    FM_ERR_NOT_PD where the oracle does."""
+    vol = synth.fieldmap_volume((1, 1, 17), 2, [0.0, 1.5e-3, 4.0e-3], 0.002, 15, synth.SEED_BASE + 985, 3, 120.0,
+                                False, 25.0, mask="full", name="low-signal line")
+    vol.reg_order = 2
+    with pytest.raises(O.OracleError):
+        O.run_volume(vol, O.COLOR3, O.IC0)
+    O.run_volume(vol, O.NATURAL, O.IC0)  # the exact factor of a line: no breakdown
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=fmap.COLOR3, precond=fmap.IC0)) as plan:
+        plan.solve(y, s, m)
+        with pytest.raises(fmap.FmapError) as ei:
+            plan.status()
+        assert ei.value.status == 5
 
 
 def test_ic0_three_colour_has_fill_terms():
