@@ -70,6 +70,11 @@ struct fm_plan {
   void *D = nullptr, *X = nullptr, *P = nullptr;
   void *X2 = nullptr;          // three-colour IC(0): y' = L^{-1} g_prev of colour 1
   uint8_t *rdiag = nullptr;    // three-colour IC(0): diag(C^T C) of the second-order operator
+  // three-colour IC(0): G, D, P, ipiv, X, X2, rdiag and a copy of the codes (ccode) are kept
+  // colour-major, cm_elems elements each (three colour blocks with two padding x-planes)
+  bool cm = false;
+  uint8_t *ccode = nullptr;
+  int64_t cm_elems = 0;
   double *ipiv = nullptr;
   double *hinv = nullptr;
   fm::State *S = nullptr;      // two ping-pong state copies
@@ -240,6 +245,8 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.X2 = (T *)p->X2;
   a.P = (T *)p->P;
   a.rdiag = p->rdiag;
+  a.ccode = p->ccode;
+  a.cm = p->cm ? 1 : 0;
   a.ipiv = p->ipiv;
   a.hinv = p->hinv;
   // the pair-mapped passes (even column length) keep 1/h of red and p of black voxels at the pair's index
@@ -706,8 +713,8 @@ fm_status enqueue_start(fm_plan *p, const double *f0, hipStream_t s) {
   set_parts(p, 0, 0);
   const uint64_t q = p->q++;
   hipLaunchKernelGGL(fm::k_start<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, f0, (const uint8_t *)p->code,
-                     (T *)p->F[1], (T *)p->Z[1], (T *)p->G[1], p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls,
-                     (const double *)p->nmask);
+                     (T *)p->F[1], (T *)p->Z[1], (T *)p->G[1], p->cm ? p->cm_elems : p->n, p->S + ((q + 1) & 1),
+                     p->prm.niter, p->prm.nmls, (const double *)p->nmask);
   FM_LAUNCH_CHECK();
   return FM_OK;
 }
@@ -948,7 +955,12 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   p->reg2 = prm->reg_order == 2;
   // one x-plane of guard entries on each side (two for the second-order stencil's +-2 neighbours)
   p->pad = (((p->reg2 ? 2 : 1) * p->geo.sx + 63) / 64) * 64;
-  if (p->n + 2 * p->pad >= ((int64_t)1 << 31)) {
+  p->cm = p->reg2 && prm->precond == FM_PRECOND_IC0;
+  if (p->cm) {
+    const int64_t m = ((int64_t)prm->nz + 2) / 3;
+    p->cm_elems = 3 * ((int64_t)prm->nx + 4) * prm->ny * m;
+  }
+  if (p->n + 2 * p->pad >= ((int64_t)1 << 31) || p->cm_elems >= ((int64_t)1 << 31)) {
     delete p;
     return fail(FM_ERR_SHAPE, "volume too large for 32-bit voxel indices");
   }
@@ -980,15 +992,23 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
   for (int i = 0; i < 2; ++i) {
     FM_ALLOC_PAD(p->F[i], ts);
     FM_ALLOC_PAD(p->Z[i], ts);
-    FM_ALLOC_PAD(p->G[i], ts);
   }
-  FM_ALLOC_PAD(p->D, ts);
-  FM_ALLOC_PAD(p->X, ts);
-  FM_ALLOC_PAD(p->P, ts);
-  FM_ALLOC_PAD(p->ipiv, sizeof(double));
-  if (p->reg2 && prm->precond == FM_PRECOND_IC0) {
-    FM_ALLOC_PAD(p->X2, ts);
-    FM_ALLOC_PAD(p->rdiag, 1);
+  if (p->cm) {
+    const size_t e = (size_t)p->cm_elems;
+    for (int i = 0; i < 2; ++i) FM_ALLOC(p->G[i], ts * e);
+    FM_ALLOC(p->D, ts * e);
+    FM_ALLOC(p->X, ts * e);
+    FM_ALLOC(p->X2, ts * e);
+    FM_ALLOC(p->P, ts * e);
+    FM_ALLOC(p->ipiv, sizeof(double) * e);
+    FM_ALLOC(p->rdiag, e);
+    FM_ALLOC(p->ccode, e);
+  } else {
+    for (int i = 0; i < 2; ++i) FM_ALLOC_PAD(p->G[i], ts);
+    FM_ALLOC_PAD(p->D, ts);
+    FM_ALLOC_PAD(p->X, ts);
+    FM_ALLOC_PAD(p->P, ts);
+    FM_ALLOC_PAD(p->ipiv, sizeof(double));
   }
   FM_ALLOC_PAD(p->hinv, sizeof(double));
   FM_ALLOC(p->S, sizeof(fm::State) * 2);
@@ -1112,8 +1132,11 @@ fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *m
     FM_LAUNCH_CHECK();
     hipLaunchKernelGGL(fm::k_count, dim3(1), dim3(kBlock), 0, s, (const double *)p->setup_part, p->grid, p->nmask);
     FM_LAUNCH_CHECK();
-    if (p->rdiag) {
-      hipLaunchKernelGGL(fm::k_rdiag2, dim3(p->grid), dim3(kBlock), 0, s, p->geo, (const uint8_t *)p->code, p->rdiag);
+    if (p->cm) {
+      const int64_t blocks = (p->cm_elems + kBlock - 1) / kBlock;
+      const dim3 grid((unsigned)(blocks < kMaxGrid ? blocks : kMaxGrid));
+      hipLaunchKernelGGL(fm::k_colour_major2, grid, dim3(kBlock), 0, s, p->geo, (const uint8_t *)p->code, p->ccode,
+                         p->rdiag);
       FM_LAUNCH_CHECK();
     }
     return FM_OK;
@@ -1151,10 +1174,17 @@ fm_status fm_precondition(fm_plan *p, const double *curv, const double *g, doubl
   if (!p->setup_done) return fail(FM_ERR_STATE, "fm_precondition needs fm_setup first");
   auto run = [&](auto tag) -> fm_status {
     using T = decltype(tag);
-    hipLaunchKernelGGL(fm::k_to_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, curv, (T *)p->D);
-    FM_LAUNCH_CHECK();
-    hipLaunchKernelGGL(fm::k_to_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, g, (T *)p->G[0]);
-    FM_LAUNCH_CHECK();
+    if (p->cm) {
+      hipLaunchKernelGGL(fm::k_to_cm<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, curv, (T *)p->D);
+      FM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(fm::k_to_cm<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, g, (T *)p->G[0]);
+      FM_LAUNCH_CHECK();
+    } else {
+      hipLaunchKernelGGL(fm::k_to_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, curv, (T *)p->D);
+      FM_LAUNCH_CHECK();
+      hipLaunchKernelGGL(fm::k_to_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, g, (T *)p->G[0]);
+      FM_LAUNCH_CHECK();
+    }
     FM_HIP(hipMemsetAsync(p->status, 0, sizeof(int32_t), s));
     const uint64_t q = p->q++;
     hipLaunchKernelGGL(fm::k_state_init, dim3(1), dim3(1), 0, s, p->S + ((q + 1) & 1), p->prm.niter, p->prm.nmls);
@@ -1168,11 +1198,20 @@ fm_status fm_precondition(fm_plan *p, const double *curv, const double *g, doubl
     }
     fm_status st = enqueue_precond<T>(p, (const T *)p->G[0], s);
     if (st) return st;
-    hipLaunchKernelGGL(fm::k_from_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const T *)p->P, pout);
-    FM_LAUNCH_CHECK();
-    if (piv) {
-      hipLaunchKernelGGL(fm::k_pivots, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const double *)p->ipiv, piv);
+    if (p->cm) {
+      hipLaunchKernelGGL(fm::k_from_cm<T>, dim3(p->grid), dim3(kBlock), 0, s, p->geo, (const T *)p->P, pout);
       FM_LAUNCH_CHECK();
+      if (piv) {
+        hipLaunchKernelGGL(fm::k_pivots_cm, dim3(p->grid), dim3(kBlock), 0, s, p->geo, (const double *)p->ipiv, piv);
+        FM_LAUNCH_CHECK();
+      }
+    } else {
+      hipLaunchKernelGGL(fm::k_from_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const T *)p->P, pout);
+      FM_LAUNCH_CHECK();
+      if (piv) {
+        hipLaunchKernelGGL(fm::k_pivots, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const double *)p->ipiv, piv);
+        FM_LAUNCH_CHECK();
+      }
     }
     int32_t status = 0;
     fm_status rs = read_status(p, s, &status);

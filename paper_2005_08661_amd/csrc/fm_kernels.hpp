@@ -226,13 +226,15 @@ __device__ __forceinline__ void init_state(State *sout, int trace_cap, int nmls,
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_start(Geo g, const double *__restrict__ f0,
                                                    const uint8_t *__restrict__ code, T *Fprev,
-                                                   T *Zprev, T *Gprev, State *sout, int trace_cap, int nmls,
-                                                   const double *nmask) {
+                                                   T *Zprev, T *Gprev, int64_t gcount, State *sout, int trace_cap,
+                                                   int nmls, const double *nmask) {
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
     Fprev[j] = (code[j] & NB_SELF) ? (T)f0[j] : T(0);
     Zprev[j] = T(0);
-    Gprev[j] = T(0);
   }
+  // gcount elements of the gradient (more than n in the colour-major layout)
+  for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < gcount; j += (int64_t)gridDim.x * kBlock)
+    Gprev[j] = T(0);
   init_state(sout, trace_cap, nmls, nmask);
 }
 
@@ -277,7 +279,9 @@ struct IterArgs {
   T *X;
   T *X2;         // second forward-solve vector (three-colour IC(0))
   T *P;
-  const uint8_t *rdiag;  // diag(C^T C) of the second-order operator (three-colour IC(0))
+  const uint8_t *rdiag;  // diag(C^T C) of the second-order operator (three-colour IC(0), colour-major)
+  const uint8_t *ccode;  // neighbour codes in the colour-major layout (three-colour IC(0))
+  int32_t cm;            // G, D, P, ipiv, X, X2 are colour-major (three-colour IC(0) plans)
   double *ipiv;  // 1 / pivot
   double *hinv;  // 1 / (D + beta deg), written by the gradient pass when needed
   int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0)): 1 for every voxel at j;

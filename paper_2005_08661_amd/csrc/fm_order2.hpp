@@ -53,6 +53,80 @@ __device__ __forceinline__ T ctc2(const Rows2 &R, T fj, const T (&v1)[6], const 
   return s;
 }
 
+// Colour-major layout of the arrays the three-colour passes share (g, g_prev,
+// D, p, the inverted pivots, y, y', the neighbour codes and diag(C^T C)):
+// block c holds the voxels of colour c, voxel (x, y, z) at slot
+// (x + 2) plane + y m + z / 3 of it, with m = ceil(nz / 3) slots per z-column,
+// plane = ny m, and two padding planes on either side of x.  Along x and y the
+// +-1 and +-2 neighbours of a colour-c voxel sit at the same within-column slot
+// of a neighbouring column in block c +- 1 (the +1 and -2 neighbours in block
+// c + 1, the -1 and +2 ones in block c - 1); along z the slot moves by at most
+// one, by an amount fixed by z mod 3.  A pass over one colour therefore reads
+// and writes that colour's block contiguously and the two others at a few
+// constant strides, and touches no cache line of the other colours' values.
+// Quotient and remainder of 0 <= j < 2^31 by d > 0 through a float64
+// reciprocal: the rounded product is within 2^-21 of j / d, so its truncation
+// is off by at most one, which one correction step on the remainder removes.
+struct Div {
+  int d;
+  double inv;
+  __device__ __forceinline__ explicit Div(int d_) : d(d_), inv(1.0 / (double)d_) {}
+  __device__ __forceinline__ int operator()(int j, int &r) const {
+    int q = (int)((double)j * inv);
+    r = j - q * d;
+    if (r < 0) {
+      --q;
+      r += d;
+    }
+    if (r >= d) {
+      ++q;
+      r -= d;
+    }
+    return q;
+  }
+};
+
+struct Cm {
+  int m, plane, S;  // slots per column, slots per x-plane, elements per colour block
+  Div dz, dy;       // division by nz and ny
+  __device__ __forceinline__ explicit Cm(const Geo &g)
+      : m((g.nz + 2) / 3), plane(g.ny * ((g.nz + 2) / 3)), S((g.nx + 4) * g.ny * ((g.nz + 2) / 3)), dz(g.nz),
+        dy(g.ny) {}
+  // element of slot t (0 <= t < nx plane) of colour c
+  __device__ __forceinline__ int at(int c, int t) const { return c * S + 2 * plane + t; }
+  // coordinates of voxel j
+  __device__ __forceinline__ void xyz(int j, int &x, int &y, int &z) const {
+    const int yx = dz(j, z);
+    x = dy(yx, y);
+  }
+  // element of voxel j
+  __device__ __forceinline__ int of(int j) const {
+    int x, y, z;
+    xyz(j, x, y, z);
+    return ((x + y + z) % 3) * S + (x + 2) * plane + y * m + z / 3;
+  }
+};
+
+// Elements of voxel j and of its six axis neighbours (in the order -x, +x,
+// -y, +y, -z, +z) in the colour-major layout.
+struct CmVox {
+  int own, nb[6];
+  __device__ __forceinline__ CmVox(const Cm &q, int j) {
+    int x, y, z;
+    q.xyz(j, x, y, z);
+    const int c = (x + y + z) % 3, z0 = z % 3;
+    const int s = (x + 2) * q.plane + y * q.m + z / 3;
+    const int up = (c == 2 ? 0 : c + 1) * q.S + s, dn = (c == 0 ? 2 : c - 1) * q.S + s;
+    own = c * q.S + s;
+    nb[0] = dn - q.plane;
+    nb[1] = up + q.plane;
+    nb[2] = dn - q.m;
+    nb[3] = up + q.m;
+    nb[4] = dn - (z0 == 0 ? 1 : 0);
+    nb[5] = up + (z0 == 2 ? 1 : 0);
+  }
+};
+
 // Gradient pass with the second-order regulariser (as k_grad): also loads the
 // +-2 neighbours of f and z and the neighbour codes.
 template <typename T, int LMAX>
@@ -66,6 +140,8 @@ __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
   T *__restrict__ fo = a.Fc;
   T *__restrict__ gg = a.Gc;
   const Offs of(g);
+  const Cm q(g);
+  const bool cm = a0.cm != 0;
   const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V], cn[V][6];
   T f0[V], z0[V], fn[V][6], zn[V][6], fn2[V][6], zn2[V][6], rho[V][LMAX], tau[V][LMAX];
@@ -100,12 +176,14 @@ __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
       const int j = base + v * kNT + (int)threadIdx.x;
       if (j >= n) continue;
       const uint32_t cv = c[v];
+      // g and D of three-colour IC(0) plans in the colour-major layout
+      const int jw = cm ? q.of(j) : j;
       if (!(cv & NB_SELF)) {
         fo[j] = T(0);
         if (a.fout) a.fout[j] = 0.0;
         if (!a.final_pass) {
-          gg[j] = T(0);
-          a.D[j] = T(0);
+          gg[jw] = T(0);
+          a.D[jw] = T(0);
         }
         continue;
       }
@@ -124,8 +202,8 @@ __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
       fo[j] = fj;
       if (a.fout) a.fout[j] = (double)fj;
       if (!a.final_pass) {
-        gg[j] = gj;
-        a.D[j] = curv;
+        gg[jw] = gj;
+        a.D[jw] = curv;
       }
       acc[0] += (double)phi;
       acc[1] += (double)fj * (double)lap;
@@ -222,6 +300,8 @@ __global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
   const T *__restrict__ f = a.Fc;
   const T *__restrict__ p = a.P;
   const Offs of(g);
+  const Cm q(g);
+  const bool cm = a0.cm != 0;
   const int n = (int)g.n, chunk = kNT * V, stride = vw.nb * chunk;
   uint32_t c[V];
   T p0[V], z0[V], f0[V], d0[V], pn[V][6], zn[V][6], fn[V][6];
@@ -231,15 +311,24 @@ __global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
       const int j = b + v * kNT + (int)threadIdx.x;
       const int jj = j < n ? j : n - 1;
       c[v] = j < n ? a.code[jj] : 0u;
-      p0[v] = p[jj];
       z0[v] = zp[jj];
       f0[v] = f[jj];
-      d0[v] = a.D[jj];
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        pn[v][k] = p[jj + of.o[k]];
         zn[v][k] = zp[jj + of.o[k]];
         fn[v][k] = f[jj + of.o[k]];
+      }
+      if (cm) {  // p and D of three-colour IC(0) plans in the colour-major layout
+        const CmVox w(q, jj);
+        p0[v] = p[w.own];
+        d0[v] = a.D[w.own];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pn[v][k] = p[w.nb[k]];
+      } else {
+        p0[v] = p[jj];
+        d0[v] = a.D[jj];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) pn[v][k] = p[jj + of.o[k]];
       }
     }
   };
@@ -296,18 +385,34 @@ __global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
 // Off-diagonal entries along axis a (rows r at the centre voxel):
 //   H(j,j+-e) = beta (-2 r_j - 2 r_{j+-e}),  H(j,j+-2e) = beta r_{j+-e}.
 
-__device__ __forceinline__ int colour3(const Geo &g, int j) {
-  const int z = j % g.nz, yx = j / g.nz, y = yx % g.ny, x = yx / g.ny;
-  return (x + y + z) % 3;
-}
+// Elements of the +-1, +-2 axis neighbours of the colour-c voxel at slot t
+// (z mod 3 = z0): m1 = j - e, p1 = j + e, m2 = j - 2e, p2 = j + 2e per axis.
+struct Nb2 {
+  int m1[3], p1[3], m2[3], p2[3];
+  __device__ __forceinline__ Nb2(const Cm &q, int c, int t, int z0) {
+    const int up = q.at(c == 2 ? 0 : c + 1, t), dn = q.at(c == 0 ? 2 : c - 1, t);
+    const int s[2] = {q.plane, q.m};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      m1[a] = dn - s[a];
+      p1[a] = up + s[a];
+      m2[a] = up - 2 * s[a];
+      p2[a] = dn + 2 * s[a];
+    }
+    m1[2] = dn - (z0 == 0 ? 1 : 0);
+    p1[2] = up + (z0 == 2 ? 1 : 0);
+    m2[2] = up - (z0 <= 1 ? 1 : 0);
+    p2[2] = dn + (z0 >= 1 ? 1 : 0);
+  }
+};
 
 // In-mask flags and row indicators on the axis line through voxel j (in the
 // mask, code c), from the codes at j-+e (cm1, cp1) and j-+2e (cm2, cp2), all
-// loaded unconditionally (the arrays are padded by two x-planes; a code read
-// past the volume's edge is never trusted: j-2e counts only through an in-mask
-// j-e, whose own code then says whether j-2e is in the mask, and a +-2
-// neighbour behind a hole couples to j through nothing), and the entries of H
-// among them.
+// loaded unconditionally (the blocks carry two padding planes and the codes of
+// padding and unused slots are 0; a code read past the volume's edge is never
+// trusted: j-2e counts only through an in-mask j-e, whose own code then says
+// whether j-2e is in the mask, and a +-2 neighbour behind a hole couples to j
+// through nothing), and the entries of H among them.
 struct Line2 {
   bool m1, p1, m2, p2;   // j-e, j+e, j-2e, j+2e in the mask
   double hm1, hp1;       // H(j,j-e), H(j,j+e)
@@ -336,42 +441,86 @@ struct Line2 {
 // The codes at j-+e and j-+2e of the three axes, issued together.
 struct Codes2 {
   uint32_t m1[3], p1[3], m2[3], p2[3];
-  __device__ __forceinline__ Codes2(const uint8_t *__restrict__ code, int j, const Offs &of) {
+  __device__ __forceinline__ Codes2(const uint8_t *__restrict__ code, const Nb2 &nb) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int o = of.o[2 * a + 1];
-      m1[a] = code[j - o];
-      p1[a] = code[j + o];
-      m2[a] = code[j - 2 * o];
-      p2[a] = code[j + 2 * o];
+      m1[a] = code[nb.m1[a]];
+      p1[a] = code[nb.p1[a]];
+      m2[a] = code[nb.m2[a]];
+      p2[a] = code[nb.p2[a]];
     }
   }
 };
 
-// Visit the voxels of colour c of the volume (a third of each z-column: every
-// third z from the column's first voxel of that colour), workgroup-strided,
-// so that the lanes of a pass that concerns one colour all work.
+// Visit the slots of colour c that hold a voxel (every slot of the block's
+// interior but the last of a column whose colour-c voxels number m - 1),
+// workgroup-strided: f(t, z mod 3).
 template <typename F>
-__device__ __forceinline__ void for_colour(const Geo &g, int c, int first, int step, F &&f) {
-  const int m = (g.nz + 2) / 3;  // slots per column
-  const int total = g.nx * g.ny * m;
+__device__ __forceinline__ void for_colour(const Geo &g, const Cm &q, int c, int first, int step, F &&f) {
+  const int total = g.nx * q.plane;
+  const Div dm(q.m);
   for (int t = first; t < total; t += step) {
-    const int col = t / m, k = t - col * m;
-    const int x = col / g.ny, y = col - x * g.ny;
-    const int z = (c + 3 - (x + y) % 3) % 3 + 3 * k;
-    if (z < g.nz) f(col * g.nz + z);
+    int k, y;
+    const int col = dm(t, k);
+    const int x = q.dy(col, y);
+    const int z0 = (c + 3 - (x + y) % 3) % 3;
+    if (z0 + 3 * k < g.nz) f(t, z0);
   }
 }
 
-// diag(C^T C) per voxel (0 outside the mask), once per setup.
-__global__ __launch_bounds__(kBlock) void k_rdiag2(Geo g, const uint8_t *__restrict__ code, uint8_t *rdiag) {
+// Colour-major codes and diag(C^T C) (0 outside the mask, in the padding planes
+// and in unused slots), once per setup; every element of both arrays is written.
+__global__ __launch_bounds__(kBlock) void k_colour_major2(Geo g, const uint8_t *__restrict__ code, uint8_t *ccode,
+                                                          uint8_t *rdiag) {
+  const Cm q(g);
   const Offs of(g);
-  for (int j = (int)blockIdx.x * kBlock + (int)threadIdx.x; j < (int)g.n; j += (int)gridDim.x * kBlock) {
-    const uint32_t c = code[j];
-    uint32_t cn[6];
+  const int total = 3 * q.S;
+  for (int e = (int)blockIdx.x * kBlock + (int)threadIdx.x; e < total; e += (int)gridDim.x * kBlock) {
+    const int c = e / q.S, r = e - c * q.S;
+    const int xp = r / q.plane, w = r - xp * q.plane;
+    const int x = xp - 2, y = w / q.m, k = w - y * q.m;
+    uint32_t cv = 0u;
+    int j = 0;
+    if (x >= 0 && x < g.nx) {
+      const int z = (c + 3 - (x + y) % 3) % 3 + 3 * k;
+      if (z < g.nz) {
+        j = x * (int)g.sx + y * g.nz + z;
+        cv = code[j];
+      }
+    }
+    uint8_t d = 0;
+    if (cv & NB_SELF) {
+      uint32_t cn[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) cn[k] = has_nb(c, k) ? code[j + of.o[k]] : 0u;
-    rdiag[j] = (c & NB_SELF) ? (uint8_t)Rows2(c, cn).diag() : (uint8_t)0;
+      for (int s = 0; s < 6; ++s) cn[s] = has_nb(cv, s) ? code[j + of.o[s]] : 0u;
+      d = (uint8_t)Rows2(cv, cn).diag();
+    }
+    ccode[e] = (uint8_t)cv;
+    rdiag[e] = d;
+  }
+}
+
+// Conversions between voxel order (user float64 arrays) and the colour-major
+// working arrays.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_to_cm(Geo g, const double *__restrict__ src, T *dst) {
+  const Cm q(g);
+  for (int j = (int)blockIdx.x * kBlock + (int)threadIdx.x; j < (int)g.n; j += (int)gridDim.x * kBlock)
+    dst[q.of(j)] = (T)src[j];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_from_cm(Geo g, const T *__restrict__ src, double *dst) {
+  const Cm q(g);
+  for (int j = (int)blockIdx.x * kBlock + (int)threadIdx.x; j < (int)g.n; j += (int)gridDim.x * kBlock)
+    dst[j] = (double)src[q.of(j)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pivots_cm(Geo g, const double *__restrict__ ipiv, double *piv) {
+  const Cm q(g);
+  for (int j = (int)blockIdx.x * kBlock + (int)threadIdx.x; j < (int)g.n; j += (int)gridDim.x * kBlock) {
+    const double ip = ipiv[q.of(j)];
+    piv[j] = ip > 0.0 ? 1.0 / ip : 0.0;
   }
 }
 
@@ -382,17 +531,20 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd1(IterArgs<T> a0, const T *__res
   const VolView vw = vol_view<false>(a0);
   const VArgs<T> a = at_volume<false>(a0, vw);
   const Geo g = a.geo;
+  const Cm q(g);
   const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
   const T *__restrict__ gp = a.Gp;
-  const Offs of(g);
+  const uint8_t *__restrict__ cc = a0.ccode;
+  const uint8_t *__restrict__ rd = a0.rdiag;
   const State st = take_state<kNT, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
   const int first = vw.bl * kNT + (int)threadIdx.x, step = vw.nb * kNT;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
-  for_colour(g, 0, first, step, [&](int j) {
-    const uint32_t c = a.code[j];
-    const double d = (double)a.D[j] + beta * (double)a0.rdiag[j], y = (double)gg[j], y2 = (double)gp[j];
+  for_colour(g, q, 0, first, step, [&](int t, int) {
+    const int j = q.at(0, t);
+    const uint32_t c = cc[j];
+    const double d = (double)a.D[j] + beta * (double)rd[j], y = (double)gg[j], y2 = (double)gp[j];
     double ip = 1.0 / d;
     if (!(c & NB_SELF)) {
       ip = 0.0;
@@ -405,17 +557,18 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd1(IterArgs<T> a0, const T *__res
     acc[1] += y2 * y * ip;
   });
   // colour 1: earlier neighbours j-e and j+2e (colour 0, pivots D + beta diag(C^T C))
-  for_colour(g, 1, first, step, [&](int j) {
-    const uint32_t c = a.code[j];
-    const Codes2 cs(a.code, j, of);
+  for_colour(g, q, 1, first, step, [&](int t, int z0) {
+    const int j = q.at(1, t);
+    const uint32_t c = cc[j];
+    const Nb2 nb(q, 1, t, z0);
+    const Codes2 cs(cc, nb);
     double dk[6], hk[6], gk[6], gpk[6];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int o = of.o[2 * ax + 1];
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
-        const int k = u ? j + 2 * o : j - o;
-        dk[2 * ax + u] = (double)a.D[k] + beta * (double)a0.rdiag[k];
+        const int k = u ? nb.p2[ax] : nb.m1[ax];
+        dk[2 * ax + u] = (double)a.D[k] + beta * (double)rd[k];
         gk[2 * ax + u] = (double)gg[k];
         gpk[2 * ax + u] = (double)gp[k];
       }
@@ -423,14 +576,14 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd1(IterArgs<T> a0, const T *__res
       hk[2 * ax] = l.m1 ? l.hm1 : 0.0;
       hk[2 * ax + 1] = l.p2 ? l.hp2 : 0.0;
     }
-    double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
+    double d = (double)a.D[j] + beta * (double)rd[j];
     double y = (double)gg[j], y2 = (double)gp[j];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const double lk = hk[q] != 0.0 ? hk[q] / dk[q] : 0.0;
-      d -= hk[q] * lk;
-      y -= hk[q] != 0.0 ? lk * gk[q] : 0.0;
-      y2 -= hk[q] != 0.0 ? lk * gpk[q] : 0.0;
+    for (int k = 0; k < 6; ++k) {
+      const double lk = hk[k] != 0.0 ? hk[k] / dk[k] : 0.0;
+      d -= hk[k] * lk;
+      y -= hk[k] != 0.0 ? lk * gk[k] : 0.0;
+      y2 -= hk[k] != 0.0 ? lk * gpk[k] : 0.0;
     }
     double ip = 1.0 / d;
     if (!(c & NB_SELF)) {
@@ -459,33 +612,35 @@ __global__ __launch_bounds__(kNT) void k_ic3_fwd2(IterArgs<T> a0, const T *__res
   const VolView vw = vol_view<false>(a0);
   const VArgs<T> a = at_volume<false>(a0, vw);
   const Geo g = a.geo;
+  const Cm q(g);
   const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
   const T *__restrict__ gp = a.Gp;
-  const Offs of(g);
+  const uint8_t *__restrict__ cc = a0.ccode;
   const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
   double acc[2] = {0.0, 0.0};
   int bad = 0;
-  for_colour(g, 2, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int j) {
-    const uint32_t c = a.code[j];
-    const Codes2 cs(a.code, j, of);
+  for_colour(g, q, 2, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int t, int z0) {
+    const int j = q.at(2, t);
+    const uint32_t c = cc[j];
+    const Nb2 nb(q, 2, t, z0);
+    const Codes2 cs(cc, nb);
     // per axis: 1/D at j-e, j+e, j-2e, j+2e; g, g_prev at j+e, j-2e (colour 0); y, y' at j-e, j+2e (colour 1)
     double ip4[3][4], g2[3][2], gp2[3][2], x2[3][2], xp2[3][2];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int o = of.o[2 * ax + 1];
-      ip4[ax][0] = a.ipiv[j - o];
-      ip4[ax][1] = a.ipiv[j + o];
-      ip4[ax][2] = a.ipiv[j - 2 * o];
-      ip4[ax][3] = a.ipiv[j + 2 * o];
-      g2[ax][0] = (double)gg[j + o];
-      g2[ax][1] = (double)gg[j - 2 * o];
-      gp2[ax][0] = (double)gp[j + o];
-      gp2[ax][1] = (double)gp[j - 2 * o];
-      x2[ax][0] = (double)a0.X[j - o];
-      x2[ax][1] = (double)a0.X[j + 2 * o];
-      xp2[ax][0] = (double)a0.X2[j - o];
-      xp2[ax][1] = (double)a0.X2[j + 2 * o];
+      ip4[ax][0] = a.ipiv[nb.m1[ax]];
+      ip4[ax][1] = a.ipiv[nb.p1[ax]];
+      ip4[ax][2] = a.ipiv[nb.m2[ax]];
+      ip4[ax][3] = a.ipiv[nb.p2[ax]];
+      g2[ax][0] = (double)gg[nb.p1[ax]];
+      g2[ax][1] = (double)gg[nb.m2[ax]];
+      gp2[ax][0] = (double)gp[nb.p1[ax]];
+      gp2[ax][1] = (double)gp[nb.m2[ax]];
+      x2[ax][0] = (double)a0.X[nb.m1[ax]];
+      x2[ax][1] = (double)a0.X[nb.p2[ax]];
+      xp2[ax][0] = (double)a0.X2[nb.m1[ax]];
+      xp2[ax][1] = (double)a0.X2[nb.p2[ax]];
     }
     double d = (double)a.D[j] + beta * (double)a0.rdiag[j];
     double y = (double)gg[j], y2 = (double)gp[j];
@@ -531,20 +686,22 @@ __global__ __launch_bounds__(kNT) void k_ic3_bwd1(IterArgs<T> a0) {
   const VolView vw = vol_view<false>(a0);
   const VArgs<T> a = at_volume<false>(a0, vw);
   const Geo g = a.geo;
-  const Offs of(g);
+  const Cm q(g);
+  const uint8_t *__restrict__ cc = a0.ccode;
   const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
-  for_colour(g, 1, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int j) {
-    const uint32_t c = a.code[j];
-    const Codes2 cs(a.code, j, of);
+  for_colour(g, q, 1, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int t, int z0) {
+    const int j = q.at(1, t);
+    const uint32_t c = cc[j];
+    const Nb2 nb(q, 1, t, z0);
+    const Codes2 cs(cc, nb);
     double ipm1[3], ipp2[3], pp1[3], pm2[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int o = of.o[2 * ax + 1];
-      ipm1[ax] = a.ipiv[j - o];
-      ipp2[ax] = a.ipiv[j + 2 * o];
-      pp1[ax] = (double)a.P[j + o];
-      pm2[ax] = (double)a.P[j - 2 * o];
+      ipm1[ax] = a.ipiv[nb.m1[ax]];
+      ipp2[ax] = a.ipiv[nb.p2[ax]];
+      pp1[ax] = (double)a.P[nb.p1[ax]];
+      pm2[ax] = (double)a.P[nb.m2[ax]];
     }
     const double ip = a.ipiv[j], yj = (double)a0.X[j];
     double s = 0.0;
@@ -570,21 +727,23 @@ __global__ __launch_bounds__(kNT) void k_ic3_bwd0(IterArgs<T> a0, const T *__res
   const VolView vw = vol_view<false>(a0);
   const VArgs<T> a = at_volume<false>(a0, vw);
   const Geo g = a.geo;
+  const Cm q(g);
   const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
-  const Offs of(g);
+  const uint8_t *__restrict__ cc = a0.ccode;
   const State st = take_state<kNT, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow, vw.leader);
   const double beta = a.beta;
-  for_colour(g, 0, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int j) {
-    const uint32_t c = a.code[j];
-    const Codes2 cs(a.code, j, of);
+  for_colour(g, q, 0, vw.bl * kNT + (int)threadIdx.x, vw.nb * kNT, [&](int t, int z0) {
+    const int j = q.at(0, t);
+    const uint32_t c = cc[j];
+    const Nb2 nb(q, 0, t, z0);
+    const Codes2 cs(cc, nb);
     double pn[3][4];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
-      const int o = of.o[2 * ax + 1];
-      pn[ax][0] = (double)a.P[j - o];
-      pn[ax][1] = (double)a.P[j + o];
-      pn[ax][2] = (double)a.P[j - 2 * o];
-      pn[ax][3] = (double)a.P[j + 2 * o];
+      pn[ax][0] = (double)a.P[nb.m1[ax]];
+      pn[ax][1] = (double)a.P[nb.p1[ax]];
+      pn[ax][2] = (double)a.P[nb.m2[ax]];
+      pn[ax][3] = (double)a.P[nb.p2[ax]];
     }
     double s = (double)gg[j];
 #pragma unroll
