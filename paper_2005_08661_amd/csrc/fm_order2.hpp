@@ -8,9 +8,10 @@
 //                         + r_{j+e} (f_j - 2 f_{j+e} + f_{j+2e})
 //                         + r_{j-e} (f_{j-2e} - 2 f_{j-e} + f_j) ],
 //   (C^T C)_jj  = sum_a [ 4 r_j + r_{j-e} + r_{j+e} ],
-// with r the row indicators.  Passes for the diagonal and identity
-// preconditioners (single volumes); arrays are padded by two x-planes so that
-// the +-2 neighbour addresses stay in bounds.
+// with r the row indicators.  Passes for single volumes with the diagonal,
+// identity or IC(0) (three-colour order) preconditioner; voxel-order arrays
+// are padded by two x-planes so that the +-2 neighbour addresses stay in
+// bounds, and the arrays of three-colour IC(0) are colour-major (below).
 #pragma once
 
 #include "fm_stream.hpp"
@@ -53,17 +54,6 @@ __device__ __forceinline__ T ctc2(const Rows2 &R, T fj, const T (&v1)[6], const 
   return s;
 }
 
-// Colour-major layout of the arrays the three-colour passes share (g, g_prev,
-// D, p, the inverted pivots, y, y', the neighbour codes and diag(C^T C)):
-// block c holds the voxels of colour c, voxel (x, y, z) at slot
-// (x + 2) plane + y m + z / 3 of it, with m = ceil(nz / 3) slots per z-column,
-// plane = ny m, and two padding planes on either side of x.  Along x and y the
-// +-1 and +-2 neighbours of a colour-c voxel sit at the same within-column slot
-// of a neighbouring column in block c +- 1 (the +1 and -2 neighbours in block
-// c + 1, the -1 and +2 ones in block c - 1); along z the slot moves by at most
-// one, by an amount fixed by z mod 3.  A pass over one colour therefore reads
-// and writes that colour's block contiguously and the two others at a few
-// constant strides, and touches no cache line of the other colours' values.
 // Quotient and remainder of 0 <= j < 2^31 by d > 0 through a float64
 // reciprocal: the rounded product is within 2^-21 of j / d, so its truncation
 // is off by at most one, which one correction step on the remainder removes.
@@ -86,6 +76,17 @@ struct Div {
   }
 };
 
+// Colour-major layout of the arrays the three-colour passes share (g, g_prev,
+// D, p, the inverted pivots, y, y', the neighbour codes and diag(C^T C)):
+// block c holds the voxels of colour c, voxel (x, y, z) at slot
+// (x + 2) plane + y m + z / 3 of it, with m = ceil(nz / 3) slots per z-column,
+// plane = ny m, and two padding planes on either side of x.  Along x and y the
+// +-1 and +-2 neighbours of a colour-c voxel sit at the same within-column slot
+// of a neighbouring column in block c +- 1 (the +1 and -2 neighbours in block
+// c + 1, the -1 and +2 ones in block c - 1); along z the slot moves by at most
+// one, by an amount fixed by z mod 3.  A pass over one colour therefore reads
+// and writes that colour's block contiguously and the two others at a few
+// constant strides, and touches no cache line of the other colours' values.
 struct Cm {
   int m, plane, S;  // slots per column, slots per x-plane, elements per colour block
   Div dz, dy;       // division by nz and ny
@@ -128,7 +129,8 @@ struct CmVox {
 };
 
 // Gradient pass with the second-order regulariser (as k_grad): also loads the
-// +-2 neighbours of f and z and the neighbour codes.
+// +-2 neighbours of f and z and the neighbour codes; g and D go to their
+// colour-major elements in three-colour IC(0) plans.
 template <typename T, int LMAX>
 __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
   constexpr int V = Vpt<T>::v;
@@ -289,6 +291,7 @@ __global__ __launch_bounds__(kNT) void k_diag2(IterArgs<T> a0, const T *__restri
 // Direction and line-search setup with the second-order regulariser (as
 // k_dir): z = -p + mu z_prev, and over the rows of C (each row taken at its
 // centre voxel) A = sum (Cz)(Cf) = z^T C^T C f and B = sum (Cz)^2; d0 = sum z^2 D.
+// p and D are read from their colour-major elements in three-colour IC(0) plans.
 template <typename T>
 __global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
   constexpr int V = Vpt<T>::v;
