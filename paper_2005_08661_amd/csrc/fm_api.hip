@@ -75,6 +75,7 @@ struct fm_plan {
   bool cm = false;
   uint8_t *ccode = nullptr;
   int64_t cm_elems = 0;
+  void *Pv = nullptr, *Dv = nullptr;  // voxel-order copies of p and D for the direction pass
   double *ipiv = nullptr;
   double *hinv = nullptr;
   fm::State *S = nullptr;      // two ping-pong state copies
@@ -247,6 +248,8 @@ fm::IterArgs<T> iter_args(fm_plan *p, uint64_t q) {
   a.rdiag = p->rdiag;
   a.ccode = p->ccode;
   a.cm = p->cm ? 1 : 0;
+  a.Pv = (T *)p->Pv;
+  a.Dv = (T *)p->Dv;
   a.ipiv = p->ipiv;
   a.hinv = p->hinv;
   // the pair-mapped passes (even column length) keep 1/h of red and p of black voxels at the pair's index
@@ -402,7 +405,12 @@ fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) 
   } else {
     fm_status st = enqueue_precond<T>(p, nullptr, s, rec);
     if (st) return st;
-    if (p->reg2) {
+    if (p->cm) {  // the direction pass reads the voxel-order copies of p and D
+      fm::IterArgs<T> a = iter_args<T>(p, p->q++);
+      a.P = (T *)p->Pv;
+      a.D = (T *)p->Dv;
+      FM_LAUNCH(FM_K_DIR, (fm::k_dir2<T>), dim3(p->sgrid), dim3(fm::kNT), s, a);
+    } else if (p->reg2) {
       FM_LAUNCH(FM_K_DIR, (fm::k_dir2<T>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
     } else {
       FM_LAUNCH(FM_K_DIR, (fm::k_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
@@ -1003,6 +1011,8 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
     FM_ALLOC(p->ipiv, sizeof(double) * e);
     FM_ALLOC(p->rdiag, e);
     FM_ALLOC(p->ccode, e);
+    FM_ALLOC_PAD(p->Pv, ts);
+    FM_ALLOC_PAD(p->Dv, ts);
   } else {
     for (int i = 0; i < 2; ++i) FM_ALLOC_PAD(p->G[i], ts);
     FM_ALLOC_PAD(p->D, ts);

@@ -282,6 +282,7 @@ struct IterArgs {
   const uint8_t *rdiag;  // diag(C^T C) of the second-order operator (three-colour IC(0), colour-major)
   const uint8_t *ccode;  // neighbour codes in the colour-major layout (three-colour IC(0))
   int32_t cm;            // G, D, P, ipiv, X, X2 are colour-major (three-colour IC(0) plans)
+  T *Pv, *Dv;            // voxel-order copies of p and D (three-colour IC(0) plans)
   double *ipiv;  // 1 / pivot
   double *hinv;  // 1 / (D + beta deg), written by the gradient pass when needed
   int32_t write_hinv;  // gradient pass also writes hinv (red-black IC(0)): 1 for every voxel at j;
