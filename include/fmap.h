@@ -113,7 +113,8 @@ typedef struct {
 typedef struct fm_plan fm_plan;
 
 /* Validate the parameters and allocate the plan's device workspace on the
- * current device (about 70 B per voxel in MIX, 140 B in F64, plus the
+ * current device (about 70 B per voxel in MIX, 140 B in F64, some 20 B (MIX)
+ * to 40 B (F64) more for IC(0) with second-order differences, plus the
  * reduction buffers).  *plan is set to NULL on failure. */
 fm_status fm_plan_create(const fm_params *prm, fm_plan **plan);
 
