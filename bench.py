@@ -406,8 +406,9 @@ def main():
     ap.add_argument("--precond", choices=["ic0", "diag", "none"], default="ic0")
     ap.add_argument("--mask", choices=["full", "paper"], default="full")
     ap.add_argument("--shape", default="128,128,64")
-    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2"], default="fieldmap",
-                    help="fieldmap: the headline line (default); batched / waterfat / order2: only that workload")
+    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2", "large"], default="fieldmap",
+                    help="fieldmap: the headline line (default); batched / waterfat / order2 / large: only that "
+                         "workload")
     ap.add_argument("--kernel-iters", type=int, default=10)
     ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -444,6 +445,11 @@ def main():
             value, ms = res["ic0_color3"]["value"], res["ic0_color3"]["ms_per_solve"]
             wl = "field map 128x128x64, 8 coils, 3 echoes, second-order finite differences, 100 NCG iterations, " \
                  "IC(0) in three-colour order, %s" % args.precision.upper()
+        elif args.workload == "large":
+            res = bench_large(args, fmap, synth, torch, prec)
+            value, ms = res["loop_voxel_iterations_per_s"], res["ms_per_solve"]
+            wl = "field map 256x256x128 (%d unknowns), 2 coils, 3 echoes, 100 NCG iterations, red-black IC(0), " \
+                 "%s schedule, %s" % (res["voxels"], res["schedule"], args.precision.upper())
         else:
             res = bench_waterfat(args, fmap, synth, torch)
             value, ms = res["loop_voxel_iterations_per_s"], res["ms_per_solve"]
