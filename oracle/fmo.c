@@ -52,7 +52,34 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+/* Loops whose iterations are independent (one voxel each, no shared sum) may
+ * run on several threads; every sum over voxels stays a sequential loop in
+ * natural order, so a build with OpenMP returns bit for bit what a build
+ * without it returns. */
+#define FMO_PARALLEL_FOR _Pragma("omp parallel for schedule(static)")
+#else
+#define FMO_PARALLEL_FOR
+#endif
+
 #define TWO_PI 6.283185307179586476925286766559
+
+int fmo_set_threads(int32_t nthreads) {
+  if (nthreads < 1) return FMO_ERR_ARG;
+#ifdef _OPENMP
+  omp_set_num_threads(nthreads);
+#endif
+  return FMO_OK;
+}
+
+int32_t fmo_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 typedef struct {
   int32_t np;     /* number of echo pairs m < n */
@@ -152,6 +179,7 @@ static int pairs_build(const fmo_problem *pb, const double *zhat, const uint8_t 
     for (int k = m + 1; k < L; ++k, ++q) {
       const double gre = pb->gam[2 * (m * L + k)], gim = pb->gam[2 * (m * L + k) + 1];
       pr->d[q] = TWO_PI * (pb->te[m] - pb->te[k]);
+      FMO_PARALLEL_FOR
       for (int64_t j = 0; j < n; ++j) {
         if (!mask[j]) continue;
         double cre, cim;
@@ -254,6 +282,7 @@ int fmo_gamma_waterfat(int32_t L, const double *te, int32_t npeak, const double 
 int fmo_combine(int64_t n, int32_t ncoil, int32_t L, const double *y, const double *s,
                 double *zhat) {
   if (n < 0 || ncoil < 1 || L < 1 || !y || !zhat || (!s && ncoil != 1)) return FMO_ERR_ARG;
+  FMO_PARALLEL_FOR
   for (int64_t j = 0; j < n; ++j) {
     double ss = 0.0;
     for (int c = 0; c < ncoil; ++c) {
@@ -282,6 +311,7 @@ int fmo_init_fieldmap(int64_t n, int32_t L, const double *zhat, const double *te
                       const uint8_t *mask, double *f0) {
   if (L < 2 || !zhat || !te || !mask || !f0) return FMO_ERR_ARG;
   if (te[1] == te[0]) return FMO_ERR_ARG;
+  FMO_PARALLEL_FOR
   for (int64_t j = 0; j < n; ++j) {
     if (!mask[j]) {
       f0[j] = 0.0;
@@ -308,6 +338,7 @@ int fmo_data_term(const fmo_problem *pb, const double *zhat, const uint8_t *mask
   const int64_t n = nvox(pb);
   pairs_t pr;
   if (pairs_build(pb, zhat, mask, &pr)) return FMO_ERR_ARG;
+  FMO_PARALLEL_FOR
   for (int64_t j = 0; j < n; ++j) {
     double a = 0, b = 0, c = 0;
     if (mask[j]) voxel_terms(&pr, n, j, f[j], &a, &b, &c);
@@ -336,8 +367,9 @@ int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, d
         }
     return FMO_OK;
   }
-  int64_t nb[6];
+  FMO_PARALLEL_FOR
   for (int64_t j = 0; j < n; ++j) {
+    int64_t nb[6];
     double s = 0.0;
     if (mask[j]) {
       const int c = neighbours(pb, mask, j, nb);
@@ -348,31 +380,92 @@ int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, d
   return FMO_OK;
 }
 
+/* End of the run of colour `colour` that starts at position q0 of the
+ * elimination order. */
+static int64_t colour_end(const fmo_problem *pb, const int64_t *order, int64_t q0, int64_t cnt, int colour) {
+  const int64_t n = nvox(pb);
+  int64_t q = q0;
+  while (q < cnt && rank_of(pb, order[q]) / n == colour) ++q;
+  return q;
+}
+
+/* Pivot of voxel j from the pivots of its earlier neighbours. */
+static double pivot_of(const fmo_problem *pb, const uint8_t *mask, const double *curv, const double *piv,
+                       int64_t j) {
+  const double b = pb->beta;
+  int64_t nb[6];
+  const int c = neighbours(pb, mask, j, nb);
+  const int64_t rj = rank_of(pb, j);
+  double s = 0.0;
+  for (int k = 0; k < c; ++k)
+    if (rank_of(pb, nb[k]) < rj) s += 1.0 / piv[nb[k]];
+  return curv[j] + b * c - b * b * s;
+}
+
 int fmo_factor(const fmo_problem *pb, const uint8_t *mask, const double *curv, double *piv) {
   if (check_pb(pb) || !mask || !curv || !piv) return FMO_ERR_ARG;
   const int64_t n = nvox(pb);
   int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
   if (!order) return FMO_ERR_ARG;
   const int64_t cnt = build_order(pb, mask, order);
-  const double b = pb->beta;
-  int64_t nb[6];
   int st = FMO_OK;
   for (int64_t j = 0; j < n; ++j) piv[j] = 0.0;
-  for (int64_t q = 0; q < cnt; ++q) {
-    const int64_t j = order[q];
-    const int c = neighbours(pb, mask, j, nb);
-    const int64_t rj = rank_of(pb, j);
-    double s = 0.0;
-    for (int k = 0; k < c; ++k)
-      if (rank_of(pb, nb[k]) < rj) s += 1.0 / piv[nb[k]];
-    piv[j] = curv[j] + b * c - b * b * s;
-    if (!(piv[j] > 0.0)) {
-      st = isfinite(piv[j]) ? FMO_ERR_NOT_PD : FMO_ERR_NONFINITE;
-      break;
+  if (ncolours(pb) == 1) {
+    for (int64_t q = 0; q < cnt; ++q) {
+      const int64_t j = order[q];
+      piv[j] = pivot_of(pb, mask, curv, piv, j);
+      if (!(piv[j] > 0.0)) {
+        st = isfinite(piv[j]) ? FMO_ERR_NOT_PD : FMO_ERR_NONFINITE;
+        break;
+      }
+    }
+  } else {
+    /* Each colour is an independent set of the 7-point stencil (axis
+     * neighbours differ by one in x+y+z), so no pivot of a colour uses
+     * another of the same colour: a colour's pivots are formed in any order,
+     * then checked in elimination order as the sequential sweep would (the
+     * first non-positive pivot stops the factorisation; later ones stay 0). */
+    int64_t q0 = 0;
+    for (int colour = 0; colour < ncolours(pb) && st == FMO_OK; ++colour) {
+      const int64_t q1 = colour_end(pb, order, q0, cnt, colour);
+      FMO_PARALLEL_FOR
+      for (int64_t q = q0; q < q1; ++q) piv[order[q]] = pivot_of(pb, mask, curv, piv, order[q]);
+      for (int64_t q = q0; q < q1; ++q) {
+        const double v = piv[order[q]];
+        if (st != FMO_OK)
+          piv[order[q]] = 0.0;
+        else if (!(v > 0.0))
+          st = isfinite(v) ? FMO_ERR_NOT_PD : FMO_ERR_NONFINITE;
+      }
+      q0 = q1;
     }
   }
   free(order);
   return st;
+}
+
+/* Forward solve (P + E) x = g at voxel j: x_j = (g_j + beta sum_{k before j} x_k) / P_j. */
+static double forward_of(const fmo_problem *pb, const uint8_t *mask, const double *piv, const double *g,
+                         const double *x, int64_t j) {
+  int64_t nb[6];
+  const int c = neighbours(pb, mask, j, nb);
+  const int64_t rj = rank_of(pb, j);
+  double s = g[j];
+  for (int k = 0; k < c; ++k)
+    if (rank_of(pb, nb[k]) < rj) s += pb->beta * x[nb[k]];
+  return s / piv[j];
+}
+
+/* Backward solve (P + E^T) p = P x at voxel j: p_j = x_j + beta sum_{k after j} p_k / P_j. */
+static double backward_of(const fmo_problem *pb, const uint8_t *mask, const double *piv, const double *x,
+                          const double *p, int64_t j) {
+  int64_t nb[6];
+  const int c = neighbours(pb, mask, j, nb);
+  const int64_t rj = rank_of(pb, j);
+  double s = 0.0;
+  for (int k = 0; k < c; ++k)
+    if (rank_of(pb, nb[k]) > rj) s += p[nb[k]];
+  return x[j] + pb->beta * s / piv[j];
 }
 
 int fmo_apply(const fmo_problem *pb, const uint8_t *mask, const double *piv, const double *g,
@@ -383,28 +476,32 @@ int fmo_apply(const fmo_problem *pb, const uint8_t *mask, const double *piv, con
   double *x = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
   if (!order || !x) return FMO_ERR_ARG;
   const int64_t cnt = build_order(pb, mask, order);
-  const double b = pb->beta;
-  int64_t nb[6];
+  /* runs of one colour in the elimination order (natural order: one run);
+   * within a run of several colours' order no voxel uses another of the run
+   * (independent sets of the 7-point stencil), so its voxels may be visited
+   * in any order */
+  int64_t bound[4] = {0, cnt, cnt, cnt};
+  const int nc = ncolours(pb);
+  for (int colour = 0; colour < nc && nc > 1; ++colour)
+    bound[colour + 1] = colour_end(pb, order, bound[colour], cnt, colour);
   /* forward: (P + E) x = g, E = strictly lower part of H (entries -beta) */
-  for (int64_t q = 0; q < cnt; ++q) {
-    const int64_t j = order[q];
-    const int c = neighbours(pb, mask, j, nb);
-    const int64_t rj = rank_of(pb, j);
-    double s = g[j];
-    for (int k = 0; k < c; ++k)
-      if (rank_of(pb, nb[k]) < rj) s += b * x[nb[k]];
-    x[j] = s / piv[j];
+  for (int r = 0; r < nc; ++r) {
+    if (nc == 1) {
+      for (int64_t q = 0; q < cnt; ++q) x[order[q]] = forward_of(pb, mask, piv, g, x, order[q]);
+    } else {
+      FMO_PARALLEL_FOR
+      for (int64_t q = bound[r]; q < bound[r + 1]; ++q) x[order[q]] = forward_of(pb, mask, piv, g, x, order[q]);
+    }
   }
   /* backward: (P + E^T) p = P x */
   for (int64_t j = 0; j < n; ++j) p[j] = 0.0;
-  for (int64_t q = cnt - 1; q >= 0; --q) {
-    const int64_t j = order[q];
-    const int c = neighbours(pb, mask, j, nb);
-    const int64_t rj = rank_of(pb, j);
-    double s = 0.0;
-    for (int k = 0; k < c; ++k)
-      if (rank_of(pb, nb[k]) > rj) s += p[nb[k]];
-    p[j] = x[j] + b * s / piv[j];
+  for (int r = nc - 1; r >= 0; --r) {
+    if (nc == 1) {
+      for (int64_t q = cnt - 1; q >= 0; --q) p[order[q]] = backward_of(pb, mask, piv, x, p, order[q]);
+    } else {
+      FMO_PARALLEL_FOR
+      for (int64_t q = bound[r + 1] - 1; q >= bound[r]; --q) p[order[q]] = backward_of(pb, mask, piv, x, p, order[q]);
+    }
   }
   free(order);
   free(x);
@@ -561,15 +658,18 @@ static double dot_mask(const uint8_t *mask, int64_t n, const double *a, const do
 static double cost_at(const fmo_problem *pb, const pairs_t *pr, const uint8_t *mask,
                       const double *f, const double *z, double alpha, double *tmp, double *lap) {
   const int64_t n = nvox(pb);
-  double phi_sum = 0.0;
+  FMO_PARALLEL_FOR
+  for (int64_t j = 0; j < n; ++j) tmp[j] = mask[j] ? f[j] + (z ? alpha * z[j] : 0.0) : 0.0;
+  /* per-voxel costs into lap, then their sum in natural order */
+  FMO_PARALLEL_FOR
   for (int64_t j = 0; j < n; ++j) {
-    tmp[j] = mask[j] ? f[j] + (z ? alpha * z[j] : 0.0) : 0.0;
-    if (mask[j]) {
-      double a, b, c;
-      voxel_terms(pr, n, j, tmp[j], &a, &b, &c);
-      phi_sum += a;
-    }
+    double a = 0.0, b, c;
+    if (mask[j]) voxel_terms(pr, n, j, tmp[j], &a, &b, &c);
+    lap[j] = a;
   }
+  double phi_sum = 0.0;
+  for (int64_t j = 0; j < n; ++j)
+    if (mask[j]) phi_sum += lap[j];
   fmo_laplacian(pb, mask, tmp, lap);
   return phi_sum + 0.5 * pb->beta * dot_mask(mask, n, tmp, lap);
 }
@@ -608,16 +708,20 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
   double gtp_prev = 0.0;
 
   for (int it = 0; it < pb->niter; ++it) {
-    /* gradient g = grad Phi + beta C^T C f, and the Huber curvature D */
-    double phi_sum = 0.0;
+    /* gradient g = grad Phi + beta C^T C f, and the Huber curvature D
+     * (per-voxel costs into tmp, summed in natural order below) */
+    FMO_PARALLEL_FOR
     for (int64_t j = 0; j < n; ++j) {
       double a = 0, b = 0, c = 0;
       if (mask[j]) voxel_terms(&pr, n, j, f[j], &a, &b, &c);
-      phi_sum += a;
+      tmp[j] = a;
       dphi[j] = b;
       curv[j] = c;
     }
+    double phi_sum = 0.0;
+    for (int64_t j = 0; j < n; ++j) phi_sum += tmp[j];
     fmo_laplacian(pb, mask, f, lap);
+    FMO_PARALLEL_FOR
     for (int64_t j = 0; j < n; ++j) g[j] = mask[j] ? dphi[j] + beta * lap[j] : 0.0;
     const double cost = phi_sum + 0.5 * beta * dot_mask(mask, n, f, lap);
 
@@ -658,6 +762,7 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
       ztg = -gtp;
       restart = 1;
     }
+    FMO_PARALLEL_FOR
     for (int64_t j = 0; j < n; ++j) z[j] = mask[j] ? -p[j] + mu * zprev[j] : 0.0;
 
     /* monotone line search on f(alpha) = Psi(f + alpha z) */
@@ -675,12 +780,19 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
             s2 += z[j] * z[j] * curv[j];
           }
       } else {
+        /* derivative and curvature at f + alpha z into tmp, tmp2; sums in natural order */
+        FMO_PARALLEL_FOR
         for (int64_t j = 0; j < n; ++j)
           if (mask[j]) {
             double a, b, c;
             voxel_terms(&pr, n, j, f[j] + alpha * z[j], &a, &b, &c);
-            s1 += z[j] * b;
-            s2 += z[j] * z[j] * c;
+            tmp[j] = b;
+            tmp2[j] = c;
+          }
+        for (int64_t j = 0; j < n; ++j)
+          if (mask[j]) {
+            s1 += z[j] * tmp[j];
+            s2 += z[j] * z[j] * tmp2[j];
           }
       }
       const double den = s2 + beta * B;
@@ -709,6 +821,7 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
       t[FMO_TR_B] = B;
       t[FMO_TR_GNORM2] = dot_mask(mask, n, g, g);
     }
+    FMO_PARALLEL_FOR
     for (int64_t j = 0; j < n; ++j) {
       if (mask[j]) f[j] += alpha * z[j];
       gprev[j] = g[j];

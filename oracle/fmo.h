@@ -171,6 +171,12 @@ int fmo_components(const fmo_problem *pb, int32_t ncoil, const double *y, const 
                    const uint8_t *mask, const double *f, int32_t K, int32_t npeak, const double *fat_hz,
                    const double *fat_amp, double *out);
 
+/* Threads for the loops over independent voxels when the oracle is built with
+ * OpenMP (no effect otherwise); every sum over voxels stays sequential in
+ * natural order, so the results do not depend on the thread count. */
+int fmo_set_threads(int32_t nthreads);
+int32_t fmo_threads(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -39,8 +39,27 @@ def lib():
         if not os.path.exists(_LIBPATH):
             from . import build as _b
             _b.build()
-        _lib = C.CDLL(_LIBPATH)
+        use_library(_LIBPATH)
     return _lib
+
+
+def use_library(path):
+    """Load the oracle from path (a build of fmo.c, e.g. the -march=native
+    timing copy of build.build_native) for the calls that follow."""
+    global _lib
+    L = C.CDLL(path)
+    L.fmo_threads.restype = C.c_int32
+    _lib = L
+    return L
+
+
+def set_threads(n):
+    """Threads for the oracle's loops over independent voxels (OpenMP)."""
+    _check(lib().fmo_set_threads(C.c_int32(int(n))))
+
+
+def threads():
+    return int(lib().fmo_threads())
 
 
 def _p(a):
