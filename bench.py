@@ -137,6 +137,133 @@ def copy_rate_gbs(torch, mbytes=1024, reps=10):
     return 2 * mbytes * 1048576 / (ms * 1e-3) / 1e9
 
 
+def flip_threshold(te):
+    """Half the period of the phase-wrap ambiguity of the closest echo pair, 1/(2 min |t_m - t_n|): a voxel
+    that differs by more than this between two maps sits in another local minimum (a basin flip)."""
+    te = np.asarray(te, dtype=np.float64)
+    return 1.0 / (2.0 * min(abs(te[m] - te[n]) for m in range(len(te)) for n in range(m + 1, len(te))))
+
+
+def map_diff(a, b, mask, thr):
+    d = (np.asarray(a) - np.asarray(b))[mask]
+    return {"rms_hz": float(np.sqrt(np.mean(d ** 2))), "max_abs_hz": float(np.abs(d).max()),
+            "basin_flips": int(np.count_nonzero(np.abs(d) > thr))}
+
+
+def host_threads():
+    """Threads for the all-cores oracle run: the CPUs this process may run on, capped by OMP_NUM_THREADS when
+    the environment sets it (the host's share of cores)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def bench_cpu(args, vol, synth, batched_vols, headline):
+    """The FP64 oracle on the host (a -O3 -march=native copy compiled here), on 1 thread and on all threads:
+    config 2 (the headline volume) in full on all threads, which also gives the parity of the GPU maps, and a
+    20-iteration sample on 1 thread; config 1 (32x32x16, 1 coil, 50 iterations, natural-order IC(0)) in full on
+    both; config 4 (the 16 uneven volumes) for 3 iterations per volume on both.  The oracle's parallel loops
+    are those over independent voxels; its sums stay sequential, so every thread count gives the same bits."""
+    import tempfile
+
+    import oracle as O
+    from oracle import build as obuild
+
+    tmp = tempfile.mkdtemp(prefix="fmo_native_")
+    O.use_library(obuild.build_native(tmp))
+    nall = host_threads()
+    affinity = len(os.sched_getaffinity(0))
+    log("cpu baseline: oracle -O3 -march=native, 1 and %d threads (%d CPUs in the affinity mask)" % (nall, affinity))
+    order = O.NATURAL if args.ordering == "natural" else O.REDBLACK
+    pc = {"ic0": O.IC0, "diag": O.DIAG, "none": O.NONE}[args.precond]
+
+    def run(v, nt, niter, ordering=order, precond=pc):
+        O.set_threads(nt)
+        t0 = time.perf_counter()
+        r = O.run_volume(v, ordering=ordering, precond=precond, niter=niter)
+        return r, time.perf_counter() - t0
+
+    out = {"affinity_cpus": affinity, "threads_all": nall, "build": "gcc -O3 -march=native -fopenmp "
+                                                                      "-ffp-contract=off"}
+    nmask = int(vol.mask.sum())
+    # config 2: full solve on all threads (the parity reference), 20-iteration sample on one thread
+    ref, t_all = run(vol, nall, vol.niter)
+    _, t_one = run(vol, 1, 20)
+    out["config2"] = {"all_threads": {"value": nmask * vol.niter / t_all, "seconds": t_all, "niter": vol.niter},
+                      "one_thread": {"value": nmask * 20 / t_one, "seconds": t_one, "niter": 20}}
+    log("cpu config 2: %.3e voxel-iterations/s on %d threads (100 iterations, %.1f s), %.3e on 1 thread "
+        "(20 iterations, %.1f s)" % (out["config2"]["all_threads"]["value"], nall, t_all,
+                                     out["config2"]["one_thread"]["value"], t_one))
+    # config 1
+    tiny = synth.tiny_fieldmap()
+    n1 = int(tiny.mask.sum())
+    _, t1a = run(tiny, nall, tiny.niter, O.NATURAL, O.IC0)
+    _, t11 = run(tiny, 1, tiny.niter, O.NATURAL, O.IC0)
+    out["config1"] = {"voxels": n1, "niter": tiny.niter, "all_threads": n1 * tiny.niter / t1a,
+                      "one_thread": n1 * tiny.niter / t11}
+    log("cpu config 1: %.3e (all) / %.3e (1 thread) voxel-iterations/s" % (out["config1"]["all_threads"],
+                                                                        out["config1"]["one_thread"]))
+    # config 4: every volume, 3 iterations
+    vols4 = batched_vols if batched_vols is not None else synth.batched(16)
+    n4 = sum(int(v.mask.sum()) for v in vols4)
+    rates = {}
+    for name, nt in (("all_threads", nall), ("one_thread", 1)):
+        t = 0.0
+        for v in vols4:
+            t += run(v, nt, 3, O.REDBLACK, O.IC0)[1]
+        rates[name] = n4 * 3 / t
+    out["config4"] = dict(voxels=n4, niter=3, **rates)
+    log("cpu config 4: %.3e (all) / %.3e (1 thread) voxel-iterations/s" % (rates["all_threads"],
+                                                                        rates["one_thread"]))
+    O.set_threads(nall)
+    # parity of the GPU maps against the oracle's full run (Sec. III Algorithm, same fixed iteration counts)
+    m = vol.mask.astype(bool)
+    thr = flip_threshold(vol.te)
+    rt = ref["trace"]
+    par = {"reference": "FP64 oracle, %d iterations, %s IC(0), same seeded inputs" % (vol.niter, args.ordering),
+           "flip_threshold_hz": thr}
+    for tag, (f, tr) in headline.items():
+        d = map_diff(f, ref["f"], m, thr)
+        d["restart_mismatches"] = int(np.count_nonzero(tr[:-1, 3] != rt[:-1, O.TR["restart"]]))
+        d["cost_max_rel_diff"] = float(np.max(np.abs(tr[:, 0] - rt[:, O.TR["cost"]]) / np.abs(rt[:, O.TR["cost"]])))
+        par[tag] = d
+        log("parity %s vs oracle: rms %.3e Hz, max %.3e Hz, %d basin flips, %d restart mismatches" % (
+            tag, d["rms_hz"], d["max_abs_hz"], d["basin_flips"], d["restart_mismatches"]))
+    if "mix" in headline and "f64" in headline:
+        par["mix_vs_f64"] = map_diff(headline["mix"][0], headline["f64"][0], m, thr)
+        log("parity MIX vs F64: rms %.3e Hz" % par["mix_vs_f64"]["rms_hz"])
+    cpu = {"value": out["config2"]["all_threads"]["value"], "unit": "voxel-iterations/s", "cores": nall,
+           "kind": "oracle",
+           "sample": "config 2 as the GPU step (%dx%dx%d, 8 coils, coil combination, eq. (w0) start, %d NCG "
+                     "iterations, FP64 C, %d threads, %.1f s); one thread: %.3e voxel-iterations/s on 20 "
+                     "iterations" % (vol.shape + (vol.niter, nall, t_all, out["config2"]["one_thread"]["value"])),
+           "detail": out}
+    return cpu, par
+
+
+def roofline_entry(kinfo, dom, traffic):
+    """Roofline of the dominant kernel.  The path has no dense contraction and its arithmetic intensity is below
+    the FP32 balance of the chip (157.3 TFLOP/s / 8 TB/s = 19.7 flop/B), so its roofline is the HBM one:
+    achieved = algorithmic bytes per launch / average launch duration.  `limiter` says what the counters show
+    limits the kernel: the bytes that crossed the L2 per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+    copy) over the launch duration, as a fraction of the HBM peak; when that is under half of the peak the
+    kernel is not waiting on HBM but on latency (grid synchronisation, dependent loads) or issue."""
+    k = kinfo[dom]
+    ent = {"bound": "hbm", "kernel": dom, "achieved": k["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": k["gbs"] / HBM_PEAK_GBS, "traffic": traffic}
+    if traffic:
+        meas = traffic / (k["avg_us"] * 1e-6) / 1e9
+        ent["measured_gbs"] = meas
+        ent["measured_frac"] = meas / HBM_PEAK_GBS
+        ent["limiter"] = "hbm bandwidth" if meas >= 0.5 * HBM_PEAK_GBS else \
+            "latency and synchronisation (measured traffic %.0f%% of the HBM peak)" % (100 * meas / HBM_PEAK_GBS)
+    else:
+        ent["limiter"] = None
+    return ent
+
+
 def time_solve(plan, fmap, y, s, m, out, steps, torch):
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -194,7 +321,7 @@ def bench_batched(args, fmap, synth, torch, prec):
            "shapes": [list(v.shape) for v in vols]}
     log("batched: %.3f ms per solve (%.3e voxel-iterations/s); loop of single solves %.3f ms; x%.2f; "
         "max RMS difference %.2e Hz" % (ms_b, res["value"], ms_l, res["speedup_vs_loop"], diff))
-    return res
+    return res, vols
 
 
 def bench_convergence(args, fmap, vol, y, s, m, torch, prec, ms_iter_rb):
@@ -410,7 +537,6 @@ def main():
                     help="fieldmap: the headline line (default); batched / waterfat / order2 / large: only that "
                          "workload")
     ap.add_argument("--kernel-iters", type=int, default=10)
-    ap.add_argument("--cpu-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-natural", action="store_true", help="skip the natural-order comparison line")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-volume batched comparison")
@@ -436,7 +562,7 @@ def main():
     if args.workload != "fieldmap":
         prec = fmap.MIX if args.precision == "mix" else fmap.F64
         if args.workload == "batched":
-            res = bench_batched(args, fmap, synth, torch, prec)
+            res, _ = bench_batched(args, fmap, synth, torch, prec)
             value, ms = res["value"], res["ms_per_solve"]
             wl = "16 field-map volumes of 64-160 x 64-160 x 32-96 voxels (%d unknowns), 4 coils, TE 0/2/5 ms, " \
                  "100 NCG iterations, one batched solve, red-black IC(0), %s" % (res["voxels"], args.precision.upper())
@@ -482,6 +608,7 @@ def main():
     ms_step = time_solve(plan, fmap, y, s, m, out, args.steps, torch)
     wall = time.perf_counter() - t0
     tr = plan.trace()
+    f_step = out.cpu().numpy()
     nmask = plan.mask_count()
     value = nmask * niter / (ms_step * 1e-3)
     log("step %.3f ms (wall %.3f ms), %.3e voxel-iterations/s" % (ms_step, wall * 1e3 / args.steps, value))
@@ -575,9 +702,9 @@ def main():
                    "loss": "||f - f_true||^2 over the mask", "outputs": "dL/dbeta, dL/dy (complex64, 8 coils)"}
         log("adjoint: %.3f ms, %d CG iterations" % (ms_adj, res["iters"]))
 
-    batched = None
+    batched, batched_vols = None, None
     if not args.no_batched:
-        batched = bench_batched(args, fmap, synth, torch, prec)
+        batched, batched_vols = bench_batched(args, fmap, synth, torch, prec)
 
     waterfat = None
     if not args.no_waterfat:
@@ -594,18 +721,14 @@ def main():
     copy_gbs = copy_rate_gbs(torch)
     log("device copy of 1 GB: %.0f GB/s (read + write)" % copy_gbs)
 
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu_baseline:
-        import oracle as O
-        log("cpu baseline: oracle, %d iterations" % args.cpu_iters)
-        t0 = time.perf_counter()
-        O.run_volume(vol, ordering=order, precond={"ic0": O.IC0, "diag": O.DIAG, "none": O.NONE}[args.precond],
-                     niter=args.cpu_iters)
-        tc = time.perf_counter() - t0
-        cpu = {"value": nmask * args.cpu_iters / tc, "unit": "voxel-iterations/s", "cores": 1, "kind": "oracle",
-               "sample": "%dx%dx%d 8 coils: coil combination, eq. (w0) start and %d NCG iterations (FP64, "
-                         "single-threaded C), %.1f s" % (shape + (args.cpu_iters, tc))}
-        log("cpu %.3e voxel-iterations/s" % cpu["value"])
+        headline = {args.precision: (f_step, tr)}
+        if args.precision == "mix":
+            with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=order, precond=pc)) as p64:
+                f64 = p64.solve(y, s, m).cpu().numpy()
+                headline["f64"] = (f64, p64.trace())
+        cpu, parity = bench_cpu(args, vol, synth, batched_vols, headline)
 
     line = {
         "metric": "NCG+IC voxel-iterations/s and % HBM roofline at 128×128×64×8 coils",
@@ -631,15 +754,7 @@ def main():
             "precision": args.precision, "ordering": args.ordering, "precond": args.precond,
         },
         "hbm_copy_gbs": copy_gbs,
-        "roofline": {
-            "bound": "hbm",
-            "kernel": dom,
-            "achieved": kinfo[dom]["gbs"],
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": kinfo[dom]["gbs"] / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom, args),
-        },
+        "roofline": roofline_entry(kinfo, dom, measured_traffic(dom, args)),
         "iteration": {
             "schedule": schedule,
             "loop_ms": ms_loop,
@@ -660,6 +775,7 @@ def main():
         "batched": batched,
         "waterfat": waterfat,
         "cpu_baseline": cpu,
+        "parity": parity,
     }
     plan.close()
     print(json.dumps(line), flush=True)

@@ -172,13 +172,14 @@ fm_status fm_get_trace(fm_plan *plan, double *trace, hipStream_t stream);
 
 /* Schedule of the iteration loop (Sec. III Algorithm; the arithmetic is the
  * same in both).  STREAM: one launch per pass, the loop replayed from a HIP
- * graph.  RESIDENT: one cooperative launch for all iterations of a call; each
- * workgroup keeps the per-voxel state of a tile of whole columns in
- * registers and LDS, and the passes are separated by grid barriers or waits
- * on the neighbour tiles.  RESIDENT needs MIX precision, red-black IC(0),
- * 2 <= necho <= 4, tiles of at most 2048 voxels that can all be resident on
- * the device at once (for example 128x128x64: 512 tiles of 4x8 columns), and
- * an even nz.  AUTO (the default) takes RESIDENT when the plan qualifies and
+ * graph.  RESIDENT: one launch for all iterations of a call; each workgroup
+ * keeps the per-voxel state of a tile of whole columns in registers and LDS,
+ * and the passes are separated by grid barriers or waits on the neighbour
+ * tiles, so the whole grid must be resident on the device at once (a grid
+ * kept from running by other work ends with FM_ERR_TIMEOUT).  RESIDENT
+ * needs MIX precision, red-black IC(0), 2 <= necho <= 4, tiles of at most
+ * 2048 voxels that can all be resident on the device at once (for example
+ * 128x128x64: 512 tiles of 4x8 columns), and an even nz.  AUTO (the default) takes RESIDENT when the plan qualifies and
  * has at least 512 voxels per compute unit (smaller volumes run as fast or
  * faster streamed). */
 enum { FM_SCHED_AUTO = 0, FM_SCHED_STREAM = 1, FM_SCHED_RESIDENT = 2 };

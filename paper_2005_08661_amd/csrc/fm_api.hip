@@ -116,7 +116,7 @@ struct fm_plan {
   double *a_hinv = nullptr, *a_ipiv = nullptr, *a_part = nullptr;
   fm::State *aS = nullptr;
   int32_t *a_status = nullptr;
-  // resident schedule (one cooperative launch for many iterations)
+  // resident schedule (one launch for many iterations)
   bool reg2 = false;           // second-order regulariser
   int32_t sched = FM_SCHED_AUTO;
   bool res_ok = false;         // the plan qualifies (MIX, red-black IC(0), <= 4 echoes, tiles fit)
@@ -591,7 +591,27 @@ void *resident_kernel_for(int necho) {
   return necho <= 2 ? resident_kernel<2>() : (necho == 3 ? resident_kernel<3>() : resident_kernel<4>());
 }
 
-// niter iterations in one cooperative launch of the resident schedule.
+// An ordinary launch: the plan has checked that the whole grid fits on the
+// device at once (occupancy x compute units), and every wait inside the
+// kernel is bounded, so a grid that is not fully resident (another kernel
+// holding compute units) ends with FM_ERR_TIMEOUT instead of hanging.  The
+// events, when given, are attached to the dispatch itself.
+template <int LR>
+hipError_t launch_resident(const fm::ResArgs &a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (e0 && e1)
+    hipExtLaunchKernelGGL(fm::k_resident<LR>, dim3(grid), dim3(fm::kResNT), 0, s, e0, e1, 0, a);
+  else
+    hipLaunchKernelGGL(fm::k_resident<LR>, dim3(grid), dim3(fm::kResNT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_resident_for(int necho, const fm::ResArgs &a, int grid, hipStream_t s, hipEvent_t e0,
+                               hipEvent_t e1) {
+  return necho <= 2 ? launch_resident<2>(a, grid, s, e0, e1)
+                    : (necho == 3 ? launch_resident<3>(a, grid, s, e0, e1) : launch_resident<4>(a, grid, s, e0, e1));
+}
+
+// niter iterations in one launch of the resident schedule.
 fm_status run_resident(fm_plan *p, int niter, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   fm::ResArgs a{};
   a.geo = p->geo;
@@ -620,12 +640,8 @@ fm_status run_resident(fm_plan *p, int niter, hipStream_t s, hipEvent_t e0 = nul
   a.status = p->status;
   a.trace = p->trace;
   FM_HIP(hipMemsetAsync(p->res_bar, 0, res_bar_bytes(p), s));
-  if (e0) FM_HIP(hipEventRecord(e0, s));
-  void *args[] = {&a};
-  hipError_t err = hipLaunchCooperativeKernel(resident_kernel_for(p->prm.necho), dim3(p->res_grid),
-                                              dim3(fm::kResNT), args, 0, s);
+  hipError_t err = launch_resident_for(p->prm.necho, a, p->res_grid, s, e0, e1);
   if (err != hipSuccess) return fail(FM_ERR_HIP, std::string("resident launch: ") + hipGetErrorString(err));
-  if (e1) FM_HIP(hipEventRecord(e1, s));
   p->q += 1;
   p->iter_host += niter;
   set_parts(p, 0, 0);
@@ -645,10 +661,9 @@ bool plan_resident(fm_plan *p) {
     return false;
   // voxel pairs (z even, z odd) of one column: one red and one black voxel
   if (q.nz > fm::kResTile || q.nz % 2) return false;
-  int ncu = 0, per = 0, coop = 0;
+  int ncu = 0, per = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || ncu < 1)
     return false;
-  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, p->device) != hipSuccess || !coop) return false;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, resident_kernel_for(q.necho), fm::kResNT, 0) != hipSuccess ||
       per < 1)
     return false;

@@ -1,6 +1,6 @@
 // Resident schedule of the red-black NCG-MLS iteration (MIX precision).
 //
-// One cooperative launch runs many iterations.  Each workgroup owns a tile of
+// One launch runs many iterations.  Each workgroup owns a tile of
 // tx x ty whole columns (at most kResNT * kResV voxels) and keeps every
 // per-voxel quantity of its voxels on chip for the whole launch: the echo data
 // in registers; f, z, g, g_prev, D, 1/h and p in LDS.  Per iteration the

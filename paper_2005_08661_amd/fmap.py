@@ -160,6 +160,8 @@ class Plan:
         h = C.c_void_p()
         _check(lib().fm_plan_create(C.byref(params), C.byref(h)))
         self._h = h
+        # bumped by every call that replaces the data or the map the adjoint differentiates
+        self.generation = 0
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -215,6 +217,7 @@ class Plan:
 
     def setup(self, y, sens, mask):
         self._take_inputs(y, sens, mask)
+        self.generation += 1
         _check(lib().fm_setup(self._h, _ptr(self._y), _ptr(self._s), _ptr(self._m), _stream()))
 
     def init(self):
@@ -236,6 +239,7 @@ class Plan:
         g = self._vec(g)
         piv = self._vol(torch.float64, g.device)
         p = self._vol(torch.float64, g.device)
+        self.generation += 1
         _check(lib().fm_precondition(self._h, _ptr(curv), _ptr(g), _ptr(piv), _ptr(p), _stream()))
         return piv, p
 
@@ -247,6 +251,7 @@ class Plan:
             out = self._vol(torch.float64, self._m.device)
         elif tuple(out.shape) != self.shape or out.dtype != torch.float64 or not out.is_contiguous():
             raise ValueError("out must be a contiguous float64 device tensor of shape %s" % (self.shape,))
+        self.generation += 1
         _check(lib().fm_solve(self._h, _ptr(self._y), _ptr(self._s), _ptr(self._m), _ptr(f0c), _ptr(out),
                               _stream()))
         return out
@@ -257,6 +262,7 @@ class Plan:
             out = self._vol(torch.float64, self._m.device)
         elif tuple(out.shape) != self.shape or out.dtype != torch.float64 or not out.is_contiguous():
             raise ValueError("out must be a contiguous float64 device tensor of shape %s" % (self.shape,))
+        self.generation += 1
         _check(lib().fm_iterate(self._h, C.c_int32(int(niter)), _ptr(out), _stream()))
         return out
 
@@ -313,6 +319,7 @@ class Plan:
         return out
 
     def set_beta(self, beta):
+        self.generation += 1
         _check(lib().fm_set_beta(self._h, C.c_double(float(beta))))
         self.params.beta = float(beta)
 
@@ -451,18 +458,25 @@ def _autograd_function():
         """f = argmin of the regularised cost for (y, beta); backward by the implicit adjoint.
 
         forward(y, sens, mask, beta, plan, f0, maxit, rtol): y complex64 [ncoil, L, X, Y, Z],
-        beta a 0-d float tensor.  Gradients flow to y and beta."""
+        beta a 0-d float tensor.  Gradients flow to y and beta.  The backward pass differentiates the
+        map the plan holds, so it must come before the plan's next solve: a backward after another
+        solve, iterate, setup or set_beta on the same plan raises instead of returning the gradient
+        of the later solve."""
 
         @staticmethod
         def forward(ctx, y, sens, mask, beta, plan, f0=None, maxit=1000, rtol=1e-10):
             plan.set_beta(float(beta))
             f = plan.solve(y.detach(), None if sens is None else sens.detach(), mask, f0)
             ctx.plan, ctx.maxit, ctx.rtol = plan, maxit, rtol
+            ctx.generation = plan.generation
             ctx.beta_dtype = beta.dtype
             return f
 
         @staticmethod
         def backward(ctx, gf):
+            if ctx.plan.generation != ctx.generation:
+                raise RuntimeError("the plan has run another solve since this forward pass; its backward "
+                                   "would differentiate that solve (use one plan per live graph)")
             out = ctx.plan.adjoint(gf.detach(), want_dy=ctx.needs_input_grad[0], maxit=ctx.maxit,
                                    rtol=ctx.rtol)
             dy = out["dy"] if ctx.needs_input_grad[0] else None

@@ -92,3 +92,36 @@ def test_source_hash_ignores_comments_only():
     assert _code_only(a) == _code_only(b)
     assert _code_only("char q = '\"'; int b; // tail") == "char q = '\"'; int b;"
     assert _code_only("int a = 1;") != _code_only("int a = 2;")
+
+
+def test_flip_threshold_and_map_diff(bench):
+    # TE 0 / 2.2 / 4.4 ms: the closest pair is 2.2 ms apart, half its wrap period is 1/(2 * 2.2 ms)
+    assert bench.flip_threshold([0.0, 2.2e-3, 4.4e-3]) == pytest.approx(1.0 / 4.4e-3)
+    a = [[0.0, 1.0], [2.0, 300.0]]
+    b = [[0.0, 0.0], [2.0, 0.0]]
+    m = [[True, True], [True, False]]
+    import numpy as np
+    d = bench.map_diff(np.array(a), np.array(b), np.array(m), 227.0)
+    assert d["max_abs_hz"] == 1.0 and d["basin_flips"] == 0
+    assert d["rms_hz"] == pytest.approx(np.sqrt(1.0 / 3.0))
+    d = bench.map_diff(np.array(a), np.array(b), np.ones((2, 2), bool), 227.0)
+    assert d["basin_flips"] == 1
+
+
+def test_host_threads_respects_environment(bench, monkeypatch):
+    n = len(os.sched_getaffinity(0))
+    monkeypatch.setenv("OMP_NUM_THREADS", "1")
+    assert bench.host_threads() == 1
+    monkeypatch.delenv("OMP_NUM_THREADS")
+    assert bench.host_threads() == n
+
+
+def test_roofline_limiter_from_measured_traffic(bench):
+    kinfo = {"resident": {"gbs": 3500.0, "avg_us": 5000.0}}
+    e = bench.roofline_entry(kinfo, "resident", None)
+    assert e["bound"] == "hbm" and e["frac"] == pytest.approx(3500.0 / 8000.0) and e["limiter"] is None
+    e = bench.roofline_entry(kinfo, "resident", 8.3e9)  # 8.3 GB in 5 ms: 1.66 TB/s
+    assert e["measured_frac"] == pytest.approx(8.3e9 / 5e-3 / 8e12)
+    assert e["limiter"].startswith("latency")
+    e = bench.roofline_entry(kinfo, "resident", 25e9)
+    assert e["limiter"] == "hbm bandwidth"

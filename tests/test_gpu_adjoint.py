@@ -151,6 +151,23 @@ def test_autograd_function_matches_adjoint():
         assert float(beta.grad) == pytest.approx(ref["dbeta"], rel=1e-9)
 
 
+def test_autograd_backward_after_another_solve_raises():
+    """The backward pass differentiates the map the plan holds: after a second forward on the same plan,
+    the first output's backward must refuse rather than return the second solve's gradient."""
+    vol = small_volume()
+    say("autograd, two forwards on one plan")
+    y, s, m = fmap.to_device(vol)
+    prm = fmap.params_for(vol, precision=fmap.F64, ordering=fmap.REDBLACK, niter=50)
+    with fmap.Plan(prm) as plan:
+        beta = torch.tensor(vol.beta, dtype=torch.float64, requires_grad=True)
+        f1 = fmap.fieldmap_solve(y, s, m, beta, plan)
+        f2 = fmap.fieldmap_solve(y, s, m, beta * 2.0, plan)
+        with pytest.raises(RuntimeError, match="another solve"):
+            f1.sum().backward()
+        f2.sum().backward()  # the live one still works
+        assert beta.grad is not None and np.isfinite(float(beta.grad))
+
+
 def test_adjoint_edge_cases():
     vol = small_volume()
     say("adjoint edge cases")

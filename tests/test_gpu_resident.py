@@ -1,4 +1,4 @@
-"""The resident schedule (one cooperative launch for all iterations) against the
+"""The resident schedule (one launch for all iterations) against the
 streaming schedule and the FP64 oracle.
 
 Both schedules run the same arithmetic per voxel; only the
