@@ -625,6 +625,7 @@ fm_status run_resident(fm_plan *p, int niter, hipStream_t s, hipEvent_t e0 = nul
     a.Z[i] = (float *)p->Z[i];
     a.G[i] = (float *)p->G[i];
   }
+  a.Gr = (float *)p->X;  // n floats: the two parity halves of the red face voxels' g (unused otherwise in red-black order)
   a.P = (float *)p->P;
   a.hinv = p->hinv;
   a.par0 = (int32_t)(p->iter_host & 1);

@@ -13,13 +13,19 @@
 // of the streaming chain).
 //
 // Neighbour values inside a tile come from LDS; across tile faces they come
-// from the plan's global arrays, which every workgroup publishes with
-// agent-coherent stores before the barrier and reads with agent-coherent
-// loads after it (the tiles of one launch may run on different XCDs, whose L2
-// caches are not coherent with each other).  The arrays are those of the
-// streaming schedule with the same parity convention (f_i in F[i&1], z_i in
-// Z[i&1], g_i in G[i&1]), so the final pass and later streaming iterations
-// continue from them unchanged.
+// from global arrays, which every workgroup publishes with agent-coherent
+// stores before the barrier and reads with agent-coherent loads after it (the
+// tiles of one launch may run on different XCDs, whose L2 caches are not
+// coherent with each other).  Per iteration only the face columns are
+// published (the columns a neighbour tile reads), each voxel pair (z even,
+// z odd) of a column with one 8-byte store, so every store fills whole cache
+// lines: f and z in the voxel-order arrays of the streaming schedule, and the
+// values only one colour's neighbours read at the pair's index j/2: g of the
+// red voxels (two parity halves of Gr), 1/h of the red voxels and p of the
+// black ones.  At the end of the launch every workgroup writes f, z and g of
+// all its voxels to the voxel-order arrays with the streaming schedule's
+// parity convention (f_i in F[i&1], z_i in Z[i&1], g_i in G[i&1]), so the
+// final pass and later streaming iterations continue from them unchanged.
 //
 // The grid barrier is a two-level arrival count (one counter per group of
 // workgroups, then one global counter); the last arrival releases each group
@@ -62,8 +68,9 @@ struct ResArgs {
   const uint8_t *code;
   const PairC<float> *pairs;
   float *F[2], *Z[2], *G[2];
-  float *P;
-  double *hinv;
+  float *Gr;           // [2][n/2]: g of the red voxels of the face columns at the pair index, by parity
+  float *P;            // p of the black voxels of the face columns at the pair index
+  double *hinv;        // 1/h of the red voxels of the face columns at the pair index
   int32_t par0;        // parity of the first iteration of the launch
   int32_t niter;       // iterations of this launch
   int32_t nparts_in;   // incoming partial sums (previous launch)
@@ -79,6 +86,12 @@ struct ResArgs {
 
 __device__ __forceinline__ uint32_t ld_coh_u32(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Agent-coherent store of two adjacent floats (p 8-byte aligned) as one 8-byte store.
+__device__ __forceinline__ void st_coh2(float *p, float lo, float hi) {
+  const uint64_t v = (uint64_t)__float_as_uint(lo) | ((uint64_t)__float_as_uint(hi) << 32);
+  __hip_atomic_store((uint64_t *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Grid barrier number e (1, 2, ...): all of this workgroup's coherent stores
@@ -282,6 +295,23 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
       }
     }
   }
+  // pairs of face columns: a voxel of the pair has an in-mask x or y neighbour outside the tile
+  uint32_t facem = 0;
+#pragma unroll
+  for (int q = 0; q < NPR; ++q) {
+    const uint32_t c0 = cv[2 * q], c1 = cv[2 * q + 1];
+    const uint32_t out0 = ((c0 >> 1) & 15u) & ~((c0 >> 8) & 15u), out1 = ((c1 >> 1) & 15u) & ~((c1 >> 8) & 15u);
+    if (jv[2 * q] >= 0 && (out0 | out1)) facem |= 1u << q;
+  }
+  const int n2 = (int)(g.n >> 1);
+  // g_{i0-1} of the red face voxels, read as g_prev by the neighbours' first black pass (after the
+  // gradient pass's neighbour wait, which completes these stores first)
+#pragma unroll
+  for (int q = 0; q < NPR; ++q) {
+    if (!(facem >> q & 1u)) continue;
+    const int l0 = 2 * (q * kResNT + (int)threadIdx.x), lir = l0 + (((cv[2 * q] >> 16) & 1u) ? 0 : 1);
+    st_coh(a.Gr + (size_t)((a.par0 & 1) ^ 1) * n2 + (jv[2 * q] >> 1), lg[(a.par0 & 1) ^ 1][lir]);
+  }
   {
     // the incoming state and the partial sums the previous launch left (as take_state)
     double t[4] = {0.0, 0.0, 0.0, 0.0};
@@ -360,7 +390,7 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
   for (int it = 0; it < a.niter && live; ++it) {
     const int par = (a.par0 + it) & 1;
     float *Fc = a.F[par], *Fp = a.F[par ^ 1], *Zc = a.Z[par], *Zp = a.Z[par ^ 1];
-    float *Gc = a.G[par], *Gp = a.G[par ^ 1];
+    float *Grc = a.Gr + (size_t)par * n2, *Grp = a.Gr + (size_t)(par ^ 1) * n2;
     float *lgc = lg[par], *lgp = lg[par ^ 1];
 
     // ---- gradient pass (as k_grad), every voxel: f_i = f_{i-1} + alpha z_{i-1}, g_i, D_i, 1/h_i
@@ -418,15 +448,16 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
         acc[2] += (double)gj * (double)gj;
         acc[3] += (double)lz[li] * (double)gj;
       }
-      // publish after the arithmetic (a store must be acknowledged before any
-      // later wait on the vector-memory counter completes)
+      // publish the face columns after the arithmetic (a store must be
+      // acknowledged before any later wait on the vector-memory counter
+      // completes): f of the pair, g and 1/h of its red voxel
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const int li = 2 * ((v >> 1) * kResNT + tid) + (v & 1), j = jv[v];
-        if (j < 0) continue;
-        st_coh(Fc + j, lf[li]);
-        st_coh(Gc + j, lgc[li]);
-        st_coh(a.hinv + j, lh[li]);
+      for (int q = 0; q < NPR; ++q) {
+        if (!(facem >> q & 1u)) continue;
+        const int l0 = 2 * (q * kResNT + tid), lir = l0 + (((cv[2 * q] >> 16) & 1u) ? 0 : 1), j0 = jv[2 * q];
+        st_coh2(Fc + j0, lf[l0], lf[l0 + 1]);
+        st_coh(Grc + (j0 >> 1), lgc[lir]);
+        st_coh(a.hinv + (j0 >> 1), lh[lir]);
       }
       res_put<4>(acc, a.part, kSlotG);
       if (!(live = res_nbwait(flags, a.tile, a.status, (uint32_t)it + 1))) break;
@@ -444,12 +475,13 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
         const bool sb = (cv[2 * q] >> 16) & 1u;
         int jx, jy;
         res_halo(sb ? cv[2 * q + 1] : cv[2 * q], sb ? jv[2 * q + 1] : jv[2 * q], jdflt, of, jx, jy);
-        hgx[q] = ld_coh(Gc + jx);
-        hpx[q] = ld_coh(Gp + jx);
-        hhx[q] = ld_coh(a.hinv + jx);
-        hgy[q] = ld_coh(Gc + jy);
-        hpy[q] = ld_coh(Gp + jy);
-        hhy[q] = ld_coh(a.hinv + jy);
+        // red neighbours across the faces: their pair's index
+        hgx[q] = ld_coh(Grc + (jx >> 1));
+        hpx[q] = ld_coh(Grp + (jx >> 1));
+        hhx[q] = ld_coh(a.hinv + (jx >> 1));
+        hgy[q] = ld_coh(Grc + (jy >> 1));
+        hpy[q] = ld_coh(Grp + (jy >> 1));
+        hhy[q] = ld_coh(a.hinv + (jy >> 1));
       }
 #pragma unroll
       for (int q = 0; q < NPR; ++q) {
@@ -491,9 +523,9 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < NPR; ++q) {
+        if (!(facem >> q & 1u)) continue;
         const bool sb = (cv[2 * q] >> 16) & 1u;
-        const uint32_t cb = sb ? cv[2 * q + 1] : cv[2 * q];
-        if (cb & NB_SELF) st_coh(a.P + (sb ? jv[2 * q + 1] : jv[2 * q]), lp[2 * (q * kResNT + tid) + (sb ? 1 : 0)]);
+        st_coh(a.P + (jv[2 * q] >> 1), lp[2 * (q * kResNT + tid) + (sb ? 1 : 0)]);
       }
       if (!(live = finish(acc, PK_DOTS, kSlotD, true))) break;
     }
@@ -510,10 +542,10 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
         const bool sb = (cv[2 * q] >> 16) & 1u;
         int jx, jy;
         res_halo(sb ? cv[2 * q] : cv[2 * q + 1], sb ? jv[2 * q] : jv[2 * q + 1], jdflt, of, jx, jy);
-        hpx[q] = ld_coh(a.P + jx);
+        hpx[q] = ld_coh(a.P + (jx >> 1));  // black neighbours' p at their pair's index
         hzx[q] = ld_coh(Zp + jx);
         hfx[q] = ld_coh(Fc + jx);
-        hpy[q] = ld_coh(a.P + jy);
+        hpy[q] = ld_coh(a.P + (jy >> 1));
         hzy[q] = ld_coh(Zp + jy);
         hfy[q] = ld_coh(Fc + jy);
       }
@@ -557,10 +589,10 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
       }
       __syncthreads();
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        lz[2 * ((v >> 1) * kResNT + tid) + (v & 1)] = znew[v];
-        if (jv[v] >= 0) st_coh(Zc + jv[v], znew[v]);
-      }
+      for (int v = 0; v < V; ++v) lz[2 * ((v >> 1) * kResNT + tid) + (v & 1)] = znew[v];
+#pragma unroll
+      for (int q = 0; q < NPR; ++q)
+        if (facem >> q & 1u) st_coh2(Zc + jv[2 * q], znew[2 * q], znew[2 * q + 1]);
       if (!(live = finish(acc, PK_DIR, kSlotR, false))) break;
     }
 
@@ -581,6 +613,19 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
       }
       live = finish(acc, PK_MLS, kSlotM + mslot, false);
       mslot ^= 1;
+    }
+  }
+  // f, z and g of every voxel of the tile for the kernels after this launch
+  // (the last iteration's parity; plain stores, ordered by the kernel boundary)
+  {
+    const int parl = (a.par0 + a.niter - 1) & 1;
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) {
+      const int l0 = 2 * (q * kResNT + (int)threadIdx.x), j0 = jv[2 * q];
+      if (j0 < 0) continue;
+      *(float2 *)(a.F[parl] + j0) = make_float2(lf[l0], lf[l0 + 1]);
+      *(float2 *)(a.Z[parl] + j0) = make_float2(lz[l0], lz[l0 + 1]);
+      *(float2 *)(a.G[parl] + j0) = make_float2(lg[parl][l0], lg[parl][l0 + 1]);
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
