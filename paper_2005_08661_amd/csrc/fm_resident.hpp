@@ -133,33 +133,36 @@ __device__ __forceinline__ bool res_barrier(uint32_t *bar, int32_t *status, uint
   return ok_s != 0;
 }
 
-// Partial sums of one phase: block-reduce, thread 0 publishes row k at
-// part[(slot * kMaxK + k) * grid + block].
 // Publish this tile's progress (all its coherent stores complete) and wait
-// until the face-neighbour tiles have reached the same count.
+// until the face-neighbour tiles have reached the same count: lanes 0-3 of
+// the first wave poll the four neighbours' flags together.
 __device__ __forceinline__ bool res_nbwait(uint32_t *flags, const ResTile &t, int32_t *status, uint32_t count) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   __shared__ int32_t okn_s;
-  if (threadIdx.x == 0) {
-    const int b = (int)blockIdx.x, bx = b / t.nty, by = b % t.nty;
-    __hip_atomic_store(flags + b, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const int b = (int)blockIdx.x;
+  if (threadIdx.x == 0) __hip_atomic_store(flags + b, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x < kWave) {
+    const int q = (int)threadIdx.x, bx = b / t.nty, by = b % t.nty;
+    int nbq = -1;
+    if (q == 0 && bx > 0) nbq = b - t.nty;
+    if (q == 1 && bx + 1 < t.ntx) nbq = b + t.nty;
+    if (q == 2 && by > 0) nbq = b - 1;
+    if (q == 3 && by + 1 < t.nty) nbq = b + 1;
     int ok = 1;
-    const int nbr[4] = {bx > 0 ? b - t.nty : -1, bx + 1 < t.ntx ? b + t.nty : -1, by > 0 ? b - 1 : -1,
-                        by + 1 < t.nty ? b + 1 : -1};
-    for (int q = 0; q < 4 && ok; ++q) {
-      if (nbr[q] < 0) continue;
-      int spins = 0;
-      while (ld_coh_u32(flags + nbr[q]) < count) {
-        if (++spins > kResSpin || __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 8) {
-          ok = 0;
-          atomicCAS(status, 0, 8);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
+    for (int spins = 0;; ++spins) {
+      const bool mine = nbq < 0 || ld_coh_u32(flags + nbq) >= count;
+      if (__all(mine)) break;
+      const bool bad = q == 0 && (spins > kResSpin ||
+                                  __hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 8);
+      if (__any(bad)) {
+        ok = 0;
+        if (q == 0) atomicCAS(status, 0, 8);
+        break;
       }
+      __builtin_amdgcn_s_sleep(1);
     }
-    okn_s = ok;
+    if (q == 0) okn_s = ok;
   }
   __syncthreads();
   return okn_s != 0;
