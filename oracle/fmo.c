@@ -704,10 +704,17 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
   double *lap = (double *)malloc(nb), *lapz = (double *)malloc(nb), *tmp = (double *)malloc(nb);
   double *tmp2 = (double *)malloc(nb);
   int st = FMO_OK;
+  /* IC_t factor: the diagonal and one row per offset of its pattern */
+  double *lict = NULL;
+  if (pb->precond == FMO_PRECOND_ICT) {
+    int32_t offs[3 * FMO_ICT_MAXOFF], noff = 0;
+    if (second_order(pb) || fmo_ict_offsets(pb->ict_level, 9, offs, &noff)) st = FMO_ERR_ARG;
+    else lict = (double *)malloc(nb * (size_t)(1 + noff));
+  }
   for (int64_t j = 0; j < n; ++j) f[j] = mask[j] ? f0[j] : 0.0;
   double gtp_prev = 0.0;
 
-  for (int it = 0; it < pb->niter; ++it) {
+  for (int it = 0; it < pb->niter && st == FMO_OK; ++it) {
     /* gradient g = grad Phi + beta C^T C f, and the Huber curvature D
      * (per-voxel costs into tmp, summed in natural order below) */
     FMO_PARALLEL_FOR
@@ -733,6 +740,10 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
       st = fmo_factor(pb, mask, curv, piv);
       if (st) break;
       fmo_apply(pb, mask, piv, g, p);
+    } else if (pb->precond == FMO_PRECOND_ICT) {
+      st = fmo_ict_factor(pb, mask, curv, lict);
+      if (st) break;
+      fmo_ict_apply(pb, mask, lict, g, p);
     } else if (pb->precond == FMO_PRECOND_DIAG) {
       for (int64_t j = 0; j < n; ++j) {
         if (!mask[j]) {
@@ -846,6 +857,7 @@ int fmo_solve(const fmo_problem *pb, const double *zhat, const uint8_t *mask, co
   free(lapz);
   free(tmp);
   free(tmp2);
+  free(lict);
   pairs_free(&pr);
   return st;
 }
@@ -970,6 +982,7 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
                 const double *dldf, int32_t maxit, double rtol, double *v, double *dldbeta,
                 double *dzhat, int32_t *iters) {
   if (check_pb(pb) || !zhat || !mask || !fhat || !dldf || !v || maxit < 0) return FMO_ERR_ARG;
+  if (pb->precond == FMO_PRECOND_ICT) return FMO_ERR_ARG; /* adjoint CG preconditioners: IC(0), diag, none */
   const int64_t n = nvox(pb);
   const int L = pb->necho;
   const double beta = pb->beta;
@@ -1071,6 +1084,201 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
   free(lap);
   pairs_free(&pr);
   return st;
+}
+
+/* ---------------------------------------------------------------------------
+ * Incomplete Cholesky with a drop tolerance (IC_t), Sec. III-B.
+ */
+
+int fmo_ict_offsets(int32_t level, int32_t side, int32_t *offs, int32_t *count) {
+  if (level < 0 || side < 3 || side % 2 == 0 || side > 15 || !offs || !count) return FMO_ERR_ARG;
+  const int S = side, N = S * S * S, BIG = 1 << 20;
+  int *lev = (int *)malloc(sizeof(int) * (size_t)N * N);
+  if (!lev) return FMO_ERR_ARG;
+  /* structural nonzeros of the 7-point H (level 0); z fastest */
+  for (int i = 0; i < N * N; ++i) lev[i] = BIG;
+  for (int i = 0; i < N; ++i) {
+    const int x = i / (S * S), y = (i / S) % S, z = i % S;
+    lev[i * N + i] = 0;
+    const int nb[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (int q = 0; q < 6; ++q) {
+      const int a = x + nb[q][0], b = y + nb[q][1], c = z + nb[q][2];
+      if (a < 0 || a >= S || b < 0 || b >= S || c < 0 || c >= S) continue;
+      lev[i * N + (a * S + b) * S + c] = 0;
+    }
+  }
+  /* symbolic elimination in natural order: eliminating k gives every pair
+   * (i, j) of later voxels the level lev(i,k) + lev(k,j) + 1 if smaller */
+  for (int k = 0; k < N; ++k)
+    for (int i = k + 1; i < N; ++i) {
+      const int lik = lev[i * N + k];
+      if (lik > level) continue;
+      for (int j = k + 1; j < N; ++j) {
+        const int lkj = lev[k * N + j];
+        if (lkj > level) continue;
+        const int v = lik + lkj + 1;
+        if (v < lev[i * N + j]) lev[i * N + j] = v;
+      }
+    }
+  const int c0 = S / 2, centre = (c0 * S + c0) * S + c0;
+  int cnt = 0;
+  /* earlier voxels in the centre row's pattern, by descending (dx, dy, dz) */
+  for (int dx = S; dx >= -S; --dx)
+    for (int dy = S; dy >= -S; --dy)
+      for (int dz = S; dz >= -S; --dz) {
+        const int a = c0 - dx, b = c0 - dy, c = c0 - dz;
+        if (a < 0 || a >= S || b < 0 || b >= S || c < 0 || c >= S) continue;
+        const int k = (a * S + b) * S + c;
+        if (k >= centre || lev[centre * N + k] > level) continue;
+        if (cnt == FMO_ICT_MAXOFF) {
+          free(lev);
+          return FMO_ERR_ARG;
+        }
+        offs[3 * cnt] = dx;
+        offs[3 * cnt + 1] = dy;
+        offs[3 * cnt + 2] = dz;
+        ++cnt;
+      }
+  free(lev);
+  *count = cnt;
+  return FMO_OK;
+}
+
+/* Voxel j - o if it lies inside the volume and the mask, else -1. */
+static int64_t ict_nb(const fmo_problem *pb, const uint8_t *mask, int64_t j, const int32_t *o) {
+  int64_t c[3];
+  coords(pb, j, c);
+  const int64_t x = c[0] - o[0], y = c[1] - o[1], z = c[2] - o[2];
+  if (x < 0 || x >= pb->nx || y < 0 || y >= pb->ny || z < 0 || z >= pb->nz) return -1;
+  const int64_t k = (x * pb->ny + y) * pb->nz + z;
+  return mask[k] ? k : -1;
+}
+
+/* Entry H_jk of H = diag(curv) + beta C^T C. */
+static double ict_h(const fmo_problem *pb, const uint8_t *mask, const double *curv, int64_t j, int64_t k) {
+  int64_t nb[6];
+  const int c = neighbours(pb, mask, j, nb);
+  if (j == k) return curv[j] + pb->beta * c;
+  for (int q = 0; q < c; ++q)
+    if (nb[q] == k) return -pb->beta;
+  return 0.0;
+}
+
+/* Pattern positions of row j (earlier voxels), ascending: returns how many;
+ * idx[] the voxel indices, slot[] their offset number. */
+static int ict_row(const fmo_problem *pb, const uint8_t *mask, const int32_t *offs, int noff, int64_t j,
+                   int64_t *idx, int *slot) {
+  int m = 0;
+  for (int u = 0; u < noff; ++u) {
+    const int64_t k = ict_nb(pb, mask, j, offs + 3 * u);
+    if (k < 0) continue;
+    int i = m++;
+    while (i > 0 && idx[i - 1] > k) {
+      idx[i] = idx[i - 1];
+      slot[i] = slot[i - 1];
+      --i;
+    }
+    idx[i] = k;
+    slot[i] = u;
+  }
+  return m;
+}
+
+int fmo_ict_factor(const fmo_problem *pb, const uint8_t *mask, const double *curv, double *L) {
+  if (check_pb(pb) || !mask || !curv || !L || second_order(pb) || !(pb->ict_factor >= 0.0)) return FMO_ERR_ARG;
+  int32_t offs[3 * FMO_ICT_MAXOFF], noff = 0;
+  if (fmo_ict_offsets(pb->ict_level, 9, offs, &noff)) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  for (int64_t i = 0; i < (int64_t)(1 + noff) * n; ++i) L[i] = 0.0;
+  /* H_max: the largest magnitude in H (diagonal, or beta off the diagonal) */
+  double hmax = 0.0;
+  for (int64_t j = 0; j < n; ++j) {
+    if (!mask[j]) continue;
+    int64_t nb[6];
+    const int c = neighbours(pb, mask, j, nb);
+    const double hjj = fabs(curv[j] + pb->beta * c);
+    if (hjj > hmax) hmax = hjj;
+    if (c > 0 && pb->beta > hmax) hmax = pb->beta;
+  }
+  const double tol = pb->ict_factor * hmax;
+  int64_t rj[FMO_ICT_MAXOFF], rk[FMO_ICT_MAXOFF];
+  int sj[FMO_ICT_MAXOFF], sk[FMO_ICT_MAXOFF];
+  for (int64_t j = 0; j < n; ++j) {
+    if (!mask[j]) continue;
+    const int mj = ict_row(pb, mask, offs, noff, j, rj, sj);
+    double diag = ict_h(pb, mask, curv, j, j);
+    for (int a = 0; a < mj; ++a) {
+      const int64_t k = rj[a];
+      double s = ict_h(pb, mask, curv, j, k);
+      /* m < k in both rows' patterns: row j's positions before k that row k also holds */
+      const int mk = ict_row(pb, mask, offs, noff, k, rk, sk);
+      for (int b = 0; b < a; ++b)
+        for (int e = 0; e < mk; ++e)
+          if (rk[e] == rj[b]) s -= L[(int64_t)(1 + sj[b]) * n + j] * L[(int64_t)(1 + sk[e]) * n + k];
+      double v = s / L[k];
+      /* drop test of reading R21: |L_jk| < tol ||H(k:N, k)||_1 */
+      int64_t nb[6];
+      const int c = neighbours(pb, mask, k, nb);
+      double colnorm = fabs(curv[k] + pb->beta * c);
+      for (int q = 0; q < c; ++q)
+        if (nb[q] > k) colnorm += pb->beta;
+      if (fabs(v) < tol * colnorm) v = 0.0;
+      L[(int64_t)(1 + sj[a]) * n + j] = v;
+    }
+    for (int a = 0; a < mj; ++a) {
+      const double v = L[(int64_t)(1 + sj[a]) * n + j];
+      diag -= v * v;
+    }
+    if (!(diag > 0.0)) return isfinite(diag) ? FMO_ERR_NOT_PD : FMO_ERR_NONFINITE;
+    L[j] = sqrt(diag);
+  }
+  return FMO_OK;
+}
+
+int fmo_ict_apply(const fmo_problem *pb, const uint8_t *mask, const double *L, const double *g, double *p) {
+  if (check_pb(pb) || !mask || !L || !g || !p) return FMO_ERR_ARG;
+  int32_t offs[3 * FMO_ICT_MAXOFF], noff = 0;
+  if (fmo_ict_offsets(pb->ict_level, 9, offs, &noff)) return FMO_ERR_ARG;
+  const int64_t n = nvox(pb);
+  double *y = (double *)calloc((size_t)(n ? n : 1), sizeof(double));
+  if (!y) return FMO_ERR_ARG;
+  int64_t rj[FMO_ICT_MAXOFF];
+  int sj[FMO_ICT_MAXOFF];
+  /* forward: L y = g, natural order */
+  for (int64_t j = 0; j < n; ++j) {
+    if (!mask[j]) continue;
+    const int mj = ict_row(pb, mask, offs, noff, j, rj, sj);
+    double s = g[j];
+    for (int a = 0; a < mj; ++a) s -= L[(int64_t)(1 + sj[a]) * n + j] * y[rj[a]];
+    y[j] = s / L[j];
+  }
+  /* backward: L^T p = y, reverse order; row j of L^T holds L_ij of the later
+   * voxels i = j + o_u (ascending i) */
+  for (int64_t j = 0; j < n; ++j) p[j] = 0.0;
+  for (int64_t j = n - 1; j >= 0; --j) {
+    if (!mask[j]) continue;
+    /* later voxels i = j + o_u inside the volume and the mask, ascending */
+    int64_t ri[FMO_ICT_MAXOFF];
+    int si[FMO_ICT_MAXOFF], m = 0;
+    for (int u = 0; u < noff; ++u) {
+      const int32_t up[3] = {-offs[3 * u], -offs[3 * u + 1], -offs[3 * u + 2]};
+      const int64_t i = ict_nb(pb, mask, j, up);
+      if (i < 0) continue;
+      int t = m++;
+      while (t > 0 && ri[t - 1] > i) {
+        ri[t] = ri[t - 1];
+        si[t] = si[t - 1];
+        --t;
+      }
+      ri[t] = i;
+      si[t] = u;
+    }
+    double s = y[j];
+    for (int a = 0; a < m; ++a) s -= L[(int64_t)(1 + si[a]) * n + ri[a]] * p[ri[a]];
+    p[j] = s / L[j];
+  }
+  free(y);
+  return FMO_OK;
 }
 
 int fmo_components(const fmo_problem *pb, int32_t ncoil, const double *y, const double *s,

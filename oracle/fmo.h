@@ -39,7 +39,11 @@ enum { FMO_OK = 0, FMO_ERR_ARG = 1, FMO_ERR_NOT_PD = 5, FMO_ERR_NONFINITE = 6 };
  * natural; no two voxels of a colour are pattern neighbours of the
  * second-order C^T C, whose neighbours lie 1 or 2 steps along an axis). */
 enum { FMO_ORDER_NATURAL = 0, FMO_ORDER_REDBLACK = 1, FMO_ORDER_COLOR3 = 2 };
-enum { FMO_PRECOND_IC0 = 0, FMO_PRECOND_DIAG = 1, FMO_PRECOND_NONE = 2 };
+/* IC(0), diag(H), none, or incomplete Cholesky with a drop tolerance (IC_t,
+ * natural order; see fmo_ict_factor). */
+enum { FMO_PRECOND_IC0 = 0, FMO_PRECOND_DIAG = 1, FMO_PRECOND_NONE = 2, FMO_PRECOND_ICT = 3 };
+/* Largest number of lower offsets of an IC_t fill pattern (level 2: 11). */
+enum { FMO_ICT_MAXOFF = 16 };
 
 /* Columns of the per-iteration trace written by fmo_solve. */
 enum {
@@ -65,6 +69,8 @@ typedef struct {
   int32_t ordering;     /* FMO_ORDER_* (IC(0) ordering) */
   int32_t precond;      /* FMO_PRECOND_* */
   int32_t reg_order;    /* finite differences of C: 1 (also when 0) or 2 (Sec. II eq. (cost)) */
+  double ict_factor;    /* IC_t: tolerance = ict_factor * H_max (Sec. III-B uses 1e-3); 0 keeps every entry */
+  int32_t ict_level;    /* IC_t: fill bound, the level-of-fill pattern kept (1 or 2) */
 } fmo_problem;
 
 /* IC(0) of H = diag(curv) + beta C^T C on the pattern of H, in the problem's
@@ -170,6 +176,35 @@ int fmo_adjoint(const fmo_problem *pb, const double *zhat, const uint8_t *mask, 
 int fmo_components(const fmo_problem *pb, int32_t ncoil, const double *y, const double *s,
                    const uint8_t *mask, const double *f, int32_t K, int32_t npeak, const double *fat_hz,
                    const double *fat_amp, double *out);
+
+/* Lower offsets (dx, dy, dz) of the level-`level` fill pattern of IC in
+ * natural order (z fastest) on a full grid: the positions (j, j - o) whose
+ * level of fill is at most `level`, where stencil entries have level 0 and
+ * eliminating voxel k gives (i, j) the level lev(i,k) + lev(k,j) + 1 (the
+ * symbolic factorisation of IC(level)).  Found by that symbolic elimination on
+ * a cube of side `side` (odd; the pattern of its centre row), returned in
+ * descending lexicographic order of (dx, dy, dz).  offs: [FMO_ICT_MAXOFF][3]. */
+int fmo_ict_offsets(int32_t level, int32_t side, int32_t *offs, int32_t *count);
+
+/* Incomplete Cholesky with a drop tolerance, IC_t (Sec. III-B, Table 1; the
+ * preconditioner of Sec. IV), of H = diag(curv) + beta C^T C over the in-mask
+ * voxels in natural order: H ~ L L^T with L lower triangular.  Row by row in
+ * natural order, each entry L_jk of a pattern position k < j (k = j - o, o one
+ * of the fmo_ict_offsets of pb->ict_level, k inside the volume and the mask)
+ * is
+ *   L_jk = (H_jk - sum_{m < k} L_jm L_km) / L_kk
+ * (m over the pattern positions of both rows, ascending), then set to zero if
+ * |L_jk| < tol ||H(k:N, k)||_1 with tol = ict_factor * H_max and H_max the
+ * largest magnitude in H (reading R21); L_jj = sqrt(H_jj - sum_k L_jk^2).
+ * Reading R23: the fill is bounded to the level-`ict_level` pattern.
+ *   L: [1 + noff][n]: row 0 the diagonal L_jj, row 1 + u the entry
+ *   L(j, j - o_u) (0 outside the mask, the volume or the pattern).
+ * FMO_ERR_NOT_PD if H_jj - sum_k L_jk^2 <= 0. */
+int fmo_ict_factor(const fmo_problem *pb, const uint8_t *mask, const double *curv, double *L);
+
+/* p = (L L^T)^{-1} g with the factor of fmo_ict_factor: forward solve
+ * L y = g in natural order, then backward solve L^T p = y in reverse. */
+int fmo_ict_apply(const fmo_problem *pb, const uint8_t *mask, const double *L, const double *g, double *p);
 
 /* Threads for the loops over independent voxels when the oracle is built with
  * OpenMP (no effect otherwise); every sum over voxels stays sequential in

@@ -16,7 +16,8 @@ _LIBPATH = os.path.join(_HERE, "libfmo.so")
 _lib = None
 
 NATURAL, REDBLACK, COLOR3 = 0, 1, 2
-IC0, DIAG, NONE = 0, 1, 2
+IC0, DIAG, NONE, ICT = 0, 1, 2, 3
+ICT_MAXOFF = 16
 TR = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)
 TR_W = 8
 ERRORS = {1: "bad argument", 5: "not positive definite", 6: "non-finite value"}
@@ -30,7 +31,8 @@ class _Problem(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("necho", C.c_int32),
                 ("te", C.c_void_p), ("gam", C.c_void_p), ("beta", C.c_double),
                 ("niter", C.c_int32), ("nmls", C.c_int32), ("ordering", C.c_int32),
-                ("precond", C.c_int32), ("reg_order", C.c_int32)]
+                ("precond", C.c_int32), ("reg_order", C.c_int32), ("ict_factor", C.c_double),
+                ("ict_level", C.c_int32)]
 
 
 def lib():
@@ -86,7 +88,8 @@ def _check(st):
 class Problem:
     """Geometry and parameters of one solve (mirrors fmo_problem)."""
 
-    def __init__(self, shape, te, gamma, beta, niter=10, nmls=3, ordering=NATURAL, precond=IC0, reg_order=1):
+    def __init__(self, shape, te, gamma, beta, niter=10, nmls=3, ordering=NATURAL, precond=IC0, reg_order=1,
+                 ict_factor=1e-3, ict_level=1):
         self.shape = tuple(int(s) for s in shape)
         self.te = _f64(te)
         self.gamma = _c128(gamma)
@@ -96,11 +99,14 @@ class Problem:
         self.ordering = int(ordering)
         self.precond = int(precond)
         self.reg_order = int(reg_order)  # finite differences of C: 1 or 2
+        self.ict_factor = float(ict_factor)  # IC_t tolerance = ict_factor * H_max
+        self.ict_level = int(ict_level)  # IC_t fill bound (level-of-fill pattern)
 
     def c(self):
         nx, ny, nz = self.shape
         s = _Problem(nx, ny, nz, len(self.te), _p(self.te).value, _p(self.gamma).value, self.beta,
-                     self.niter, self.nmls, self.ordering, self.precond, self.reg_order)
+                     self.niter, self.nmls, self.ordering, self.precond, self.reg_order, self.ict_factor,
+                     self.ict_level)
         return s
 
 
@@ -161,6 +167,34 @@ def reg_diag(pb, mask):
     c = pb.c()
     _check(lib().fmo_reg_diag(C.byref(c), _p(mask), _p(out)))
     return out
+
+
+def ict_offsets(level, side=9):
+    """Lower offsets (dx, dy, dz) of the level-`level` fill pattern (fmo_ict_offsets), descending."""
+    offs = np.zeros((ICT_MAXOFF, 3), np.int32)
+    cnt = C.c_int32(0)
+    _check(lib().fmo_ict_offsets(C.c_int32(int(level)), C.c_int32(int(side)), _p(offs), C.byref(cnt)))
+    return [tuple(int(v) for v in offs[i]) for i in range(cnt.value)]
+
+
+def ict_factor(pb, mask, curv):
+    """IC_t factor (fmo_ict_factor): array [1 + noff, ...shape], row 0 the diagonal L_jj, row 1 + u the
+    entry L(j, j - o_u) for the offsets of ict_offsets(pb.ict_level)."""
+    mask, curv = _u8(mask), _f64(curv)
+    noff = len(ict_offsets(pb.ict_level))
+    L = np.zeros((1 + noff,) + pb.shape)
+    c = pb.c()
+    _check(lib().fmo_ict_factor(C.byref(c), _p(mask), _p(curv), _p(L)))
+    return L
+
+
+def ict_apply(pb, mask, L, g):
+    """p = (L L^T)^{-1} g with an IC_t factor of ict_factor."""
+    mask, L, g = _u8(mask), _f64(L), _f64(g)
+    p = np.zeros(pb.shape)
+    c = pb.c()
+    _check(lib().fmo_ict_apply(C.byref(c), _p(mask), _p(L), _p(g), _p(p)))
+    return p
 
 
 def ic_general(pb, mask, curv, g):
@@ -279,14 +313,15 @@ def components(pb, y, sens, mask, f, fat_hz=None, fat_amp=None):
 
 # --- whole pipeline for a synthetic volume --------------------------------------
 
-def problem_for(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, beta=None):
+def problem_for(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, beta=None, ict_factor=1e-3,
+                ict_level=1):
     if vol.model == "waterfat":
         gam = gamma_waterfat(vol.te, vol.fat_hz, vol.fat_amp)
     else:
         gam = gamma_fieldmap(vol.necho)
     return Problem(vol.shape, vol.te, gam, vol.beta if beta is None else beta,
                    vol.niter if niter is None else niter, vol.nmls if nmls is None else nmls,
-                   ordering, precond, getattr(vol, "reg_order", 1))
+                   ordering, precond, getattr(vol, "reg_order", 1), ict_factor, ict_level)
 
 
 def largest_fat_offset(vol):
@@ -302,9 +337,10 @@ def initial_map(vol, pb, zhat, pwls_iters=10, nsweep=100):
     return init_fieldmap(zhat, vol.te, vol.mask)
 
 
-def run_volume(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, f0=None, want_mls=False):
+def run_volume(vol, ordering=NATURAL, precond=IC0, niter=None, nmls=None, f0=None, want_mls=False, ict_factor=1e-3,
+               ict_level=1):
     """Combine, initialise and solve one synthetic volume with the oracle."""
-    pb = problem_for(vol, ordering, precond, niter, nmls)
+    pb = problem_for(vol, ordering, precond, niter, nmls, ict_factor=ict_factor, ict_level=ict_level)
     zhat = combine(vol.y, vol.sens)
     if f0 is None:
         f0 = initial_map(vol, pb, zhat)

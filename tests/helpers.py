@@ -64,3 +64,39 @@ def textbook_ic0(A):
 
 def wrap(x):
     return x - 2 * np.pi * np.round(x / (2 * np.pi))
+
+
+def pattern_from_offsets(mask, offsets):
+    """Boolean [n, n] (in-mask unknowns, natural order) marking the diagonal and
+    the lower positions (j, j - o) for the given (dx, dy, dz) offsets whose
+    voxel lies inside the volume and the mask."""
+    mask = mask.astype(bool)
+    shape = mask.shape
+    idx = np.arange(mask.size).reshape(shape)
+    sel = mask.ravel()
+    col = np.full(mask.size, -1)
+    col[sel] = np.arange(int(sel.sum()))
+    n = int(sel.sum())
+    P = np.eye(n, dtype=bool)
+    x, y, z = np.meshgrid(*[np.arange(s) for s in shape], indexing="ij")
+    for dx, dy, dz in offsets:
+        xs, ys, zs = x - dx, y - dy, z - dz
+        ok = (xs >= 0) & (xs < shape[0]) & (ys >= 0) & (ys < shape[1]) & (zs >= 0) & (zs < shape[2]) & mask
+        j = idx[ok]
+        k = idx[xs[ok], ys[ok], zs[ok]]
+        both = sel[k]
+        P[col[j[both]], col[k[both]]] = True
+    return P
+
+
+def textbook_ic_pattern(A, pat):
+    """Dense incomplete Cholesky restricted to a lower pattern (column-oriented
+    textbook algorithm): entries outside pat are never formed."""
+    n = A.shape[0]
+    L = np.zeros_like(A)
+    for k in range(n):
+        L[k, k] = np.sqrt(A[k, k] - np.dot(L[k, :k], L[k, :k]))
+        for i in range(k + 1, n):
+            if pat[i, k]:
+                L[i, k] = (A[i, k] - np.dot(L[i, :k], L[k, :k])) / L[k, k]
+    return L
