@@ -69,8 +69,17 @@ typedef enum { FM_PREC_F64 = 0, FM_PREC_MIX = 1 } fm_precision;
  * C^T C couples voxels 1 and 2 steps apart and so couples voxels of one
  * red-black colour; built for reg_order 2 with IC(0) only). */
 typedef enum { FM_ORDER_NATURAL = 0, FM_ORDER_REDBLACK = 1, FM_ORDER_COLOR3 = 2 } fm_ordering;
-/* Preconditioner: IC(0) (the paper's), diag(H), or none. */
-typedef enum { FM_PRECOND_IC0 = 0, FM_PRECOND_DIAG = 1, FM_PRECOND_NONE = 2 } fm_precond;
+/* Preconditioner: IC(0), diag(H), none, or incomplete Cholesky with a drop
+ * tolerance (IC_t, the preconditioner of Sec. III-B and Sec. IV: entries of
+ * the factor below ict_factor x H_max, scaled by their column's 1-norm, are
+ * dropped; H_max is the largest magnitude in H).  IC_t runs in natural order
+ * with its fill bounded to the level-ict_level pattern of natural-order IC
+ * (fm_ict_offsets); it needs the first-order regulariser and is not available
+ * to batches, fm_adjoint or the resident schedule. */
+typedef enum { FM_PRECOND_IC0 = 0, FM_PRECOND_DIAG = 1, FM_PRECOND_NONE = 2, FM_PRECOND_ICT = 3 } fm_precond;
+
+/* Largest number of lower offsets of an IC_t pattern (level 2). */
+#define FM_ICT_MAXOFF 11
 
 /* Columns of the per-iteration trace (see fm_get_trace). */
 enum {
@@ -108,6 +117,9 @@ typedef struct {
                                     in the volume and the mask); 2 needs the field-map model and, with
                                     IC(0), the three-colour order (FM_ERR_ARG otherwise), and is not
                                     available to batches or fm_adjoint */
+  double ict_factor;             /* IC_t: drop tolerance = ict_factor x H_max (Sec. III-B uses 1e-3); >= 0,
+                                    0 keeps every entry of the pattern */
+  int32_t ict_level;             /* IC_t: fill bound, the level-of-fill pattern kept (0, 1 or 2) */
 } fm_params;
 
 typedef struct fm_plan fm_plan;
@@ -120,6 +132,21 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **plan);
 
 /* Free the plan and its workspace.  NULL is accepted. */
 fm_status fm_plan_destroy(fm_plan *plan);
+
+/* The IC_t fill pattern of a level (Sec. III-B; host only, no device work):
+ * the lower offsets (dx, dy, dz) such that L(j, j - o) may be nonzero, voxel
+ * j - o being (x - dx, y - dy, z - dz), in descending lexicographic order.
+ *   offsets host int32 [FM_ICT_MAXOFF][3]; count host int32.
+ * FM_ERR_ARG for a level outside 0..2. */
+fm_status fm_ict_offsets(int32_t level, int32_t *offsets, int32_t *count);
+
+/* The IC_t factor of the plan's last preconditioner step (fm_precondition,
+ * or the last iteration of fm_solve / fm_iterate): L with H ~ L L^T.
+ *   L dev float64 [1 + count][nx][ny][nz]: block 0 the diagonal L_jj, block
+ *     1 + u the entry L(j, j - o_u) for offset u of fm_ict_offsets(ict_level)
+ *     (0 outside the mask, the volume, or where the drop test removed it)
+ * FM_ERR_ARG if the plan's preconditioner is not IC_t. */
+fm_status fm_get_factor(fm_plan *plan, double *L, hipStream_t stream);
 
 /* Setup (Sec. II eq. (r) and the Algorithm's precompute step): coil-combine
  * the images into zhat_l = sum_c conj(s_c) y_cl / sqrt(sum_c |s_c|^2) and keep
@@ -144,9 +171,10 @@ fm_status fm_eval(fm_plan *plan, const double *f, double *phi, double *dphi, dou
 
 /* Preconditioner step of the Algorithm for a given curvature d and gradient
  * g (dev float64 [N]): builds the plan's preconditioner for
- * H = diag(d) + beta C^T C (IC(0) in the plan's ordering, diag(H), or the
- * identity) and writes p = P^{-1} g (dev float64 [N]).  piv, if not NULL,
- * receives the IC(0) pivots P_jj (dev float64 [N]).  Needs fm_setup.
+ * H = diag(d) + beta C^T C (IC(0) in the plan's ordering, diag(H), the
+ * identity, or IC_t) and writes p = P^{-1} g (dev float64 [N]).  piv, if not
+ * NULL, receives the pivots P_jj (dev float64 [N]; IC_t: L_jj^2).  Needs
+ * fm_setup.
  * Returns FM_ERR_NOT_PD (after synchronising the stream) if a pivot is not
  * positive. */
 fm_status fm_precondition(fm_plan *plan, const double *curv, const double *g, double *piv,

@@ -21,6 +21,7 @@
 #include "fm_adjoint.hpp"
 #include "fm_resident.hpp"
 #include "fm_order2.hpp"
+#include "fm_ict.hpp"
 
 using fm::kBlock;
 using fm::kMaxGrid;
@@ -125,6 +126,11 @@ struct fm_plan {
   int res_grid = 0;
   double *res_part = nullptr;  // [2][kMaxK][res_grid]
   uint32_t *res_bar = nullptr; // barrier counters
+  // IC_t (incomplete Cholesky with a drop tolerance, natural order, bounded fill)
+  bool ict = false;
+  int ict_noff = 0, ict_nlev = 0, ict_kcol = 0, ict_blocks = 0;
+  double *ict_lo = nullptr, *ict_ld = nullptr, *ict_y = nullptr, *ict_pd = nullptr;
+  double *ict_hmax = nullptr, *ict_hpart = nullptr;
 };
 
 namespace {
@@ -309,6 +315,39 @@ void set_parts(fm_plan *p, int nparts, int nvals) {
   p->last_nvals = nvals;
 }
 
+// IC_t: H_max, then the factorisation with the forward solve level by level,
+// then the backward solve in reverse level order (outside the state chain).
+template <typename T, int LEVEL>
+fm_status enqueue_ict(fm_plan *p, const T *g, hipStream_t s, Recorder *rec) {
+  fm::IctArgs<T> a{};
+  a.geo = p->geo;
+  a.beta = p->prm.beta;
+  a.factor = p->prm.ict_factor;
+  a.hmax = p->ict_hmax;
+  a.code = p->code;
+  a.D = (const T *)p->D;
+  a.kcol = p->ict_kcol;
+  a.lo = p->ict_lo;
+  a.ld = p->ict_ld;
+  a.y = p->ict_y;
+  a.pd = p->ict_pd;
+  a.P = (T *)p->P;
+  a.status = p->status;
+  FM_LAUNCH(FM_K_PRECOND_A, fm::k_ict_hmax<T>, dim3(p->grid), dim3(kBlock), s, p->geo, (const uint8_t *)p->code,
+            (const T *)p->D, p->prm.beta, p->ict_hpart);
+  FM_LAUNCH_CHECK();
+  FM_LAUNCH(FM_K_PRECOND_A, fm::k_ict_hmax_fin, dim3(1), dim3(kBlock), s, (const double *)p->ict_hpart, p->grid,
+            p->ict_hmax);
+  FM_LAUNCH_CHECK();
+  for (int lv = 0; lv < p->ict_nlev; ++lv)
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_ict_fwd<T, LEVEL>), dim3(p->ict_blocks), dim3(kBlock), s, a, g, lv);
+  FM_LAUNCH_CHECK();
+  for (int lv = p->ict_nlev - 1; lv >= 0; --lv)
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_ict_bwd<T, LEVEL>), dim3(p->ict_blocks), dim3(kBlock), s, a, lv);
+  FM_LAUNCH_CHECK();
+  return FM_OK;
+}
+
 template <typename T>
 fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *rec = nullptr) {
   auto pargs = [&](fm_plan *pp, uint64_t q) {
@@ -316,7 +355,16 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
     a.store_piv = gsrc ? 1 : 0;  // the standalone call reports the pivots
     return a;
   };
-  if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_COLOR3) {
+  if (p->prm.precond == FM_PRECOND_ICT) {
+    const T *g = gsrc ? gsrc : (const T *)p->G[p->iter_host & 1];
+    fm_status st = p->prm.ict_level == 0 ? enqueue_ict<T, 0>(p, g, s, rec)
+                   : (p->prm.ict_level == 1 ? enqueue_ict<T, 1>(p, g, s, rec) : enqueue_ict<T, 2>(p, g, s, rec));
+    if (st) return st;
+    FM_LAUNCH(FM_K_DOTS, fm::k_ict_dots<T>, dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++),
+              (const double *)p->ict_pd, gsrc);
+    FM_LAUNCH_CHECK();
+    set_parts(p, p->sgrid, 2);
+  } else if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_COLOR3) {
     // second-order C: forward colours 0-1, forward colour 2 (+ its p), backward colours 1, 0
     FM_LAUNCH(FM_K_PRECOND_A, (fm::k_ic3_fwd1<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
     FM_LAUNCH_CHECK();
@@ -513,7 +561,7 @@ fm_status validate(const fm_params *p) {
   if (p->precision != FM_PREC_F64 && p->precision != FM_PREC_MIX) return fail(FM_ERR_ARG, "bad precision");
   if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK && p->ordering != FM_ORDER_COLOR3)
     return fail(FM_ERR_ARG, "bad ordering");
-  if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_NONE) return fail(FM_ERR_ARG, "bad preconditioner");
+  if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_ICT) return fail(FM_ERR_ARG, "bad preconditioner");
   if (p->reg_order < 0 || p->reg_order > 2) return fail(FM_ERR_ARG, "reg_order must be 1 or 2");
   if (p->reg_order == 2 && p->model != FM_FIELDMAP)
     return fail(FM_ERR_ARG, "second-order differences are built for the field-map model only");
@@ -521,6 +569,12 @@ fm_status validate(const fm_params *p) {
     return fail(FM_ERR_ARG, "IC(0) with second-order differences is built in three-colour order (FM_ORDER_COLOR3)");
   if (p->ordering == FM_ORDER_COLOR3 && (p->reg_order != 2 || p->precond != FM_PRECOND_IC0))
     return fail(FM_ERR_ARG, "three-colour order is built for IC(0) with second-order differences only");
+  if (p->precond == FM_PRECOND_ICT) {
+    if (p->ordering != FM_ORDER_NATURAL) return fail(FM_ERR_ARG, "IC_t is built in natural order");
+    if (p->reg_order == 2) return fail(FM_ERR_ARG, "IC_t is built for first-order differences");
+    if (p->ict_level < 0 || p->ict_level > 2) return fail(FM_ERR_ARG, "ict_level must be 0, 1 or 2");
+    if (!(p->ict_factor >= 0.0) || !std::isfinite(p->ict_factor)) return fail(FM_ERR_ARG, "ict_factor must be finite, >= 0");
+  }
   if (p->model == FM_FIELDMAP && p->te[1] == p->te[0])
     return fail(FM_ERR_ARG, "field-map initialisation needs t_2 != t_1");
   if (p->model == FM_WATERFAT) {
@@ -694,9 +748,22 @@ bool plan_resident(fm_plan *p) {
   return true;
 }
 
+fm_status run_graph(fm_plan *p, int niter, hipStream_t s);
+
 fm_status run_iterations(fm_plan *p, int niter, hipStream_t s) {
   if (niter <= 0) return FM_OK;
   if (use_resident(p)) return run_resident(p, niter, s);
+  if (!p->ict) return run_graph(p, niter, s);
+  // IC_t launches a kernel per wavefront level (thousands per iteration): one
+  // graph of one iteration, replayed niter times
+  for (int i = 0; i < niter; ++i) {
+    fm_status st = run_graph(p, 1, s);
+    if (st) return st;
+  }
+  return FM_OK;
+}
+
+fm_status run_graph(fm_plan *p, int niter, hipStream_t s) {
   const std::vector<int64_t> key = {(int64_t)(p->q & 1), niter, p->iter_host & 1, p->last_nparts, p->last_nvals};
   auto it = p->graphs.find(key);
   if (it == p->graphs.end()) {
@@ -1075,6 +1142,30 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
     FM_ALLOC(p->res_part, sizeof(double) * fm::kResSlots * kMaxK * (size_t)p->res_grid);
     FM_ALLOC(p->res_bar, res_bar_bytes(p));
   }
+  if (prm->precond == FM_PRECOND_ICT) {
+    int noff = 0, wa = 1, wb = 1;
+    if (prm->ict_level == 0) {
+      noff = fm::IctPattern<0>::n, wa = fm::IctPattern<0>::a, wb = fm::IctPattern<0>::b;
+    } else if (prm->ict_level == 1) {
+      noff = fm::IctPattern<1>::n, wa = fm::IctPattern<1>::a, wb = fm::IctPattern<1>::b;
+    } else {
+      noff = fm::IctPattern<2>::n, wa = fm::IctPattern<2>::a, wb = fm::IctPattern<2>::b;
+    }
+    p->ict = true;
+    p->ict_noff = noff;
+    p->ict_nlev = wa * (prm->nx - 1) + wb * (prm->ny - 1) + (prm->nz - 1) + 1;
+    p->ict_kcol = (prm->nz - 1) / wb + 1;
+    p->ict_blocks = (int)(((int64_t)prm->nx * p->ict_kcol + kBlock - 1) / kBlock);
+    FM_ALLOC(p->ict_lo, sizeof(double) * n * (size_t)noff);
+    FM_ALLOC(p->ict_ld, sizeof(double) * n);
+    FM_ALLOC(p->ict_y, sizeof(double) * n);
+    FM_ALLOC(p->ict_pd, sizeof(double) * n);
+    FM_ALLOC(p->ict_hmax, sizeof(double));
+    FM_ALLOC(p->ict_hpart, sizeof(double) * kMaxGrid);
+    if (hipMemset(p->ict_lo, 0, sizeof(double) * n * (size_t)noff) != hipSuccess ||
+        hipMemset(p->ict_ld, 0, sizeof(double) * n) != hipSuccess)
+      return cleanup(fail(FM_ERR_HIP, "hipMemset of the IC_t factor failed"));
+  }
   if (prm->model == FM_WATERFAT) {
     FM_ALLOC(p->rho, sizeof(double) * n);
     FM_ALLOC(p->gabs, sizeof(double) * L * L);
@@ -1117,6 +1208,36 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
 fm_status fm_plan_destroy(fm_plan *p) {
   if (!p) return FM_OK;
   free_plan(p);
+  return FM_OK;
+}
+
+fm_status fm_ict_offsets(int32_t level, int32_t *offsets, int32_t *count) {
+  if (!offsets || !count) return fail(FM_ERR_ARG, "offsets and count must not be NULL");
+  auto put = [&](auto pat) {
+    using P = decltype(pat);
+    for (int u = 0; u < P::n; ++u)
+      for (int d = 0; d < 3; ++d) offsets[3 * u + d] = P::off[u][d];
+    *count = P::n;
+  };
+  if (level == 0)
+    put(fm::IctPattern<0>{});
+  else if (level == 1)
+    put(fm::IctPattern<1>{});
+  else if (level == 2)
+    put(fm::IctPattern<2>{});
+  else
+    return fail(FM_ERR_ARG, "IC_t level must be 0, 1 or 2");
+  return FM_OK;
+}
+
+fm_status fm_get_factor(fm_plan *p, double *L, hipStream_t s) {
+  fm_status cs = check_plan(p);
+  if (cs) return cs;
+  if (!L) return fail(FM_ERR_ARG, "L must not be NULL");
+  if (!p->ict) return fail(FM_ERR_ARG, "the plan's preconditioner is not IC_t");
+  const size_t n = (size_t)p->n;
+  FM_HIP(hipMemcpyAsync(L, p->ict_ld, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  FM_HIP(hipMemcpyAsync(L + n, p->ict_lo, sizeof(double) * n * (size_t)p->ict_noff, hipMemcpyDeviceToDevice, s));
   return FM_OK;
 }
 
@@ -1234,7 +1355,11 @@ fm_status fm_precondition(fm_plan *p, const double *curv, const double *g, doubl
     } else {
       hipLaunchKernelGGL(fm::k_from_work<T>, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const T *)p->P, pout);
       FM_LAUNCH_CHECK();
-      if (piv) {
+      if (piv && p->ict) {
+        hipLaunchKernelGGL(fm::k_ict_piv, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const uint8_t *)p->code,
+                           (const double *)p->ict_ld, piv);
+        FM_LAUNCH_CHECK();
+      } else if (piv) {
         hipLaunchKernelGGL(fm::k_pivots, dim3(p->grid), dim3(kBlock), 0, s, p->n, (const double *)p->ipiv, piv);
         FM_LAUNCH_CHECK();
       }
@@ -1327,6 +1452,7 @@ fm_status fm_adjoint(fm_plan *p, const double *dldf, const void *sens, void *dld
   if (maxit < 0 || !(rtol >= 0.0) || !std::isfinite(rtol)) return fail(FM_ERR_ARG, "maxit must be >= 0 and rtol finite, >= 0");
   if (!p->solved) return fail(FM_ERR_STATE, "fm_adjoint needs a converged map from fm_solve or fm_iterate");
   if (p->reg2) return fail(FM_ERR_ARG, "fm_adjoint is built for the first-order regulariser only");
+  if (p->ict) return fail(FM_ERR_ARG, "fm_adjoint preconditions with IC(0), the diagonal or nothing, not IC_t");
   fm_status st = adj_alloc(p);
   if (st) return st;
   FM_HIP(hipMemsetAsync(p->a_status, 0, sizeof(int32_t), s));

@@ -20,7 +20,8 @@ FM_MAX_PEAK = 16
 FIELDMAP, WATERFAT = 0, 1
 F64, MIX = 0, 1
 NATURAL, REDBLACK, COLOR3 = 0, 1, 2
-IC0, DIAG, NONE = 0, 1, 2
+IC0, DIAG, NONE, ICT = 0, 1, 2, 3
+ICT_MAXOFF = 11
 TRACE_COLS = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)
 TRACE_W = 8
 
@@ -32,7 +33,8 @@ EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval
             "fm_solve", "fm_iterate", "fm_get_trace", "fm_mask_count", "fm_time_kernels",
             "fm_adjoint", "fm_set_beta", "fm_components", "fm_plan_status", "fm_set_schedule",
             "fm_get_schedule", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
-            "fm_batch_get_trace", "fm_batch_set_grid", "fm_batch_autotune", "fm_status_string", "fm_last_error"]
+            "fm_batch_get_trace", "fm_batch_set_grid", "fm_batch_autotune", "fm_status_string", "fm_last_error",
+            "fm_ict_offsets", "fm_get_factor"]
 KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls", "resident"]
 SCHED_AUTO, SCHED_STREAM, SCHED_RESIDENT = 0, 1, 2
 
@@ -49,7 +51,8 @@ class Params(C.Structure):
                 ("niter", C.c_int32), ("nmls", C.c_int32), ("model", C.c_int32), ("npeak", C.c_int32),
                 ("fat_hz", C.c_double * FM_MAX_PEAK), ("fat_amp", C.c_double * FM_MAX_PEAK),
                 ("nsweep", C.c_int32), ("pwls_iters", C.c_int32), ("precision", C.c_int32),
-                ("ordering", C.c_int32), ("precond", C.c_int32), ("reg_order", C.c_int32)]
+                ("ordering", C.c_int32), ("precond", C.c_int32), ("reg_order", C.c_int32),
+                ("ict_factor", C.c_double), ("ict_level", C.c_int32)]
 
 
 _lib = None
@@ -88,6 +91,8 @@ def lib():
         L.fm_batch_set_grid.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         L.fm_batch_autotune.argtypes = [vp, vp, vp, vp, C.c_int32, C.POINTER(C.c_int32),
                                         C.POINTER(C.c_double), vp]
+        L.fm_ict_offsets.argtypes = [C.c_int32, vp, C.POINTER(C.c_int32)]
+        L.fm_get_factor.argtypes = [vp, vp, vp]
         L.fm_status_string.restype = C.c_char_p
         L.fm_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -112,7 +117,8 @@ def _stream():
 
 
 def make_params(shape, ncoil, te, beta, niter=100, nmls=3, model=FIELDMAP, fat_hz=None, fat_amp=None,
-                nsweep=100, pwls_iters=10, precision=F64, ordering=NATURAL, precond=IC0, reg_order=1):
+                nsweep=100, pwls_iters=10, precision=F64, ordering=NATURAL, precond=IC0, reg_order=1,
+                ict_factor=1e-3, ict_level=1):
     p = Params()
     p.nx, p.ny, p.nz = (int(s) for s in shape)
     p.ncoil = int(ncoil)
@@ -139,16 +145,19 @@ def make_params(shape, ncoil, te, beta, niter=100, nmls=3, model=FIELDMAP, fat_h
     p.ordering = int(ordering)
     p.precond = int(precond)
     p.reg_order = int(reg_order)
+    p.ict_factor = float(ict_factor)
+    p.ict_level = int(ict_level)
     return p
 
 
-def params_for(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, nmls=None):
+def params_for(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, nmls=None, ict_factor=1e-3,
+               ict_level=1):
     """Parameters for a synthetic volume of paper_2005_08661_amd.synth."""
     return make_params(vol.shape, vol.ncoil, vol.te, vol.beta, vol.niter if niter is None else niter,
                        vol.nmls if nmls is None else nmls,
                        WATERFAT if vol.model == "waterfat" else FIELDMAP, vol.fat_hz, vol.fat_amp,
                        precision=precision, ordering=ordering, precond=precond,
-                       reg_order=getattr(vol, "reg_order", 1))
+                       reg_order=getattr(vol, "reg_order", 1), ict_factor=ict_factor, ict_level=ict_level)
 
 
 class Plan:
@@ -323,10 +332,27 @@ class Plan:
         _check(lib().fm_set_beta(self._h, C.c_double(float(beta))))
         self.params.beta = float(beta)
 
+    def factor(self):
+        """IC_t factor of the last preconditioner step (fm_get_factor): float64 [1 + noff, X, Y, Z], block 0
+        the diagonal, block 1 + u the entry L(j, j - o_u) for the offsets of ict_offsets(ict_level)."""
+        import torch
+        noff = len(ict_offsets(self.params.ict_level))
+        out = torch.zeros((1 + noff,) + self.shape, dtype=torch.float64, device=self._m.device)
+        _check(lib().fm_get_factor(self._h, _ptr(out), _stream()))
+        return out
+
     def mask_count(self):
         v = C.c_int64(0)
         _check(lib().fm_mask_count(self._h, C.byref(v), _stream()))
         return v.value
+
+
+def ict_offsets(level):
+    """The IC_t fill pattern of a level (fm_ict_offsets): list of (dx, dy, dz)."""
+    offs = np.zeros((ICT_MAXOFF, 3), np.int32)
+    n = C.c_int32(0)
+    _check(lib().fm_ict_offsets(C.c_int32(int(level)), C.c_void_p(offs.ctypes.data), C.byref(n)))
+    return [tuple(int(v) for v in offs[i]) for i in range(n.value)]
 
 
 def _ptr_array(ts):
@@ -439,13 +465,13 @@ def to_device(vol, device="cuda"):
 
 
 def solve_volume(vol, precision=F64, ordering=NATURAL, precond=IC0, niter=None, nmls=None, f0=None,
-                 device="cuda"):
+                 device="cuda", ict_factor=1e-3, ict_level=1):
     """Solve one synthetic volume on the GPU; returns (f as numpy, trace)."""
     import torch
     y, s, m = to_device(vol, device)
     if f0 is not None and not isinstance(f0, torch.Tensor):
         f0 = torch.from_numpy(np.ascontiguousarray(f0, dtype=np.float64)).to(device)
-    with Plan(params_for(vol, precision, ordering, precond, niter, nmls)) as plan:
+    with Plan(params_for(vol, precision, ordering, precond, niter, nmls, ict_factor, ict_level)) as plan:
         f = plan.solve(y, s, m, f0)
         tr = plan.trace()
         return f.cpu().numpy(), tr

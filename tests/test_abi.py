@@ -124,3 +124,35 @@ def test_three_colour_order_validation_on_the_host():
     for p in refused:
         assert L.fm_plan_create(C.byref(p), C.byref(h)) == 1 and not h.value
         assert len(L.fm_last_error()) > 0
+
+
+def test_ict_pattern_tables_match_the_oracles_symbolic_elimination():
+    """The GPU's compile-time IC_t patterns (fm_ict_offsets, host only) equal the level-of-fill patterns
+    the oracle derives by symbolic elimination."""
+    if not os.path.exists(fmap.LIBPATH):
+        pytest.skip("libfmap.so not built")
+    import oracle as O
+    for level in (0, 1, 2):
+        assert fmap.ict_offsets(level) == O.ict_offsets(level)
+    with pytest.raises(fmap.FmapError):
+        fmap.ict_offsets(3)
+
+
+def test_ict_parameters_validated_on_the_host():
+    if not os.path.exists(fmap.LIBPATH):
+        pytest.skip("libfmap.so not built")
+    L = fmap.lib()
+    h = C.c_void_p()
+    bad = [
+        fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT, ordering=fmap.REDBLACK),
+        fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT, ict_level=3),
+        fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT, ict_factor=-1.0),
+        fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT, ict_factor=float("nan")),
+        fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT, reg_order=2),
+        fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=4),
+    ]
+    for p in bad:
+        assert L.fm_plan_create(C.byref(p), C.byref(h)) == 1, L.fm_last_error()
+        assert not h.value
+    arr = (fmap.Params * 2)(*[fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT)] * 2)
+    assert L.fm_batch_create(2, C.cast(arr, C.c_void_p), C.byref(h)) == 1
