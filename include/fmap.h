@@ -338,6 +338,32 @@ enum {
 fm_status fm_time_kernels(fm_plan *plan, int32_t niter, double *ms, int32_t *launches,
                           hipStream_t stream);
 
+/* ---- Allocation-free solve ------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * solve as fm_solve (coil combination, the initial map of eq. (w0) unless f0
+ * is given, niter iterations, the final map), on a problem described by prm
+ * alone (no plan), with every piece of workspace taken from one fixed device
+ * array of 48 MiB that the library holds on each GPU it runs on until the
+ * process ends.  The call launches kernels on the stream and nothing else: no
+ * device allocation or free, no memset, no copy, no graph; it does not
+ * synchronise.  The first call on a device looks the array's device address
+ * up (make that first call outside any stream capture).
+ *   prm        host; the field-map model, first-order differences,
+ *              necho <= 4, red-black IC(0) / diag(H) / none, at most 2^18
+ *              voxels and 4096 iterations, and a workspace that fits the
+ *              array (FM_ERR_SHAPE otherwise, FM_ERR_ARG for the rest)
+ *   y, sens, mask, f0   as for fm_solve (f0 may be NULL)
+ *   f_out      dev float64 [N], written
+ *   status_out dev int32, or NULL: receives the device status word of the
+ *              solve (FM_OK, FM_ERR_NOT_PD, FM_ERR_NONFINITE)
+ * Every call on one GPU uses the same array, which keeps the last call's
+ * contents (the state the solve needs cleared is cleared by each call):
+ * calls that overlap on one GPU (on different streams or threads) race and
+ * must be serialised by the caller. */
+fm_status fm_solve_noalloc(const fm_params *prm, const void *y, const void *sens, const uint8_t *mask,
+                           const double *f0, double *f_out, int32_t *status_out, hipStream_t stream);
+
 /* Human-readable text for a status code, and the last error message of the
  * calling thread. */
 const char *fm_status_string(fm_status st);

@@ -1009,6 +1009,10 @@ struct OpAdjoint {
 
 }  // namespace
 
+namespace {
+fm_status setup_launch(fm_plan *p, const void *y, const void *sens, const uint8_t *mask, hipStream_t s);
+}
+
 // ---------------------------------------------------------------------------
 extern "C" {
 
@@ -1246,6 +1250,18 @@ fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *m
   if (cs) return cs;
   if (!y || !mask) return fail(FM_ERR_ARG, "y and mask must not be NULL");
   if (!sens && p->prm.ncoil != 1) return fail(FM_ERR_ARG, "sens may be NULL only when ncoil == 1");
+  fm_status st = setup_launch(p, y, sens, mask, s);
+  if (st) return st;
+  p->setup_done = true;
+  return FM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// The setup kernels of fm_setup (coil combination, codes, initial map, in-mask
+// count), on the plan's arrays.
+fm_status setup_launch(fm_plan *p, const void *y, const void *sens, const uint8_t *mask, hipStream_t s) {
   const double two_pi = 6.283185307179586476925286766559;
   auto launch = [&](auto tag) -> fm_status {
     using T = decltype(tag);
@@ -1288,11 +1304,11 @@ fm_status fm_setup(fm_plan *p, const void *y, const void *sens, const uint8_t *m
     }
     return FM_OK;
   };
-  fm_status st = p->mix ? launch(float{}) : launch(double{});
-  if (st) return st;
-  p->setup_done = true;
-  return FM_OK;
+  return p->mix ? launch(float{}) : launch(double{});
 }
+}  // namespace
+
+extern "C" {
 
 fm_status fm_init(fm_plan *p, double *f0, hipStream_t s) {
   fm_status cs = check_plan(p);
@@ -1567,3 +1583,6 @@ fm_status fm_mask_count(fm_plan *p, int64_t *count, hipStream_t s) {
 
 // Batched solves of many volumes.
 #include "fm_batch.inc"
+
+// The allocation-free solve.
+#include "fm_noalloc.inc"

@@ -34,7 +34,7 @@ EXPORTED = ["fm_plan_create", "fm_plan_destroy", "fm_setup", "fm_init", "fm_eval
             "fm_adjoint", "fm_set_beta", "fm_components", "fm_plan_status", "fm_set_schedule",
             "fm_get_schedule", "fm_batch_create", "fm_batch_destroy", "fm_batch_solve",
             "fm_batch_get_trace", "fm_batch_set_grid", "fm_batch_autotune", "fm_status_string", "fm_last_error",
-            "fm_ict_offsets", "fm_get_factor"]
+            "fm_ict_offsets", "fm_get_factor", "fm_solve_noalloc"]
 KERNEL_CLASSES = ["grad", "precond_a", "precond_b", "dots", "dir", "mls", "resident"]
 SCHED_AUTO, SCHED_STREAM, SCHED_RESIDENT = 0, 1, 2
 
@@ -93,6 +93,7 @@ def lib():
                                         C.POINTER(C.c_double), vp]
         L.fm_ict_offsets.argtypes = [C.c_int32, vp, C.POINTER(C.c_int32)]
         L.fm_get_factor.argtypes = [vp, vp, vp]
+        L.fm_solve_noalloc.argtypes = [C.POINTER(Params), vp, vp, vp, vp, vp, vp, vp]
         L.fm_status_string.restype = C.c_char_p
         L.fm_last_error.restype = C.c_char_p
         for name in EXPORTED:
@@ -353,6 +354,32 @@ def ict_offsets(level):
     n = C.c_int32(0)
     _check(lib().fm_ict_offsets(C.c_int32(int(level)), C.c_void_p(offs.ctypes.data), C.byref(n)))
     return [tuple(int(v) for v in offs[i]) for i in range(n.value)]
+
+
+def solve_noalloc(params, y, sens, mask, f0=None, out=None, status=None):
+    """fm_solve_noalloc: a solve with no plan and no device allocation inside the library (the caller's
+    tensors y, sens, mask, f0, out and the optional int32 device word status are the only memory it is
+    given).  Returns out."""
+    import torch
+    shape = (params.nx, params.ny, params.nz)
+    if tuple(y.shape) != (params.ncoil, params.necho) + shape or not y.is_cuda:
+        raise ValueError("y must be a device tensor of shape %s" % ((params.ncoil, params.necho) + shape,))
+    if tuple(mask.shape) != shape:
+        raise ValueError("mask must have shape %s" % (shape,))
+    for t in (y, sens, mask, f0, out, status):
+        if t is not None and not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+    if y.dtype != torch.complex64 or mask.dtype != torch.uint8 or (sens is not None and sens.dtype != torch.complex64):
+        raise ValueError("y and sens must be complex64, mask uint8")
+    if out is None or tuple(out.shape) != shape or out.dtype != torch.float64:
+        raise ValueError("out must be a float64 device tensor of shape %s" % (shape,))
+    if f0 is not None and (tuple(f0.shape) != shape or f0.dtype != torch.float64):
+        raise ValueError("f0 must be float64 of shape %s" % (shape,))
+    if status is not None and (status.numel() != 1 or status.dtype != torch.int32):
+        raise ValueError("status must be one int32")
+    _check(lib().fm_solve_noalloc(C.byref(params), _ptr(y), _ptr(sens), _ptr(mask), _ptr(f0), _ptr(out),
+                                  _ptr(status), _stream()))
+    return out
 
 
 def _ptr_array(ts):

@@ -156,3 +156,26 @@ def test_ict_parameters_validated_on_the_host():
         assert not h.value
     arr = (fmap.Params * 2)(*[fmap.make_params((4, 4, 4), 1, [0, 1e-3], 0.1, precond=fmap.ICT)] * 2)
     assert L.fm_batch_create(2, C.cast(arr, C.c_void_p), C.byref(h)) == 1
+
+
+def test_noalloc_solve_refuses_before_any_device_work():
+    """fm_solve_noalloc checks the problem against its fixed workspace on the host: too many voxels or
+    iterations give FM_ERR_SHAPE, unsupported modes FM_ERR_ARG, before anything touches a device."""
+    if not os.path.exists(fmap.LIBPATH):
+        pytest.skip("libfmap.so not built")
+    L = fmap.lib()
+    dummy = C.c_void_p(16)  # never dereferenced: every case is refused on the host
+    cases = [
+        (fmap.make_params((128, 128, 64), 1, [0, 1e-3, 2e-3], 0.1, precision=fmap.MIX, ordering=fmap.REDBLACK), 2),
+        (fmap.make_params((16, 16, 16), 1, [0, 1e-3, 2e-3], 0.1, niter=5000, ordering=fmap.REDBLACK), 2),
+        (fmap.make_params((16, 16, 16), 1, [0, 1e-3, 2e-3], 0.1, ordering=fmap.NATURAL), 1),
+        (fmap.make_params((16, 16, 16), 1, [0, 1e-3, 2e-3], 0.1, precond=fmap.ICT), 1),
+        (fmap.make_params((16, 16, 16), 1, [0, 1e-3, 2e-3, 3e-3, 4e-3], 0.1, ordering=fmap.REDBLACK), 1),
+        (fmap.make_params((16, 16, 16), 1, [1e-3, 2e-3], 0.1, model=fmap.WATERFAT, fat_hz=[-400.0],
+                          fat_amp=[1.0], ordering=fmap.REDBLACK), 1),
+    ]
+    for prm, expect in cases:
+        st = L.fm_solve_noalloc(C.byref(prm), dummy, None, dummy, None, dummy, None, None)
+        assert st == expect, (st, expect, L.fm_last_error())
+    prm = fmap.make_params((16, 16, 16), 1, [0, 1e-3], 0.1, ordering=fmap.REDBLACK)
+    assert L.fm_solve_noalloc(C.byref(prm), None, None, dummy, None, dummy, None, None) == 1
