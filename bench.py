@@ -326,12 +326,14 @@ def bench_batched(args, fmap, synth, torch, prec):
 
 def bench_convergence(args, fmap, vol, y, s, m, torch, prec, ms_iter_rb):
     """Iterations and time to reach a relative cost gap (Psi_i - Psi*) / (Psi_0 - Psi*) of 1e-3 and
-    1e-4 for each preconditioner on the benchmark volume, Psi* = the least cost of 400-iteration F64
-    solves with natural-order IC(0) and red-black IC(0).  Time = iterations x the measured time of one
+    1e-4 for each preconditioner on the benchmark volume, Psi* = the least cost of the 400-iteration F64
+    solves (IC(0) in natural and red-black order, IC_t with the level-1 pattern and the tolerance
+    1e-3 x H_max in natural order, diag(H), none).  Time = iterations x the measured time of one
     iteration of that preconditioner."""
     log("convergence: 400-iteration traces per preconditioner")
     runs = {"ic0_natural": (fmap.NATURAL, fmap.IC0), "ic0_redblack": (fmap.REDBLACK, fmap.IC0),
-            "diag": (fmap.NATURAL, fmap.DIAG), "none": (fmap.NATURAL, fmap.NONE)}
+            "ict_natural": (fmap.NATURAL, fmap.ICT), "diag": (fmap.NATURAL, fmap.DIAG),
+            "none": (fmap.NATURAL, fmap.NONE)}
     traces, ms_iter = {}, {}
     stream = torch.cuda.current_stream()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -362,6 +364,37 @@ def bench_convergence(args, fmap, vol, y, s, m, torch, prec, ms_iter_rb):
         log("  %-13s %.4f ms/iteration; gap 1e-3 after %s iterations (%s ms), 1e-4 after %s (%s ms)" % (
             name, ms_iter[name], row["iters_0.001"], None if row["ms_0.001"] is None else round(row["ms_0.001"], 2),
             row["iters_0.0001"], None if row["ms_0.0001"] is None else round(row["ms_0.0001"], 2)))
+    return res
+
+
+def bench_paper_mask(args, fmap, synth, torch, prec):
+    """The headline problem on the paper-rule mask (reading R13: the first echo's coil-combined magnitude
+    thresholded at 0.1 of its maximum, its convex hull, dilated twice): same solve, in-mask unknowns only."""
+    log("paper mask: generating 128x128x64 with the convex-hull mask")
+    vol = synth.mid_fieldmap(mask="paper")
+    y, s, m = fmap.to_device(vol)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = torch.zeros(vol.shape, dtype=torch.float64, device="cuda")
+    with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=fmap.REDBLACK)) as plan:
+        sched = "resident" if plan.schedule() == fmap.SCHED_RESIDENT else "stream"
+        plan.solve(y, s, m, out=out)
+        torch.cuda.synchronize()
+        ms_solve = time_solve(plan, fmap, y, s, m, out, args.steps, torch)
+        ev0.record(stream)
+        plan.iterate(vol.niter, out=out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_loop = ev0.elapsed_time(ev1)
+        n = plan.mask_count()
+    b = alg_bytes_per_voxel(args.precision, vol.necho, vol.nmls) * n
+    res = {"grid": list(vol.shape), "voxels": n, "mask_fraction": n / float(vol.mask.size), "schedule": sched,
+           "ms_per_step": ms_solve, "value": n * vol.niter / (ms_solve * 1e-3), "loop_ms": ms_loop,
+           "loop_voxel_iterations_per_s": n * vol.niter / (ms_loop * 1e-3),
+           "hbm_frac": b / (ms_loop * 1e-3 / vol.niter) / (HBM_PEAK_GBS * 1e9)}
+    log("paper mask: %d unknowns (%.1f%%), %s schedule, step %.3f ms (%.3e voxel-iterations/s), loop %.3f ms, "
+        "%.1f%% of HBM peak" % (n, 100 * res["mask_fraction"], sched, ms_solve, res["value"], ms_loop,
+                                100 * res["hbm_frac"]))
     return res
 
 
@@ -533,9 +566,10 @@ def main():
     ap.add_argument("--precond", choices=["ic0", "diag", "none"], default="ic0")
     ap.add_argument("--mask", choices=["full", "paper"], default="full")
     ap.add_argument("--shape", default="128,128,64")
-    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2", "large"], default="fieldmap",
+    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2", "large", "copy"],
+                    default="fieldmap",
                     help="fieldmap: the headline line (default); batched / waterfat / order2 / large: only that "
-                         "workload")
+                         "workload; copy: a plain 1 GiB device copy (the calibration of the traffic counters)")
     ap.add_argument("--kernel-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-natural", action="store_true", help="skip the natural-order comparison line")
@@ -544,6 +578,7 @@ def main():
     ap.add_argument("--no-waterfat", action="store_true", help="skip the 192x192x64 water-fat solve")
     ap.add_argument("--no-large", action="store_true", help="skip the 256x256x128 HBM-sized field-map loop")
     ap.add_argument("--no-order2", action="store_true", help="skip the second-order regulariser solves")
+    ap.add_argument("--no-paper-mask", action="store_true", help="skip the headline problem on the paper-rule mask")
     ap.add_argument("--no-convergence", action="store_true",
                     help="skip the time-to-accuracy comparison of the preconditioners")
     args = ap.parse_args()
@@ -559,6 +594,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "copy":
+        gbs = copy_rate_gbs(torch, 1024, max(1, args.steps))
+        print(json.dumps({"metric": "device copy rate (read + write)", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup, "ms_per_step": 2 * 1024 * 1048576 / gbs / 1e6,
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                          "data": "synthetic", "config": {"workload": "copy of 1 GiB (1073741824 bytes)"}}),
+              flush=True)
+        return
     if args.workload != "fieldmap":
         prec = fmap.MIX if args.precision == "mix" else fmap.F64
         if args.workload == "batched":
@@ -718,6 +761,10 @@ def main():
     if not args.no_order2 and args.shape == "128,128,64" and args.mask == "full":
         order2 = bench_order2(args, fmap, synth, torch, prec)
 
+    paper_mask = None
+    if not args.no_paper_mask and args.shape == "128,128,64" and args.mask == "full":
+        paper_mask = bench_paper_mask(args, fmap, synth, torch, prec)
+
     copy_gbs = copy_rate_gbs(torch)
     log("device copy of 1 GB: %.0f GB/s (read + write)" % copy_gbs)
 
@@ -770,6 +817,7 @@ def main():
         "natural_order": natural,
         "large_256x256x128": large,
         "second_order": order2,
+        "paper_mask": paper_mask,
         "convergence": convergence,
         "adjoint": adjoint,
         "batched": batched,
