@@ -563,8 +563,6 @@ fm_status validate(const fm_params *p) {
     return fail(FM_ERR_ARG, "bad ordering");
   if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_ICT) return fail(FM_ERR_ARG, "bad preconditioner");
   if (p->reg_order < 0 || p->reg_order > 2) return fail(FM_ERR_ARG, "reg_order must be 1 or 2");
-  if (p->reg_order == 2 && p->model != FM_FIELDMAP)
-    return fail(FM_ERR_ARG, "second-order differences are built for the field-map model only");
   if (p->reg_order == 2 && p->precond == FM_PRECOND_IC0 && p->ordering != FM_ORDER_COLOR3)
     return fail(FM_ERR_ARG, "IC(0) with second-order differences is built in three-colour order (FM_ORDER_COLOR3)");
   if (p->ordering == FM_ORDER_COLOR3 && (p->reg_order != 2 || p->precond != FM_PRECOND_IC0))

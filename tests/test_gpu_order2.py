@@ -322,8 +322,8 @@ def test_what_is_not_built_is_refused():
     with pytest.raises(fmap.FmapError):
         fmap.Batch([p, p])
     wf = fmap.make_params((8, 8, 8), 1, 1e-3 * (1.2 + np.arange(6)), 0.1, model=fmap.WATERFAT,
-                          fat_hz=[-434.0, -332.0], fat_amp=[0.7, 0.3], precond=fmap.DIAG, reg_order=2)
-    with pytest.raises(fmap.FmapError):
+                          fat_hz=[-434.0, -332.0], fat_amp=[0.7, 0.3], precond=fmap.IC0, reg_order=2)
+    with pytest.raises(fmap.FmapError):  # water-fat too: IC(0) of the second-order C in three-colour order
         fmap.Plan(wf)
     bad = fmap.params_for(vol, precision=fmap.F64, precond=fmap.DIAG)
     bad.reg_order = 3
@@ -334,3 +334,66 @@ def test_what_is_not_built_is_refused():
         f = plan.solve(y, s, m)
         with pytest.raises(fmap.FmapError):
             plan.adjoint(2.0 * f * m)
+
+
+def wf2_volume(shape=(24, 20, 8), seed=77, niter=20):
+    vol = synth.waterfat_volume(shape, 3, 1.2e-3 + 1e-3 * np.arange(6), 2.0 ** -4, niter, synth.SEED_BASE + seed,
+                                150.0, 40.0, name="water-fat %s second order" % (shape,))
+    vol.reg_order = 2
+    return vol
+
+
+@pytest.mark.parametrize("precond", ["ic0", "diag"])
+@pytest.mark.parametrize("prec", ["f64", "mix"])
+def test_waterfat_second_order_matches_oracle(prec, precond):
+    """Water-fat with second-order differences (Sec. IV-C's regulariser): the sweep + PWLS start with the
+    second-order C^T C, then the iteration, against fmo_solve; IC(0) in three-colour order or diag(H)."""
+    vol = wf2_volume()
+    P = fmap.F64 if prec == "f64" else fmap.MIX
+    order, pc = (fmap.COLOR3, fmap.IC0) if precond == "ic0" else (fmap.NATURAL, fmap.DIAG)
+    oorder, opc = (O.COLOR3, O.IC0) if precond == "ic0" else (O.NATURAL, O.DIAG)
+    say("water-fat second order %s %s" % (prec, precond))
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=P, ordering=order, precond=pc)) as plan:
+        plan.setup(y, s, m)
+        f0 = plan.init().cpu().numpy()
+        f = plan.solve(y, s, m).cpu().numpy()
+        tr = plan.trace()
+    ref = O.run_volume(vol, ordering=oorder, precond=opc)
+    msk = vol.mask.astype(bool)
+    e0 = rms(f0 - ref["f0"], msk)
+    err = rms(f - ref["f"], msk)
+    say("  initial map rms %.3e Hz; solve rms vs oracle %.3e Hz, max %.3e Hz" % (e0, err,
+                                                                               np.abs(f - ref["f"])[msk].max()))
+    assert e0 < 1e-6
+    assert np.all(f[~msk] == 0)
+    if prec == "f64":
+        assert err < 1e-3
+        np.testing.assert_array_equal(tr[:-1, 3], ref["trace"][:-1, O.TR["restart"]])
+        np.testing.assert_allclose(tr[:, 0], ref["trace"][:, O.TR["cost"]], rtol=1e-9)
+    else:
+        assert err < 0.05
+        f64 = fmap.solve_volume(vol, precision=fmap.F64, ordering=order, precond=pc)[0]
+        assert rms(f - f64, msk) < 0.01
+
+
+def test_waterfat_second_order_start_on_a_crop_of_the_full_size_case():
+    """The 192x192x64, 8-coil, 6-echo water-fat data with second-order differences: the sweep + PWLS start
+    (ten CG iterations on 2 diag(rho) + beta C^T C of second differences) on a crop, against the oracle."""
+    vol = synth.waterfat()
+    sl = (slice(88, 104), slice(88, 104), slice(28, 36))
+    crop = synth.Volume(y=vol.y[(slice(None), slice(None)) + sl], sens=vol.sens[(slice(None),) + sl],
+                        te=vol.te, mask=vol.mask[sl], f_true=None, beta=vol.beta, niter=1, model="waterfat",
+                        fat_hz=vol.fat_hz, fat_amp=vol.fat_amp)
+    crop.reg_order = 2
+    say("water-fat second-order start on a crop %s" % (crop.shape,))
+    yc, sc, mc = fmap.to_device(crop)
+    with fmap.Plan(fmap.params_for(crop, precision=fmap.F64, niter=1, precond=fmap.DIAG)) as plan:
+        plan.setup(yc, sc, mc)
+        got = plan.init().cpu().numpy()
+    pbc = O.problem_for(crop)
+    assert pbc.reg_order == 2
+    ref0 = O.initial_map(crop, pbc, O.combine(crop.y, crop.sens))
+    e = rms(got - ref0, crop.mask.astype(bool))
+    say("  rms vs oracle %.3e Hz" % e)
+    assert e < 1e-6
