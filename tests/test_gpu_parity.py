@@ -49,6 +49,14 @@ def rms(a, m):
     return float(np.sqrt(np.mean(a[m] ** 2))) if m.any() else 0.0
 
 
+def flips(a, m, te):
+    """Voxels whose difference exceeds half the phase-wrap period of the closest echo pair,
+    1/(2 min |t_m - t_n|): they sit in another local minimum."""
+    te = np.asarray(te, dtype=np.float64)
+    dt = min(abs(te[i] - te[k]) for i in range(len(te)) for k in range(i + 1, len(te)))
+    return int(np.count_nonzero(np.abs(a[m]) > 1.0 / (2.0 * dt)))
+
+
 @pytest.mark.parametrize("prec", ["f64", "mix"])
 @pytest.mark.parametrize("vname", list(VOLUMES))
 def test_setup_and_init_match_oracle(vname, prec):
@@ -120,8 +128,10 @@ def test_solve_matches_oracle(vname, prec, ordering):
     ref = O.run_volume(vol, ordering=order)
     msk = vol.mask.astype(bool)
     err = rms(f - ref["f"], msk)
-    say("  rms vs oracle %.3e Hz, max %.3e Hz" % (err, np.abs(f - ref["f"])[msk].max()))
+    nflip = flips(f - ref["f"], msk, vol.te)
+    say("  rms vs oracle %.3e Hz, max %.3e Hz, basin flips %d" % (err, np.abs(f - ref["f"])[msk].max(), nflip))
     assert np.all(f[~msk] == 0)
+    assert nflip == 0
     rt = ref["trace"]
     if prec == "f64":
         assert err < 1e-3
@@ -142,8 +152,9 @@ def test_mixed_precision_close_to_f64_on_gpu(ordering):
     f64, _ = fmap.solve_volume(vol, precision=fmap.F64, ordering=order)
     fmx, _ = fmap.solve_volume(vol, precision=fmap.MIX, ordering=order)
     d = rms(fmx - f64, vol.mask.astype(bool))
-    say("  mix vs f64 rms %.3e Hz" % d)
+    say("  mix vs f64 rms %.3e Hz, max %.3e Hz" % (d, np.abs(fmx - f64)[vol.mask.astype(bool)].max()))
     assert d <= 0.01
+    assert flips(fmx - f64, vol.mask.astype(bool), vol.te) == 0
 
 
 @pytest.mark.parametrize("precond", ["diag", "none"])
