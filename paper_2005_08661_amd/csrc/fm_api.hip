@@ -22,6 +22,7 @@
 #include "fm_resident.hpp"
 #include "fm_order2.hpp"
 #include "fm_ict.hpp"
+#include "fm_tile.hpp"
 
 using fm::kBlock;
 using fm::kMaxGrid;
@@ -424,6 +425,35 @@ bool fused_red_dir(const fm_plan *p) {
 // Values per partial block left by the last pass of an iteration.
 int tail_nvals(const fm_plan *p) { return p->prm.nmls > 1 ? 2 : 3; }
 
+#ifndef FM_TILE_XCMIN
+#define FM_TILE_XCMIN 4
+#endif
+
+// Plane-march shape of the tiled red-black passes: strips of ty columns (all
+// pair slots of a workgroup on one plane), runs of at least FM_TILE_XCMIN
+// planes, lengthened until the grid fits the partial-sum rows.  grid 0 where
+// the tile does not apply (odd or long columns).
+fm::TileShape tile_shape(const fm::Geo &g) {
+  fm::TileShape t{};
+  if (g.nz % 2 != 0 || g.nz > fm::kTileMaxNz) return t;
+  const int nzp = g.nz / 2;
+  t.ty = std::min(fm::kTileSlots / nzp, g.ny);
+  t.nyt = (g.ny + t.ty - 1) / t.ty;
+  if (t.nyt > kMaxGrid) return fm::TileShape{};
+  t.xc = std::max<int>(FM_TILE_XCMIN, (int)(((int64_t)t.nyt * g.nx + kMaxGrid - 1) / kMaxGrid));
+  while ((int64_t)t.nyt * ((g.nx + t.xc - 1) / t.xc) > kMaxGrid) ++t.xc;
+  t.grid = t.nyt * ((g.nx + t.xc - 1) / t.xc);
+  return t;
+}
+
+// Workgroups (hence partial sums) of the last pass of an iteration: a line-search
+// pass, or the direction step's last pass (tiled or not) when there is none.
+int tail_nparts(const fm_plan *p) {
+  if (p->prm.nmls > 1) return p->sgrid;
+  const fm::TileShape ts = fused_red_dir(p) ? tile_shape(p->geo) : fm::TileShape{};
+  return ts.grid > 0 ? ts.grid : p->sgrid;
+}
+
 // One NCG iteration: gradient, preconditioner (+ dots), direction, and the
 // remaining line-search passes; the last pass is consumed by the next
 // iteration's gradient pass (or by the final pass).
@@ -436,7 +466,17 @@ fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) 
   }
   FM_LAUNCH_CHECK();
   set_parts(p, p->sgrid, 4);
-  if (fused_red_dir(p) && p->geo.nz % 2 == 0) {
+  const fm::TileShape ts = fused_red_dir(p) ? tile_shape(p->geo) : fm::TileShape{};
+  int dir_parts = p->sgrid;  // workgroups of the pass that ends the direction step
+  if (ts.grid > 0) {
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black_tile<T>), dim3(ts.grid), dim3(fm::kNT), s, iter_args<T>(p, p->q++), ts);
+    FM_LAUNCH_CHECK();
+    set_parts(p, ts.grid, 2);
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_rb_red_dir_tile<T>), dim3(ts.grid), dim3(fm::kNT), s, iter_args<T>(p, p->q++),
+              ts);
+    FM_LAUNCH_CHECK();
+    dir_parts = ts.grid;
+  } else if (fused_red_dir(p) && p->geo.nz % 2 == 0) {
     FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black_pair<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
     FM_LAUNCH_CHECK();
     set_parts(p, p->sgrid, 2);
@@ -465,7 +505,7 @@ fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) 
     }
     FM_LAUNCH_CHECK();
   }
-  set_parts(p, p->sgrid, 3);
+  set_parts(p, dir_parts, 3);
   for (int k = 1; k < p->prm.nmls; ++k) {
     FM_LAUNCH(FM_K_MLS, (fm::k_mls<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
     FM_LAUNCH_CHECK();
@@ -790,7 +830,7 @@ fm_status run_graph(fm_plan *p, int niter, hipStream_t s) {
   } else {
     p->q += launches_per_iteration(p) * (uint64_t)niter;
     p->iter_host += niter;
-    set_parts(p, p->sgrid, tail_nvals(p));  // the last pass of an iteration is a streaming pass
+    set_parts(p, tail_nparts(p), tail_nvals(p));
   }
   FM_HIP(hipGraphLaunch(it->second.second, s));
   return FM_OK;
