@@ -172,7 +172,10 @@ __device__ __forceinline__ bool res_nbwait(uint32_t *flags, const ResTile &t, in
 // first, then the waves' sums in wave order); the totals go to thread 0 only
 // (the one that publishes or applies them).  Thread k sums value k over the
 // waves, so no thread holds more than the K totals (block_sum's every-thread
-// loop over K x waves would).
+// loop over K x waves would).  No barrier before the wave sums are written:
+// every call is separated from the one before it by at least one
+// __syncthreads (a pass, a grid barrier or a neighbour wait lies between), so
+// they cannot overwrite sums the previous call is still reading.
 template <int K>
 __device__ __forceinline__ void res_block_sum(double (&v)[K]) {
   constexpr int NW = kResNT / kWave;
@@ -180,7 +183,6 @@ __device__ __forceinline__ void res_block_sum(double (&v)[K]) {
   __shared__ double tot[K];
   wave_reduce<K>(v);
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  __syncthreads();
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) red[k][wid] = v[k];
@@ -344,8 +346,9 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
   int mslot = 0;   // alternating line-search slot
   uint32_t *flags = a.bar + kResBarHead;
 
-  // sum all workgroups' K partials of a slot (fixed order, identical everywhere)
-  auto take = [&](auto &t, int slot) {
+  // sum all workgroups' K partials of slot s0 (values 0 .. K0-1) and of slot
+  // s1 (the rest) in one block sum (fixed order, identical everywhere)
+  auto take = [&](auto &t, int s0, int k0, int s1) {
     constexpr int K = sizeof(t) / sizeof(double);
 #pragma unroll
     for (int k = 0; k < K; ++k) t[k] = 0.0;
@@ -355,7 +358,8 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
       // and would wait for each one before issuing the next
       double x[K];
 #pragma unroll
-      for (int k = 0; k < K; ++k) x[k] = ld_coh(a.part + ((size_t)slot * kMaxK + k) * nb + b);
+      for (int k = 0; k < K; ++k)
+        x[k] = ld_coh(a.part + ((size_t)(k < k0 ? s0 : s1) * kMaxK + (k < k0 ? k : k - k0)) * nb + b);
 #pragma unroll
       for (int k = 0; k < K; ++k) t[k] += x[k];
     }
@@ -378,13 +382,20 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
     res_put<K>(acc, a.part, slot);
     if (!res_barrier(a.bar, a.status, ++e)) return false;
     if (with_grad) {
-      double tg[4];
-      take(tg, kSlotG);
+      double tt[4 + K];
+      take(tt, kSlotG, 4, slot);
+      double tg[4], t[K];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) tg[k] = tt[k];
+#pragma unroll
+      for (int k = 0; k < K; ++k) t[k] = tt[4 + k];
       apply(tg, PK_GRAD);
+      apply(t, kind);
+    } else {
+      double t[K];
+      take(t, slot, K, slot);
+      apply(t, kind);
     }
-    double t[K];
-    take(t, slot);
-    apply(t, kind);
     __syncthreads();
     return true;
   };
