@@ -874,4 +874,210 @@ __global__ __launch_bounds__(kNT) void k_mls(IterArgs<T> a0) {
   put_state(st, a.sout, PK_MLS, vw.nb, vw.leader);
 }
 
+// Mark loaded values as used where they were loaded: the compiler would
+// otherwise sink a load whose value a masked voxel does not need into that
+// voxel's branch, issuing it late and waiting for it alone.
+__device__ __forceinline__ void keep(float4 v) { asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w)); }
+__device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
+__device__ __forceinline__ void keep(uint32_t v) { asm volatile("" ::"v"(v)); }
+
+// The line-search pass of k_mls with four consecutive voxels per thread
+// (FP32, NE = L echoes fixed at compile time so that no load is conditional,
+// n a multiple of 4): the codes in one 4-byte load, f, z and each echo's data
+// in 16-byte loads, so a wave's load moves 1 KiB of one array (k_mls's
+// per-voxel loads move 256 B, and 64 B for the codes).  Same arithmetic per
+// voxel; only the order of the partial sums differs.
+template <int NE>
+__global__ __launch_bounds__(kNT) void k_mls_q(IterArgs<float> a0) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<float> a = at_volume<false>(a0, vw);
+  const int nq = (int)(a.geo.n >> 2), stride = vw.nb * kNT;
+  const int64_t es = a.geo.n;
+  uint32_t c4;
+  float4 f4, z4, d4[NE][2];
+  auto load = [&](int q) {
+    const int j = 4 * q;
+    c4 = *reinterpret_cast<const uint32_t *>(a.code + j);
+    f4 = *reinterpret_cast<const float4 *>(a.Fc + j);
+    z4 = *reinterpret_cast<const float4 *>(a.Zc + j);
+#pragma unroll
+    for (int l = 0; l < NE; ++l) {
+      const float4 *d = reinterpret_cast<const float4 *>(a.dat + (size_t)l * (size_t)es + j);
+      d4[l][0] = d[0];
+      d4[l][1] = d[1];
+    }
+  };
+  int q = vw.bl * kNT + (int)threadIdx.x;
+  const State st = take_state<kNT, 3>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow,
+                                      vw.leader);
+  const float alpha = (float)st.alpha;
+  constexpr int NP = NE * (NE - 1) / 2;
+  PairC<float> pc[NP];  // the echo-pair constants, read once
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pc[k] = a.pairs[k];
+  double acc[2] = {0.0, 0.0};
+  for (; q < nq; q += stride) {
+    load(q);
+    keep(c4);
+    keep(f4);
+    keep(z4);
+#pragma unroll
+    for (int l = 0; l < NE; ++l) {
+      keep(d4[l][0]);
+      keep(d4[l][1]);
+    }
+    const float fv[4] = {f4.x, f4.y, f4.z, f4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const bool in = (c4 >> (8 * i)) & NB_SELF;
+      float rho[NE], tau[NE];
+#pragma unroll
+      for (int l = 0; l < NE; ++l) {
+        const float4 &d = d4[l][i >> 1];
+        rho[l] = (i & 1) ? d.z : d.x;
+        tau[l] = (i & 1) ? d.w : d.y;
+      }
+      float phi, dphi, curv;
+      voxel_terms<float, NE>(rho, tau, NE, pc, fv[i] + alpha * zv[i], phi, dphi, curv);
+      acc[0] += in ? (double)zv[i] * (double)dphi : 0.0;
+      acc[1] += in ? (double)zv[i] * (double)zv[i] * (double)curv : 0.0;
+    }
+  }
+  store_partials<2, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_MLS, vw.nb, vw.leader);
+}
+
+// The gradient pass of k_grad (iteration only: no final pass, no user
+// output) with four consecutive voxels of a column per thread (FP32, at most
+// four echoes, nz a multiple of 4): codes in one 4-byte load; f, z, the echo
+// data and the +-x, +-y neighbours' f and z in 16-byte loads; the -z / +z
+// neighbours inside the four from registers; f, g, D stored 16 bytes at a time
+// (NE = L echoes fixed at compile time, as k_mls_q).  Every neighbour's updated
+// f is formed with the expression k_grad uses, so f, g, D and 1/h are the same
+// bits; only the order of the partial sums differs.
+template <int NE>
+__global__ __launch_bounds__(kNT) void k_grad_q(IterArgs<float> a0) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<float> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const int nq = (int)(g.n >> 2), stride = vw.nb * kNT, sx = (int)g.sx, sy = (int)g.sy;
+  const int64_t es = g.n;
+  const float *__restrict__ fin = a.Fp;
+  const float *__restrict__ zin = a.Zp;
+  uint32_t c4;
+  float4 f4, z4, fx[2], zx[2], fy[2], zy[2], d4[NE][2];
+  float fzm, zzm, fzp, zzp;  // f, z of the voxels below and above the four
+  auto load = [&](int q) {
+    const int j = 4 * q;
+    c4 = *reinterpret_cast<const uint32_t *>(a.code + j);
+    f4 = *reinterpret_cast<const float4 *>(fin + j);
+    z4 = *reinterpret_cast<const float4 *>(zin + j);
+    fx[0] = *reinterpret_cast<const float4 *>(fin + j - sx);
+    fx[1] = *reinterpret_cast<const float4 *>(fin + j + sx);
+    zx[0] = *reinterpret_cast<const float4 *>(zin + j - sx);
+    zx[1] = *reinterpret_cast<const float4 *>(zin + j + sx);
+    fy[0] = *reinterpret_cast<const float4 *>(fin + j - sy);
+    fy[1] = *reinterpret_cast<const float4 *>(fin + j + sy);
+    zy[0] = *reinterpret_cast<const float4 *>(zin + j - sy);
+    zy[1] = *reinterpret_cast<const float4 *>(zin + j + sy);
+    fzm = fin[j - 1];
+    zzm = zin[j - 1];
+    fzp = fin[j + 4];
+    zzp = zin[j + 4];
+#pragma unroll
+    for (int l = 0; l < NE; ++l) {
+      const float4 *d = reinterpret_cast<const float4 *>(a.dat + (size_t)l * (size_t)es + j);
+      d4[l][0] = d[0];
+      d4[l][1] = d[1];
+    }
+  };
+  int q = vw.bl * kNT + (int)threadIdx.x;
+  const State st = take_state<kNT, 3>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow,
+                                      vw.leader);
+  const float alpha = (float)st.alpha;
+  const float beta = (float)a.beta;
+  constexpr int NP = NE * (NE - 1) / 2;
+  PairC<float> pc[NP];  // the echo-pair constants, read once
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pc[k] = a.pairs[k];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (; q < nq; q += stride) {
+    load(q);
+    keep(c4);
+    keep(f4);
+    keep(z4);
+#pragma unroll
+    for (int l = 0; l < NE; ++l) {
+      keep(d4[l][0]);
+      keep(d4[l][1]);
+    }
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      keep(fx[k]);
+      keep(zx[k]);
+      keep(fy[k]);
+      keep(zy[k]);
+    }
+    keep(fzm);
+    keep(zzm);
+    keep(fzp);
+    keep(zzp);
+    const int j = 4 * q;
+    const float fv[4] = {f4.x, f4.y, f4.z, f4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
+    const float fxm[4] = {fx[0].x, fx[0].y, fx[0].z, fx[0].w}, fxp[4] = {fx[1].x, fx[1].y, fx[1].z, fx[1].w};
+    const float zxm[4] = {zx[0].x, zx[0].y, zx[0].z, zx[0].w}, zxp[4] = {zx[1].x, zx[1].y, zx[1].z, zx[1].w};
+    const float fym[4] = {fy[0].x, fy[0].y, fy[0].z, fy[0].w}, fyp[4] = {fy[1].x, fy[1].y, fy[1].z, fy[1].w};
+    const float zym[4] = {zy[0].x, zy[0].y, zy[0].z, zy[0].w}, zyp[4] = {zy[1].x, zy[1].y, zy[1].z, zy[1].w};
+    float fo[4], go[4], dout[4];
+    double hv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t cv = (c4 >> (8 * i)) & 0xffu;
+      const bool in = cv & NB_SELF;
+      const float fj = fv[i] + alpha * zv[i];
+      const float fn[6] = {fxm[i] + alpha * zxm[i], fxp[i] + alpha * zxp[i], fym[i] + alpha * zym[i],
+                           fyp[i] + alpha * zyp[i], i > 0 ? fv[i - 1] + alpha * zv[i - 1] : fzm + alpha * zzm,
+                           i < 3 ? fv[i + 1] + alpha * zv[i + 1] : fzp + alpha * zzp};
+      float lap = 0.f;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (has_nb(cv, k)) lap += fj - fn[k];
+      float rho[NE], tau[NE];
+#pragma unroll
+      for (int l = 0; l < NE; ++l) {
+        const float4 &d = d4[l][i >> 1];
+        rho[l] = (i & 1) ? d.z : d.x;
+        tau[l] = (i & 1) ? d.w : d.y;
+      }
+      float phi, dphi, curv;
+      voxel_terms<float, NE>(rho, tau, NE, pc, fj, phi, dphi, curv);
+      const float gj = dphi + beta * lap;
+      fo[i] = in ? fj : 0.f;
+      go[i] = in ? gj : 0.f;
+      dout[i] = in ? curv : 0.f;
+      const double h = (double)curv + a.beta * nb_deg(cv);
+      hv[i] = in && h > 0.0 ? 1.0 / h : 0.0;
+      acc[0] += in ? (double)phi : 0.0;
+      acc[1] += in ? (double)fj * (double)lap : 0.0;
+      acc[2] += in ? (double)gj * (double)gj : 0.0;
+      acc[3] += in ? (double)zv[i] * (double)gj : 0.0;
+    }
+    *reinterpret_cast<float4 *>(a.Fc + j) = make_float4(fo[0], fo[1], fo[2], fo[3]);
+    *reinterpret_cast<float4 *>(a.Gc + j) = make_float4(go[0], go[1], go[2], go[3]);
+    *reinterpret_cast<float4 *>(a.D + j) = make_float4(dout[0], dout[1], dout[2], dout[3]);
+    if (a.write_hinv == 1) {
+      *reinterpret_cast<double2 *>(a.hinv + j) = make_double2(hv[0], hv[1]);
+      *reinterpret_cast<double2 *>(a.hinv + j + 2) = make_double2(hv[2], hv[3]);
+    } else if (a.write_hinv == 2) {
+      // 1/h of each pair's red voxel at the pair index (x + y + z even is red)
+      const int col = j / sy, x = col / g.ny, y = col - x * g.ny;
+      const bool first_red = ((x + y) & 1) == 0;  // the pair's first voxel (z even) is red
+      *reinterpret_cast<double2 *>(a.hinv + (j >> 1)) =
+          make_double2(first_red ? hv[0] : hv[1], first_red ? hv[2] : hv[3]);
+    }
+  }
+  store_partials<4, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_GRAD, vw.nb, vw.leader);
+}
+
 }  // namespace fm
