@@ -881,18 +881,32 @@ __device__ __forceinline__ void keep(float4 v) { asm volatile("" ::"v"(v.x), "v"
 __device__ __forceinline__ void keep(float v) { asm volatile("" ::"v"(v)); }
 __device__ __forceinline__ void keep(uint32_t v) { asm volatile("" ::"v"(v)); }
 
+// An echo-pair constant read by every lane alike, moved to scalar registers
+// (the vector registers are the scarce ones in the four-voxel passes).
+__device__ __forceinline__ float uniform_f(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ PairC<float> uniform_pair(const PairC<float> &p) {
+  PairC<float> q = p;
+  q.w = uniform_f(p.w);
+  q.g = uniform_f(p.g);
+  q.dt = uniform_f(p.dt);
+  q.d2pi = uniform_f(p.d2pi);
+  return q;
+}
+
 // The line-search pass of k_mls with four consecutive voxels per thread
 // (FP32, NE = L echoes fixed at compile time so that no load is conditional,
 // n a multiple of 4): the codes in one 4-byte load, f, z and each echo's data
 // in 16-byte loads, so a wave's load moves 1 KiB of one array (k_mls's
 // per-voxel loads move 256 B, and 64 B for the codes).  Same arithmetic per
 // voxel; only the order of the partial sums differs.
-template <int NE>
+template <int NE, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_mls_q(IterArgs<float> a0) {
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<float> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<float> a = at_volume<BATCH>(a0, vw);
   const int nq = (int)(a.geo.n >> 2), stride = vw.nb * kNT;
-  const int64_t es = a.geo.n;
+  const int64_t es = vw.es;
   uint32_t c4;
   float4 f4, z4, d4[NE][2];
   auto load = [&](int q) {
@@ -912,9 +926,9 @@ __global__ __launch_bounds__(kNT) void k_mls_q(IterArgs<float> a0) {
                                       vw.leader);
   const float alpha = (float)st.alpha;
   constexpr int NP = NE * (NE - 1) / 2;
-  PairC<float> pc[NP];  // the echo-pair constants, read once
+  PairC<float> pc[NP];  // the echo-pair constants, read once into scalar registers
 #pragma unroll
-  for (int k = 0; k < NP; ++k) pc[k] = a.pairs[k];
+  for (int k = 0; k < NP; ++k) pc[k] = uniform_pair(a.pairs[k]);
   double acc[2] = {0.0, 0.0};
   for (; q < nq; q += stride) {
     load(q);
@@ -955,13 +969,13 @@ __global__ __launch_bounds__(kNT) void k_mls_q(IterArgs<float> a0) {
 // (NE = L echoes fixed at compile time, as k_mls_q).  Every neighbour's updated
 // f is formed with the expression k_grad uses, so f, g, D and 1/h are the same
 // bits; only the order of the partial sums differs.
-template <int NE>
+template <int NE, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_grad_q(IterArgs<float> a0) {
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<float> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<float> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
   const int nq = (int)(g.n >> 2), stride = vw.nb * kNT, sx = (int)g.sx, sy = (int)g.sy;
-  const int64_t es = g.n;
+  const int64_t es = vw.es;
   const float *__restrict__ fin = a.Fp;
   const float *__restrict__ zin = a.Zp;
   uint32_t c4;
@@ -997,9 +1011,9 @@ __global__ __launch_bounds__(kNT) void k_grad_q(IterArgs<float> a0) {
   const float alpha = (float)st.alpha;
   const float beta = (float)a.beta;
   constexpr int NP = NE * (NE - 1) / 2;
-  PairC<float> pc[NP];  // the echo-pair constants, read once
+  PairC<float> pc[NP];  // the echo-pair constants, read once into scalar registers
 #pragma unroll
-  for (int k = 0; k < NP; ++k) pc[k] = a.pairs[k];
+  for (int k = 0; k < NP; ++k) pc[k] = uniform_pair(a.pairs[k]);
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (; q < nq; q += stride) {
     load(q);
