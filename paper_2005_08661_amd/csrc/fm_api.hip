@@ -483,10 +483,10 @@ fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) 
   const fm::TileShape ts = fused_red_dir(p) ? tile_shape(p->geo) : fm::TileShape{};
   int dir_parts = p->sgrid;  // workgroups of the pass that ends the direction step
   if (ts.grid > 0) {
-    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black_tile<T>), dim3(ts.grid), dim3(fm::kNT), s, iter_args<T>(p, p->q++), ts);
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_rb_black_tile<T, false>), dim3(ts.grid), dim3(fm::kNT), s, iter_args<T>(p, p->q++), ts);
     FM_LAUNCH_CHECK();
     set_parts(p, ts.grid, 2);
-    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_rb_red_dir_tile<T>), dim3(ts.grid), dim3(fm::kNT), s, iter_args<T>(p, p->q++),
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_rb_red_dir_tile<T, false>), dim3(ts.grid), dim3(fm::kNT), s, iter_args<T>(p, p->q++),
               ts);
     FM_LAUNCH_CHECK();
     dir_parts = ts.grid;

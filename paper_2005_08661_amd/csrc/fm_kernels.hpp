@@ -254,6 +254,7 @@ struct VolDesc {
   int64_t off;     // global index of the volume's voxel 0
   int32_t b0, nb;  // its workgroups [b0, b0 + nb) of a streaming launch
   double beta;
+  int32_t tty, txc, tnyt;  // plane-march tiles of the red-black passes: strip width, run length, strips
 };
 
 struct Batch {

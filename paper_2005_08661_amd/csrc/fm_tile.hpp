@@ -41,6 +41,9 @@ struct TileShape {
   int ty, xc, nyt, grid;
 };
 
+// The shape a batched volume's descriptor holds.
+__device__ __forceinline__ TileShape tile_of(const VolDesc &d) { return TileShape{d.tty, d.txc, d.tnyt, 0}; }
+
 // A workgroup's strip and run, and this thread's slots in them.
 struct TileSlots {
   int y0, x0, x1, nzp, ty;
@@ -56,27 +59,31 @@ struct TileSlots {
 // workgroup shares with its neighbours are then fetched into the same L2.
 constexpr int kXcds = 8;
 
-__device__ __forceinline__ TileSlots tile_slots(const Geo &g, const TileShape &ts) {
+// Workgroup bl of the nb a volume has (a batched launch may give a volume more
+// workgroups than its tiles: the surplus ones own no plane and only take part
+// in the partial sums).  The XCD remap applies where the volume's workgroups
+// start at a multiple of kXcds and come in multiples of it.
+__device__ __forceinline__ TileSlots tile_slots(const Geo &g, const TileShape &ts, int bl, int nb, int b0) {
   TileSlots t;
   t.nzp = g.nz >> 1;
   t.ty = ts.ty;
-  int bl = (int)blockIdx.x;
-  if ((int)gridDim.x % kXcds == 0) bl = (bl % kXcds) * ((int)gridDim.x / kXcds) + bl / kXcds;
+  if (nb % kXcds == 0 && b0 % kXcds == 0) bl = (bl % kXcds) * (nb / kXcds) + bl / kXcds;
   t.y0 = (bl % ts.nyt) * ts.ty;
   t.x0 = (bl / ts.nyt) * ts.xc;
-  t.x1 = t.x0 + ts.xc < g.nx ? t.x0 + ts.xc : g.nx;
+  const bool run = t.x0 < g.nx;
+  t.x1 = !run ? t.x0 : (t.x0 + ts.xc < g.nx ? t.x0 + ts.xc : g.nx);
 #pragma unroll
   for (int v = 0; v < kTilePPT; ++v) {
     const int s = (int)threadIdx.x + v * kNT;
     t.cy[v] = s / t.nzp;
     t.zq[v] = s - t.cy[v] * t.nzp;
-    t.ok[v] = t.cy[v] < t.ty && t.y0 + t.cy[v] < g.ny;
+    t.ok[v] = run && t.cy[v] < t.ty && t.y0 + t.cy[v] < g.ny;
   }
   const int side = (int)threadIdx.x / t.nzp;
   t.hz = (int)threadIdx.x - side * t.nzp;
   t.hs = side < 2;
   t.hy = side == 0 ? t.y0 - 1 : t.y0 + t.ty;
-  t.hok = t.hs && t.hy >= 0 && t.hy < g.ny;
+  t.hok = run && t.hs && t.hy >= 0 && t.hy < g.ny;
   t.he = (side == 0 ? 0 : t.ty + 1) * t.nzp + t.hz;
   return t;
 }
@@ -135,14 +142,14 @@ __device__ __forceinline__ TileBH<T> tile_b_halo(const VArgs<T> &a, const Geo &g
   return t;
 }
 
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_rb_black_tile(IterArgs<T> a0, TileShape ts) {
   __shared__ double lh[2][kTileLds];
   __shared__ T lg[2][kTileLds], lgp[2][kTileLds];
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<T> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const TileSlots t = tile_slots(g, ts);
+  const TileSlots t = tile_slots(g, BATCH ? tile_of(a0.bt.vol[vw.vol]) : ts, vw.bl, vw.nb, BATCH ? vw.pfirst : 0);
   const int nzp = t.nzp;
   TileB<T> q[kTileDepth + 1][kTilePPT];  // planes x .. x + kTileDepth
   TileBH<T> hq[kTileDepth + 1];
@@ -300,13 +307,13 @@ __device__ __forceinline__ TileRH<T> tile_r_halo(const VArgs<T> &a, const Geo &g
   return t;
 }
 
-template <typename T>
+template <typename T, bool BATCH>
 __global__ __launch_bounds__(kNT) void k_rb_red_dir_tile(IterArgs<T> a0, TileShape ts) {
   __shared__ T lp[2][kTileLds], lz[2][kTileLds], lf[2][kTileLds];
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<T> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
-  const TileSlots t = tile_slots(g, ts);
+  const TileSlots t = tile_slots(g, BATCH ? tile_of(a0.bt.vol[vw.vol]) : ts, vw.bl, vw.nb, BATCH ? vw.pfirst : 0);
   const int nzp = t.nzp;
   TileR<T> q[kTileDepth + 1][kTilePPT];  // planes x .. x + kTileDepth
   TileRH<T> hq[kTileDepth + 1];

@@ -155,3 +155,23 @@ def test_batch_sixteen_uneven_volumes_mix():
         m = vol.mask.astype(bool)
         assert rms(fb[v] - fs, m) < 0.01, v
         assert tb[v][-1, 0] == pytest.approx(ts[-1, 0], rel=1e-5)
+
+
+def test_batch_tiles_partition_sizes_agree():
+    """Even columns: the batched red-black passes march planes in tiles fitted to each volume's share
+    of the workgroups.  From one workgroup per volume (runs of whole volumes) to more workgroups than
+    tiles (the surplus ones only sum), shares that are multiples of 8 dealt by XCD, every partition
+    gives the oracle's map and the same map as the others."""
+    vols = uneven_volumes(((12, 9, 8), (20, 17, 10), (6, 5, 4), (24, 8, 16)))
+    say("batch tiles: partitions")
+    base, tb, _ = run_batch(vols, fmap.F64)
+    for v, vol in enumerate(vols):
+        m = vol.mask.astype(bool)
+        ref = O.run_volume(vol, O.REDBLACK, O.IC0)
+        assert rms(base[v] - ref["f"], m) < 1e-6, v
+        np.testing.assert_array_equal(tb[v][:-1, 3], ref["trace"][:-1, 3])
+    for g in (4, 32, 64, 100000):
+        got, _, used = run_batch(vols, fmap.F64, grid=g)
+        say("  grid %d: %d workgroups" % (g, used))
+        for v in range(len(vols)):
+            assert np.abs(got[v] - base[v]).max() < 1e-9, (g, v)
