@@ -156,6 +156,47 @@ __device__ __forceinline__ void voxel_terms(const T (&rho)[LMAX], const T (&tau)
   curv = c2;
 }
 
+// The same terms from per-pair values that do not change during a solve: the
+// weight w_q = 2|Gamma_mn| rho_m rho_n and the phase offset
+// xg_q = angle(Gamma_mn)/2pi + tau_n - tau_m (turns), formed once with the
+// expressions voxel_terms uses (pair_consts), so the results are the same bits.
+template <typename T, int L>
+__device__ __forceinline__ void pair_consts(const T (&rho)[L], const T (&tau)[L], const PairC<T> *__restrict__ pc,
+                                            T (&w)[L * (L - 1) / 2], T (&xg)[L * (L - 1) / 2]) {
+  int q = 0;
+#pragma unroll
+  for (int m = 0; m < L; ++m) {
+#pragma unroll
+    for (int n = m + 1; n < L; ++n, ++q) {
+      const PairC<T> P = pc[q];
+      w[q] = P.w * rho[m] * rho[n];
+      xg[q] = P.g + (tau[n] - tau[m]);
+    }
+  }
+}
+
+template <typename T, int NP>
+__device__ __forceinline__ void voxel_terms_pc(const T (&w)[NP], const T (&xg)[NP], const PairC<T> *__restrict__ pc,
+                                               T f, T &phi, T &dphi, T &curv) {
+  T c0 = 0, c1 = 0, c2 = 0;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const PairC<T> P = pc[q];
+    const T xi = xg[q] + f * P.dt;
+    const T x = T(3.14159265358979323846) * (xi - rint_t(xi));
+    T sx, c;
+    sinx_cos(x, sx, c);
+    const T s = x * sx;
+    const T wd = w[q] * P.d2pi;
+    c0 += w[q] * (T(2) * s * s);
+    c1 += wd * (T(2) * s * c);
+    c2 += wd * P.d2pi * (sx * c);
+  }
+  phi = c0;
+  dphi = c1;
+  curv = c2;
+}
+
 // ---------------------------------------------------------------------------
 // Deterministic FP64 reductions without atomics.  A kernel reduces its K
 // values per block and stores one partial per block; the next kernel in the

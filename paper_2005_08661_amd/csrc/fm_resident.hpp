@@ -133,15 +133,19 @@ __device__ __forceinline__ bool res_barrier(uint32_t *bar, int32_t *status, uint
   return ok_s != 0;
 }
 
-// Publish this tile's progress (all its coherent stores complete) and wait
-// until the face-neighbour tiles have reached the same count: lanes 0-3 of
-// the first wave poll the four neighbours' flags together.
-__device__ __forceinline__ bool res_nbwait(uint32_t *flags, const ResTile &t, int32_t *status, uint32_t count) {
+// Publish this tile's progress: all its coherent stores are complete when
+// thread 0 stores the count.
+__device__ __forceinline__ void res_publish(uint32_t *flags, uint32_t count) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flags + blockIdx.x, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wait until the face-neighbour tiles have published the count: lanes 0-3 of
+// the first wave poll the four neighbours' flags together.
+__device__ __forceinline__ bool res_nbwait(uint32_t *flags, const ResTile &t, int32_t *status, uint32_t count) {
   __shared__ int32_t okn_s;
   const int b = (int)blockIdx.x;
-  if (threadIdx.x == 0) __hip_atomic_store(flags + b, count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (threadIdx.x < kWave) {
     const int q = (int)threadIdx.x, bx = b / t.nty, by = b % t.nty;
     int nbq = -1;
@@ -270,7 +274,11 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
   // code | in-tile neighbour bits << 8 | (second voxel of the pair is black) << 16, echo data
   int jv[V];
   uint32_t cv[V];
-  float rho[V][LR], tau[V][LR];
+  // the echo data, or with at most three echoes (no more pairs than echoes) the
+  // per-pair weights and phase offsets, which do not change during the launch
+  constexpr bool PCN = NP <= LR;
+  constexpr int NE = PCN ? NP : LR;
+  float ea[V][NE], eb[V][NE];
   {
     const int odd = a.par0 & 1;
 #pragma unroll
@@ -292,11 +300,21 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
       lp[li] = 0.f;
       ld[li] = 0.f;
       lh[li] = 0.0;
+      float rho[LR], tau[LR];
 #pragma unroll
       for (int l = 0; l < LR; ++l) {
         const T2<float> d = valid ? a.dat[(size_t)l * (size_t)g.n + j] : T2<float>{0.f, 0.f};
-        rho[v][l] = d.x;
-        tau[v][l] = d.y;
+        rho[l] = d.x;
+        tau[l] = d.y;
+      }
+      if constexpr (PCN) {
+        pair_consts<float, LR>(rho, tau, a.pairs, ea[v], eb[v]);
+      } else {
+#pragma unroll
+        for (int l = 0; l < LR; ++l) {
+          ea[v][l] = rho[l];
+          eb[v][l] = tau[l];
+        }
       }
     }
   }
@@ -450,7 +468,10 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
             lap += fj[v] - fn;
           }
         float phi, dphi, curv;
-        voxel_terms<float, LR>(rho[v], tau[v], LR, lpc, fj[v], phi, dphi, curv);
+        if constexpr (PCN)
+          voxel_terms_pc<float, NP>(ea[v], eb[v], lpc, fj[v], phi, dphi, curv);
+        else
+          voxel_terms<float, LR>(ea[v], eb[v], LR, lpc, fj[v], phi, dphi, curv);
         const float gj = dphi + betaf * lap;
         const double h = (double)curv + beta * nb_deg(c);
         const double hi = h > 0.0 ? 1.0 / h : 0.0;
@@ -474,50 +495,37 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
         st_coh(a.hinv + (j0 >> 1), lh[lir]);
       }
       res_put<4>(acc, a.part, kSlotG);
-      if (!(live = res_nbwait(flags, a.tile, a.status, (uint32_t)it + 1))) break;
+      res_publish(flags, (uint32_t)it + 1);
     }
 
     // ---- black pass with both dot products (as k_rb_black_pair): per pair,
-    // the black voxel's pivot and p, the red voxel's terms of the dot products
+    // the black voxel's pivot and p, the red voxel's terms of the dot products.
+    // The red terms and the black voxels whose neighbours are all in the tile
+    // come first, while the face-neighbour tiles finish their gradient pass;
+    // then the wait for them, the halo loads and the black voxels on the faces.
     {
       const int tid = res_opaque(jv);
       double acc[2] = {0.0, 0.0};
-      float hgx[NPR], hpx[NPR], hgy[NPR], hpy[NPR];
-      double hhx[NPR], hhy[NPR];
+      bool bface[NPR];  // the black voxel has an in-mask x or y neighbour outside the tile
 #pragma unroll
       for (int q = 0; q < NPR; ++q) {
-        const bool sb = (cv[2 * q] >> 16) & 1u;
-        int jx, jy;
-        res_halo(sb ? cv[2 * q + 1] : cv[2 * q], sb ? jv[2 * q + 1] : jv[2 * q], jdflt, of, jx, jy);
-        // red neighbours across the faces: their pair's index
-        hgx[q] = ld_coh(Grc + (jx >> 1));
-        hpx[q] = ld_coh(Grp + (jx >> 1));
-        hhx[q] = ld_coh(a.hinv + (jx >> 1));
-        hgy[q] = ld_coh(Grc + (jy >> 1));
-        hpy[q] = ld_coh(Grp + (jy >> 1));
-        hhy[q] = ld_coh(a.hinv + (jy >> 1));
+        const uint32_t cb = ((cv[2 * q] >> 16) & 1u) ? cv[2 * q + 1] : cv[2 * q];
+        bface[q] = (((cb >> 1) & 15u) & ~((cb >> 8) & 15u)) != 0;
       }
-#pragma unroll
-      for (int q = 0; q < NPR; ++q) {
+      auto black = [&](int q, float hgx, float hpx, double hhx, float hgy, float hpy, double hhy) {
         const bool sb = (cv[2 * q] >> 16) & 1u;
-        const uint32_t cb = sb ? cv[2 * q + 1] : cv[2 * q], cr = sb ? cv[2 * q] : cv[2 * q + 1];
-        const int l0 = 2 * (q * kResNT + tid), lib = l0 + (sb ? 1 : 0), lir = l0 + (sb ? 0 : 1);
-        if (cr & NB_SELF) {
-          const float g0 = lgc[lir];
-          const double gh = (double)g0 * lh[lir];
-          acc[0] += (double)g0 * gh;
-          acc[1] += (double)lgp[lir] * gh;
-        }
-        if (!(cb & NB_SELF)) continue;
+        const uint32_t cb = sb ? cv[2 * q + 1] : cv[2 * q];
+        const int lib = 2 * (q * kResNT + tid) + (sb ? 1 : 0);
+        if (!(cb & NB_SELF)) return;
         const float g0 = lgc[lib], gp0 = lgp[lib];
         const double h = (double)ld[lib] + beta * nb_deg(cb);
         double sp = 0.0, sxv = 0.0, syp = 0.0;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
           const bool in = (cb >> (8 + k)) & 1u;
-          const double hn = res_nb(lh, lib, loff[k], in, k < 2 ? hhx[q] : hhy[q]);
-          const float gn = res_nb(lgc, lib, loff[k], in, k < 2 ? hgx[q] : hgy[q]);
-          const float gpn = res_nb(lgp, lib, loff[k], in, k < 2 ? hpx[q] : hpy[q]);
+          const double hn = res_nb(lh, lib, loff[k], in, k < 2 ? hhx : hhy);
+          const float gn = res_nb(lgc, lib, loff[k], in, k < 2 ? hgx : hgy);
+          const float gpn = res_nb(lgp, lib, loff[k], in, k < 2 ? hpx : hpy);
           const bool hk = has_nb(cb, k);
           sp += hk ? hn : 0.0;
           sxv += hk ? (double)gn * hn : 0.0;
@@ -534,7 +542,39 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
         lp[lib] = (float)xb;
         acc[0] += yb * xb;
         acc[1] += ((double)gp0 + beta * syp) * xb;
+      };
+#pragma unroll
+      for (int q = 0; q < NPR; ++q) {
+        const bool sb = (cv[2 * q] >> 16) & 1u;
+        const uint32_t cr = sb ? cv[2 * q] : cv[2 * q + 1];
+        const int lir = 2 * (q * kResNT + tid) + (sb ? 0 : 1);
+        if (cr & NB_SELF) {
+          const float g0 = lgc[lir];
+          const double gh = (double)g0 * lh[lir];
+          acc[0] += (double)g0 * gh;
+          acc[1] += (double)lgp[lir] * gh;
+        }
+        if (!bface[q]) black(q, 0.f, 0.f, 0.0, 0.f, 0.f, 0.0);  // every neighbour it uses is in the tile
       }
+      if (!(live = res_nbwait(flags, a.tile, a.status, (uint32_t)it + 1))) break;
+      float hgx[NPR], hpx[NPR], hgy[NPR], hpy[NPR];
+      double hhx[NPR], hhy[NPR];
+#pragma unroll
+      for (int q = 0; q < NPR; ++q) {
+        const bool sb = (cv[2 * q] >> 16) & 1u;
+        int jx, jy;
+        res_halo(sb ? cv[2 * q + 1] : cv[2 * q], sb ? jv[2 * q + 1] : jv[2 * q], jdflt, of, jx, jy);
+        // red neighbours across the faces: their pair's index
+        hgx[q] = ld_coh(Grc + (jx >> 1));
+        hpx[q] = ld_coh(Grp + (jx >> 1));
+        hhx[q] = ld_coh(a.hinv + (jx >> 1));
+        hgy[q] = ld_coh(Grc + (jy >> 1));
+        hpy[q] = ld_coh(Grp + (jy >> 1));
+        hhy[q] = ld_coh(a.hinv + (jy >> 1));
+      }
+#pragma unroll
+      for (int q = 0; q < NPR; ++q)
+        if (bface[q]) black(q, hgx[q], hpx[q], hhx[q], hgy[q], hpy[q], hhy[q]);
 #pragma unroll
       for (int q = 0; q < NPR; ++q) {
         if (!(facem >> q & 1u)) continue;
@@ -621,7 +661,10 @@ __global__ __launch_bounds__(kResNT, 4) void k_resident(ResArgs a) {
         const int li = 2 * ((v >> 1) * kResNT + tid) + (v & 1);
         const float z0 = lz[li];
         float phi, dphi, curv;
-        voxel_terms<float, LR>(rho[v], tau[v], LR, lpc, lf[li] + alpha * z0, phi, dphi, curv);
+        if constexpr (PCN)
+          voxel_terms_pc<float, NP>(ea[v], eb[v], lpc, lf[li] + alpha * z0, phi, dphi, curv);
+        else
+          voxel_terms<float, LR>(ea[v], eb[v], LR, lpc, lf[li] + alpha * z0, phi, dphi, curv);
         acc[0] += (double)z0 * (double)dphi;
         acc[1] += (double)z0 * (double)z0 * (double)curv;
       }
