@@ -151,15 +151,11 @@ __global__ __launch_bounds__(kBlock) void k_ict_fwd(IctArgs<T> a, const T *__res
   const Geo g = a.geo;
   const int n = (int)g.n;
   const int j = (x * g.ny + y) * g.nz + z;
+  // Every load of the voxel is issued before the mask test (a level is a
+  // chain of dependent memory round trips; the test must not add one).
   const uint32_t c = a.code[j];
-  if (!(c & NB_SELF)) {
-#pragma unroll
-    for (int u = 0; u < NO; ++u) a.lo[(size_t)u * n + j] = 0.0;
-    a.ld[j] = 0.0;
-    a.y[j] = 0.0;
-    return;
-  }
-  const double beta = a.beta, tol = a.factor * *a.hmax;
+  const double hmax = *a.hmax, dj = (double)a.D[j], gj = (double)gsrc[j];
+  const double beta = a.beta;
   // the earlier voxels k = j - o_u of the pattern (-1: outside the volume or
   // the mask), their L_kk, y_k and ||H(k:N, k)||_1 = |H_kk| + beta x (in-mask
   // neighbours after k), and the entries of their rows the products use
@@ -189,6 +185,14 @@ __global__ __launch_bounds__(kBlock) void k_ict_fwd(IctArgs<T> a, const T *__res
       lkm[u][v] = ok ? e : 0.0;
     }
   }
+  if (!(c & NB_SELF)) {
+#pragma unroll
+    for (int u = 0; u < NO; ++u) a.lo[(size_t)u * n + j] = 0.0;
+    a.ld[j] = 0.0;
+    a.y[j] = 0.0;
+    return;
+  }
+  const double tol = a.factor * hmax;
   double row[NO];
 #pragma unroll
   for (int u = 0; u < NO; ++u) {
@@ -203,12 +207,12 @@ __global__ __launch_bounds__(kBlock) void k_ict_fwd(IctArgs<T> a, const T *__res
     if (fabs(val) < tol * cn[u]) val = 0.0;
     row[u] = kv[u] >= 0 ? val : 0.0;
   }
-  double diag = (double)a.D[j] + beta * nb_deg(c);
+  double diag = dj + beta * nb_deg(c);
 #pragma unroll
   for (int u = 0; u < NO; ++u) diag = diag - row[u] * row[u];
   const bool bad = !(diag > 0.0);
   const double ljj = bad ? 0.0 : sqrt(diag);
-  double yv = (double)gsrc[j];
+  double yv = gj;
 #pragma unroll
   for (int u = 0; u < NO; ++u) yv = yv - row[u] * yk[u];
 #pragma unroll
@@ -230,11 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_ict_bwd(IctArgs<T> a, int s) {
   const Geo g = a.geo;
   const int n = (int)g.n;
   const int j = (x * g.ny + y) * g.nz + z;
-  if (!(a.code[j] & NB_SELF)) {
-    a.pd[j] = 0.0;
-    a.P[j] = T(0);
-    return;
-  }
+  const uint32_t c = a.code[j];  // loaded with the rest, tested after (as in the forward sweep)
+  const double yj = a.y[j], lj = a.ld[j];
   double li[NO], pi[NO];
 #pragma unroll
   for (int u = 0; u < NO; ++u) {
@@ -245,10 +246,15 @@ __global__ __launch_bounds__(kBlock) void k_ict_bwd(IctArgs<T> a, int s) {
     li[u] = ok ? e : 0.0;
     pi[u] = ok ? pv : 0.0;
   }
-  double sum = a.y[j];
+  if (!(c & NB_SELF)) {
+    a.pd[j] = 0.0;
+    a.P[j] = T(0);
+    return;
+  }
+  double sum = yj;
 #pragma unroll
   for (int u = NO - 1; u >= 0; --u) sum = sum - li[u] * pi[u];
-  const double p = sum / a.ld[j];
+  const double p = sum / lj;
   a.pd[j] = p;
   a.P[j] = (T)p;
 }
