@@ -210,8 +210,11 @@ std::vector<double> make_component_matrix(const fm_params &p, int *K) {
 template <typename T>
 using SetupKernel = void (*)(fm::SetupArgs<T>);
 template <typename T>
-SetupKernel<T> setup_kernel(int lmax, bool wf) {
+SetupKernel<T> setup_kernel(int lmax, bool wf, int necho) {
   if (wf) return lmax <= 4 ? fm::k_setup<T, 4, true> : (lmax <= 8 ? fm::k_setup<T, 8, true> : fm::k_setup<T, 16, true>);
+  // the field-map model with 2-4 echoes: the exact echo count, so no echo slot is loaded or summed for nothing
+  if (necho == 2) return fm::k_setup<T, 2, false>;
+  if (necho == 3) return fm::k_setup<T, 3, false>;
   return lmax <= 4 ? fm::k_setup<T, 4, false> : (lmax <= 8 ? fm::k_setup<T, 8, false> : fm::k_setup<T, 16, false>);
 }
 
@@ -1355,7 +1358,8 @@ fm_status setup_launch(fm_plan *p, const void *y, const void *sens, const uint8_
       a.ftilde = p->wf_tmp;
     }
     a.partials = p->setup_part;
-    hipLaunchKernelGGL(setup_kernel<T>(p->lmax, p->prm.model == FM_WATERFAT), dim3(p->grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(setup_kernel<T>(p->lmax, p->prm.model == FM_WATERFAT, p->prm.necho), dim3(p->grid),
+                       dim3(kBlock), 0, s, a);
     FM_LAUNCH_CHECK();
     hipLaunchKernelGGL(fm::k_count, dim3(1), dim3(kBlock), 0, s, (const double *)p->setup_part, p->grid, p->nmask);
     FM_LAUNCH_CHECK();

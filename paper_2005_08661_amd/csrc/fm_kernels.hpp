@@ -55,7 +55,7 @@ struct SetupArgs {
 // water-fat outputs (the sweep and the PWLS weights), so the field-map
 // instantiation carries none of their registers.
 template <typename T, int LMAX, bool WF>
-__global__ __launch_bounds__(kBlock) void k_setup(SetupArgs<T> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 3 ? 3 : 1))) void k_setup(SetupArgs<T> a) {
   const Geo g = a.geo;
   double cnt[1] = {0.0};
   for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < g.n; j += (int64_t)gridDim.x * kBlock) {
