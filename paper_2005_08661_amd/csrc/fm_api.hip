@@ -211,6 +211,7 @@ template <typename T>
 using SetupKernel = void (*)(fm::SetupArgs<T>);
 template <typename T>
 SetupKernel<T> setup_kernel(int lmax, bool wf, int necho) {
+  if (wf && necho == 6) return fm::k_setup<T, 6, true>;  // the water-fat echo count of the paper's experiments
   if (wf) return lmax <= 4 ? fm::k_setup<T, 4, true> : (lmax <= 8 ? fm::k_setup<T, 8, true> : fm::k_setup<T, 16, true>);
   // the field-map model with 2-4 echoes: the exact echo count, so no echo slot is loaded or summed for nothing
   if (necho == 2) return fm::k_setup<T, 2, false>;

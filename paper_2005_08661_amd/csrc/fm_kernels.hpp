@@ -135,22 +135,51 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(LMAX <= 
       // from the FP64 Taylor form of sinx_cos (|pi h| <= pi/2).
       double best = 1.0 / 0.0, bestf = 0.0;
       if (in) {
-        for (int q = 0; q < a.nsweep; ++q) {
-          const double fs = -a.sweep_half + 2.0 * a.sweep_half * q / (a.nsweep - 1);
-          double c0 = 0.0;
-          int pq = 0;
+        constexpr int NPM = LMAX * (LMAX - 1) / 2;
+        constexpr bool HOIST = LMAX <= 6;  // the per-voxel pair parts fit in registers
+        // the per-pair parts that do not depend on the sweep value, formed once
+        // with the expressions of the per-value form (same bits); slot k of the
+        // unrolled (m, n) loops, pair pq of the table (slots with n >= L skipped)
+        double pa[HOIST ? NPM : 1], pw[HOIST ? NPM : 1];
+        if constexpr (HOIST) {
+          int k = 0, pq = 0;
 #pragma unroll
           for (int m = 0; m < LMAX; ++m) {
 #pragma unroll
-            for (int n2 = m + 1; n2 < LMAX; ++n2) {
+            for (int n2 = m + 1; n2 < LMAX; ++n2, ++k) {
+              pa[k] = pw[k] = 0.0;
               if (n2 < a.L) {
                 const PairC<double> P = a.pairs_d[pq];
-                const double xi = P.g + (ph[n2] - ph[m]) + fs * P.dt;
+                pa[k] = P.g + (ph[n2] - ph[m]);
+                pw[k] = P.w * mag[m] * mag[n2];
+                ++pq;
+              }
+            }
+          }
+        }
+        for (int q = 0; q < a.nsweep; ++q) {
+          const double fs = -a.sweep_half + 2.0 * a.sweep_half * q / (a.nsweep - 1);
+          double c0 = 0.0;
+          int k = 0, pq = 0;
+#pragma unroll
+          for (int m = 0; m < LMAX; ++m) {
+#pragma unroll
+            for (int n2 = m + 1; n2 < LMAX; ++n2, ++k) {
+              if (n2 < a.L) {
+                const PairC<double> P = a.pairs_d[pq];
+                double xi, w;
+                if constexpr (HOIST) {
+                  xi = pa[k] + fs * P.dt;
+                  w = pw[k];
+                } else {
+                  xi = P.g + (ph[n2] - ph[m]) + fs * P.dt;
+                  w = P.w * mag[m] * mag[n2];
+                }
                 const double x = 3.14159265358979323846 * (xi - rint(xi));
                 double sx, cs;
                 sinx_cos(x, sx, cs);
                 const double sn = x * sx;
-                c0 += P.w * mag[m] * mag[n2] * (2.0 * sn * sn);
+                c0 += w * (2.0 * sn * sn);
                 ++pq;
               }
             }
