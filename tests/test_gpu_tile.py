@@ -116,3 +116,25 @@ def test_tile_single_line_search_pass_and_graph_replay():
             say("tile nmls=1 solve %d: max |f - oracle| %.3e Hz" % (rep, d))
             np.testing.assert_allclose(tr[:, 0], ref["trace"][:, O.TR["cost"]], rtol=1e-10)
             assert d < 1e-6
+
+
+def test_large_streaming_volume_against_oracle():
+    """256x256x128 (8.4 M voxels, the HBM-sized streaming workload of the bench, 2 coils): the tiled
+    red-black passes at their 1024-workgroup shape (dealt by XCD) and the four-voxel gradient and
+    line-search passes, 6 iterations in MIX against the oracle's run: RMS within the MIX bar, no basin
+    flips, restarts and cost trace as the oracle's."""
+    shape = (256, 256, 128)
+    vol = synth.fieldmap_volume(shape, 2, [0.0, 2.2e-3, 4.4e-3], 2.0 ** -4, 6, synth.SEED_BASE + 1, 8, 250.0,
+                                True, 30.0, mask="full", name="fieldmap 256x256x128 2 coils 3 echoes")
+    msk = vol.mask.astype(bool)
+    f, tr = stream_solve(vol, fmap.MIX)
+    ref = O.run_volume(vol, ordering=O.REDBLACK)
+    d = f - ref["f"]
+    err = float(np.sqrt(np.mean(d[msk] ** 2)))
+    nflip = int(np.count_nonzero(np.abs(d[msk]) > 1.0 / (2.0 * 2.2e-3)))
+    say("large 256x256x128 mix: rms vs oracle %.3e Hz, max %.3e Hz, %d basin flips" % (err, np.abs(d[msk]).max(),
+                                                                                         nflip))
+    assert nflip == 0
+    assert err < 0.05
+    np.testing.assert_array_equal(tr[:-1, 3], ref["trace"][:-1, O.TR["restart"]])
+    np.testing.assert_allclose(tr[:, 0], ref["trace"][:, O.TR["cost"]], rtol=1e-4)
