@@ -346,10 +346,10 @@ fm_status enqueue_ict(fm_plan *p, const T *g, hipStream_t s, Recorder *rec) {
             p->ict_hmax);
   FM_LAUNCH_CHECK();
   for (int lv = 0; lv < p->ict_nlev; ++lv)
-    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_ict_fwd<T, LEVEL>), dim3(p->ict_blocks), dim3(kBlock), s, a, g, lv);
+    FM_LAUNCH(FM_K_PRECOND_A, (fm::k_ict_fwd<T, LEVEL>), dim3(p->ict_blocks), dim3(fm::kIctNT), s, a, g, lv);
   FM_LAUNCH_CHECK();
   for (int lv = p->ict_nlev - 1; lv >= 0; --lv)
-    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_ict_bwd<T, LEVEL>), dim3(p->ict_blocks), dim3(kBlock), s, a, lv);
+    FM_LAUNCH(FM_K_PRECOND_B, (fm::k_ict_bwd<T, LEVEL>), dim3(p->ict_blocks), dim3(fm::kIctNT), s, a, lv);
   FM_LAUNCH_CHECK();
   return FM_OK;
 }
@@ -1227,7 +1227,7 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
     p->ict_noff = noff;
     p->ict_nlev = wa * (prm->nx - 1) + wb * (prm->ny - 1) + (prm->nz - 1) + 1;
     p->ict_kcol = (prm->nz - 1) / wb + 1;
-    p->ict_blocks = (int)(((int64_t)prm->nx * p->ict_kcol + kBlock - 1) / kBlock);
+    p->ict_blocks = (int)(((int64_t)prm->nx * p->ict_kcol + fm::kIctNT - 1) / fm::kIctNT);
     FM_ALLOC(p->ict_lo, sizeof(double) * n * (size_t)noff);
     FM_ALLOC(p->ict_ld, sizeof(double) * n);
     FM_ALLOC(p->ict_y, sizeof(double) * n);
