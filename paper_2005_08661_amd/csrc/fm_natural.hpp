@@ -26,7 +26,7 @@
 namespace fm {
 
 constexpr int kTile = 8;         // tile edge (8x8 columns = one wavefront)
-constexpr int kStepU = 4;        // steps per unrolled group / prefetch distance (8 and 16 measured slower)
+constexpr int kStepU = 4;        // steps per unrolled group / prefetch distance (2, 3, 6, 8 and 16 measured slower)
 constexpr int kSpinLimit = 1 << 16;  // polls per wait (each ~1 us): about 0.1 s
 
 struct Wavefront {
