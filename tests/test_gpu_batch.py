@@ -175,3 +175,39 @@ def test_batch_tiles_partition_sizes_agree():
         say("  grid %d: %d workgroups" % (g, used))
         for v in range(len(vols)):
             assert np.abs(got[v] - base[v]).max() < 1e-9, (g, v)
+
+
+def test_batch_sixteen_volumes_full_scale():
+    """The benchmarked batch (16 uneven volumes, 15.9 M unknowns, 100 iterations, MIX, red-black
+    IC(0), autotuned workgroup count as bench.py runs it): every volume within 0.01 Hz RMS of its
+    single-volume GPU F64 solve with no basin flips (differences above 1/(2 min |t_m - t_n|)), and
+    the two smallest volumes within 0.01 Hz RMS of the FP64 oracle's 100 iterations with the same
+    restart decisions."""
+    vols = synth.batched(16)
+    assert sum(v.mask.size for v in vols) == 15918592 and all(v.niter == 100 for v in vols)
+    say("16 volumes at full scale, 100 iterations: batched MIX (autotuned grid)")
+    fb, tb, info = run_batch(vols, fmap.MIX, autotune=True)
+    say("  grid %s" % (info,))
+    te = np.asarray(vols[0].te, dtype=np.float64)
+    thr = 1.0 / (2.0 * min(abs(te[a] - te[b]) for a in range(len(te)) for b in range(a + 1, len(te))))
+    worst = 0.0
+    for v, vol in enumerate(vols):
+        fs, _ = fmap.solve_volume(vol, fmap.F64, fmap.REDBLACK)
+        m = vol.mask.astype(bool)
+        d = np.abs(fb[v] - fs)[m]
+        e = float(np.sqrt(np.mean(d ** 2)))
+        worst = max(worst, e)
+        assert e <= 0.01, (v, e)
+        assert int(np.count_nonzero(d > thr)) == 0, v
+    say("  batched MIX vs single-volume F64: worst rms %.3e Hz" % worst)
+    small = sorted(range(len(vols)), key=lambda v: vols[v].mask.size)[:2]
+    for v in small:
+        vol = vols[v]
+        ref = O.run_volume(vol, O.REDBLACK, O.IC0)
+        m = vol.mask.astype(bool)
+        d = np.abs(fb[v] - ref["f"])[m]
+        say("  volume %d %s vs oracle: rms %.3e Hz, max %.3e Hz" % (v, vol.shape, float(np.sqrt(np.mean(d ** 2))),
+                                                                 float(d.max())))
+        assert float(np.sqrt(np.mean(d ** 2))) <= 0.01
+        assert int(np.count_nonzero(d > thr)) == 0
+        np.testing.assert_array_equal(tb[v][:-1, 3], ref["trace"][:-1, 3])
