@@ -115,8 +115,7 @@ typedef struct {
   int32_t reg_order;             /* C of eq. (cost): 1 (also when 0) first-order finite differences,
                                     2 second-order (rows f_{j-e} - 2 f_j + f_{j+e} with all three voxels
                                     in the volume and the mask); 2 needs, with IC(0), the three-colour
-                                    order (FM_ERR_ARG otherwise), and is not available to batches or
-                                    fm_adjoint */
+                                    order (FM_ERR_ARG otherwise), and is not available to batches */
   double ict_factor;             /* IC_t: drop tolerance = ict_factor x H_max (Sec. III-B uses 1e-3); >= 0,
                                     0 keeps every entry of the pattern */
   int32_t ict_level;             /* IC_t: fill bound, the level-of-fill pattern kept (0, 1 or 2) */
@@ -250,7 +249,9 @@ fm_status fm_components(fm_plan *plan, const void *y, const void *sens, const do
  * of the cost at the map (h_j from the cosines of the echo-pair terms, not
  * the Huber bound of Sec. III-B eq. (ls_huber)), it solves H v = dL/df by
  * conjugate gradients preconditioned as the iteration is (IC(0) of the Huber
- * model in the plan's ordering, its diagonal, or none), stopping once
+ * model in the plan's ordering, its diagonal, or none; with reg_order 2, C^T C
+ * the 13-point operator and the diagonal D + beta diag(C^T C) in place of
+ * IC(0): v does not depend on the preconditioner), stopping once
  * ||r|| <= rtol ||dL/df|| or after maxit iterations, and returns
  *   dL/dbeta = -v^T C^T C f                               (host float64)
  *   dL/dy_cl = -(s_c / sqrt(sum |s|^2)) v d g / d zhat_l  (dev complex64,

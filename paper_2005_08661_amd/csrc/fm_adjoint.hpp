@@ -19,9 +19,16 @@
 //                Im(Gamma_mn conj(zhat_m) zhat_n e^{i 2 pi dt_mn f_j}),
 //   dL/dy_cl   = (s_c / sqrt(sum_c |s_c|^2)) dL/dzhat_l  (zhat is linear in y),
 // complex gradients in the d/dRe + i d/dIm convention.
+//
+// With the second-order regulariser (R2) C^T C is the 13-point operator of
+// fm_order2.hpp in the Hessian products and in dL/dbeta, and CG is
+// preconditioned by diag(H) (the Huber curvature plus beta diag(C^T C)) or
+// not at all: the solution v does not depend on the preconditioner, only the
+// iteration count does.
 #pragma once
 
 #include "fm_stream.hpp"
+#include "fm_order2.hpp"
 
 namespace fm {
 
@@ -121,16 +128,16 @@ __global__ __launch_bounds__(kNT) void k_adj_setup(AdjArgs<T> a, const double *_
 }
 
 // Direction d = z + (rho / rho_prev) d_prev and the partial d^T H d.
-template <typename T>
+template <typename T, bool R2>
 __global__ __launch_bounds__(kNT) void k_adj_dir(AdjArgs<T> a) {
-  constexpr int V = Vpt<T>::v;
+  constexpr int V = R2 ? 1 : Vpt<T>::v, K2 = R2 ? 6 : 1;
   const Geo g = a.geo;
   const T *__restrict__ dp = a.Dd[(a.par + 1) & 1];
   T *__restrict__ dn = a.Dd[a.par & 1];
   const Offs of(g);
   const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
-  uint32_t c[V];
-  T z0[V], d0[V], h0[V], zn[V][6], dnb[V][6];
+  uint32_t c[V], cn[V][K2];
+  T z0[V], d0[V], h0[V], zn[V][6], dnb[V][6], zn2[V][K2], dnb2[V][K2];
   auto load = [&](int b) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -144,6 +151,14 @@ __global__ __launch_bounds__(kNT) void k_adj_dir(AdjArgs<T> a) {
       for (int k = 0; k < 6; ++k) {
         zn[v][k] = a.Zp[jj + of.o[k]];
         dnb[v][k] = dp[jj + of.o[k]];
+      }
+      if constexpr (R2) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          cn[v][k] = a.code[jj + of.o[k]];
+          zn2[v][k] = a.Zp[jj + 2 * of.o[k]];
+          dnb2[v][k] = dp[jj + 2 * of.o[k]];
+        }
       }
     }
   };
@@ -168,9 +183,19 @@ __global__ __launch_bounds__(kNT) void k_adj_dir(AdjArgs<T> a) {
         }
         const T dj = z0[v] + bcg * d0[v];
         T lap = T(0);
+        if constexpr (R2) {
+          T v1[6], v2[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-          if (has_nb(cv, k)) lap += dj - (zn[v][k] + bcg * dnb[v][k]);
+          for (int k = 0; k < 6; ++k) {
+            v1[k] = zn[v][k] + bcg * dnb[v][k];
+            v2[k] = zn2[v][k] + bcg * dnb2[v][k];
+          }
+          lap = ctc2(Rows2(cv, cn[v]), dj, v1, v2);
+        } else {
+#pragma unroll
+          for (int k = 0; k < 6; ++k)
+            if (has_nb(cv, k)) lap += dj - (zn[v][k] + bcg * dnb[v][k]);
+        }
         dn[j] = dj;
         const T qj = h0[v] * dj + beta * lap;
         acc[0] += (double)dj * (double)qj;
@@ -183,15 +208,15 @@ __global__ __launch_bounds__(kNT) void k_adj_dir(AdjArgs<T> a) {
 }
 
 // v += alpha d, r -= alpha H d; partial ||r||^2.
-template <typename T>
+template <typename T, bool R2>
 __global__ __launch_bounds__(kNT) void k_adj_update(AdjArgs<T> a) {
-  constexpr int V = Vpt<T>::v;
+  constexpr int V = R2 ? 1 : Vpt<T>::v, K2 = R2 ? 6 : 1;
   const Geo g = a.geo;
   const T *__restrict__ d = a.Dd[a.par & 1];
   const Offs of(g);
   const int n = (int)g.n, chunk = kNT * V, stride = (int)gridDim.x * chunk;
-  uint32_t c[V];
-  T d0[V], h0[V], v0[V], r0[V], dnb[V][6];
+  uint32_t c[V], cn[V][K2];
+  T d0[V], h0[V], v0[V], r0[V], dnb[V][6], dnb2[V][K2];
   auto load = [&](int b) {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -204,6 +229,13 @@ __global__ __launch_bounds__(kNT) void k_adj_update(AdjArgs<T> a) {
       r0[v] = a.R[jj];
 #pragma unroll
       for (int k = 0; k < 6; ++k) dnb[v][k] = d[jj + of.o[k]];
+      if constexpr (R2) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          cn[v][k] = a.code[jj + of.o[k]];
+          dnb2[v][k] = d[jj + 2 * of.o[k]];
+        }
+      }
     }
   };
   int base = (int)blockIdx.x * chunk;
@@ -222,9 +254,13 @@ __global__ __launch_bounds__(kNT) void k_adj_update(AdjArgs<T> a) {
         if (!(cv & NB_SELF)) continue;
         const T dj = d0[v];
         T lap = T(0);
+        if constexpr (R2) {
+          lap = ctc2(Rows2(cv, cn[v]), dj, dnb[v], dnb2[v]);
+        } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k)
-          if (has_nb(cv, k)) lap += dj - dnb[v][k];
+          for (int k = 0; k < 6; ++k)
+            if (has_nb(cv, k)) lap += dj - dnb[v][k];
+        }
         const T qj = h0[v] * dj + beta * lap;
         const T rj = r0[v] - alpha * qj;
         a.V[j] = v0[v] + alpha * dj;
@@ -240,7 +276,7 @@ __global__ __launch_bounds__(kNT) void k_adj_update(AdjArgs<T> a) {
 
 // Gradients from v: dL/dy (complex64, layout of y), v as float64, and the
 // partial v^T C^T C fhat for dL/dbeta.
-template <typename T, int LMAX>
+template <typename T, int LMAX, bool R2>
 __global__ __launch_bounds__(kNT) void k_adj_out(AdjArgs<T> a, const float2 *__restrict__ sens, int ncoil,
                                                  float2 *__restrict__ dldy, double *__restrict__ vout) {
   const Geo g = a.geo;
@@ -262,9 +298,21 @@ __global__ __launch_bounds__(kNT) void k_adj_out(AdjArgs<T> a, const float2 *__r
       const T fj = a.F[j];
       T lap = T(0);
       const int o[6] = {-(int)g.sx, (int)g.sx, -(int)g.sy, (int)g.sy, -1, 1};
+      if constexpr (R2) {
+        uint32_t cn[6];
+        T v1[6], v2[6];
 #pragma unroll
-      for (int k = 0; k < 6; ++k)
-        if (has_nb(c, k)) lap += fj - a.F[j + o[k]];
+        for (int k = 0; k < 6; ++k) {
+          cn[k] = a.code[j + o[k]];
+          v1[k] = a.F[j + o[k]];
+          v2[k] = a.F[j + 2 * o[k]];
+        }
+        lap = ctc2(Rows2(c, cn), fj, v1, v2);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+          if (has_nb(c, k)) lap += fj - a.F[j + o[k]];
+      }
       acc[0] += (double)vj * (double)lap;
       load_echoes<T, LMAX>(a.dat, (int64_t)n, j, a.L, rho, tau);
       int q = 0;

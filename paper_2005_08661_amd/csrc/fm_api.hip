@@ -982,7 +982,14 @@ template <typename T>
 fm_status adj_enqueue_iteration(fm_plan *p, uint64_t &q, int &np, int &nv, int k, hipStream_t s) {
   const T *r = (const T *)p->aR;
   Recorder *rec = nullptr;
-  if (p->prm.precond == FM_PRECOND_IC0) {
+  if (p->reg2) {
+    // second-order C: diag(H) with diag(C^T C) of the 13-point operator (also for IC(0) plans), or none
+    FM_LAUNCH(0, fm::k_diag2<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_precond_args<T>(p, q++, np, nv), r,
+              p->prm.precond == FM_PRECOND_NONE ? 1 : 0);
+    FM_LAUNCH_CHECK();
+    np = p->sgrid;
+    nv = 2;
+  } else if (p->prm.precond == FM_PRECOND_IC0) {
     if (p->prm.ordering == FM_ORDER_NATURAL) {
       FM_LAUNCH(0, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np, nv), p->wf, r);
       FM_LAUNCH_CHECK();
@@ -1009,11 +1016,17 @@ fm_status adj_enqueue_iteration(fm_plan *p, uint64_t &q, int &np, int &nv, int k
     np = p->sgrid;
     nv = 2;
   }
-  FM_LAUNCH(0, fm::k_adj_dir<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
+  if (p->reg2)
+    FM_LAUNCH(0, (fm::k_adj_dir<T, true>), dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
+  else
+    FM_LAUNCH(0, (fm::k_adj_dir<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
   FM_LAUNCH_CHECK();
   np = p->sgrid;
   nv = 1;
-  FM_LAUNCH(0, fm::k_adj_update<T>, dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
+  if (p->reg2)
+    FM_LAUNCH(0, (fm::k_adj_update<T, true>), dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
+  else
+    FM_LAUNCH(0, (fm::k_adj_update<T, false>), dim3(p->sgrid), dim3(fm::kNT), s, adj_args<T>(p, q++, k & 1, np, nv));
   FM_LAUNCH_CHECK();
   np = p->sgrid;
   nv = 1;
@@ -1063,8 +1076,12 @@ struct OpAdjoint {
       fm_status e = adj_finish(p, q, np, nv, &st, s);
       if (e) return e;
     }
-    hipLaunchKernelGGL((fm::k_adj_out<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), 0, s, adj_args<T>(p, q++, 0, np, nv),
-                       (const float2 *)sens, p->prm.ncoil, (float2 *)dldy, vout);
+    if (p->reg2)
+      hipLaunchKernelGGL((fm::k_adj_out<T, LMAX, true>), dim3(p->sgrid), dim3(fm::kNT), 0, s,
+                         adj_args<T>(p, q++, 0, np, nv), (const float2 *)sens, p->prm.ncoil, (float2 *)dldy, vout);
+    else
+      hipLaunchKernelGGL((fm::k_adj_out<T, LMAX, false>), dim3(p->sgrid), dim3(fm::kNT), 0, s,
+                         adj_args<T>(p, q++, 0, np, nv), (const float2 *)sens, p->prm.ncoil, (float2 *)dldy, vout);
     FM_LAUNCH_CHECK();
     np = p->sgrid;
     nv = 1;
@@ -1536,7 +1553,6 @@ fm_status fm_adjoint(fm_plan *p, const double *dldf, const void *sens, void *dld
   if (!sens && p->prm.ncoil != 1 && dldy) return fail(FM_ERR_ARG, "sens may be NULL only when ncoil == 1");
   if (maxit < 0 || !(rtol >= 0.0) || !std::isfinite(rtol)) return fail(FM_ERR_ARG, "maxit must be >= 0 and rtol finite, >= 0");
   if (!p->solved) return fail(FM_ERR_STATE, "fm_adjoint needs a converged map from fm_solve or fm_iterate");
-  if (p->reg2) return fail(FM_ERR_ARG, "fm_adjoint is built for the first-order regulariser only");
   if (p->ict) return fail(FM_ERR_ARG, "fm_adjoint preconditions with IC(0), the diagonal or nothing, not IC_t");
   fm_status st = adj_alloc(p);
   if (st) return st;
