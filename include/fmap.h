@@ -115,7 +115,8 @@ typedef struct {
   int32_t reg_order;             /* C of eq. (cost): 1 (also when 0) first-order finite differences,
                                     2 second-order (rows f_{j-e} - 2 f_j + f_{j+e} with all three voxels
                                     in the volume and the mask); 2 needs, with IC(0), the three-colour
-                                    order (FM_ERR_ARG otherwise), and is not available to batches */
+                                    order (FM_ERR_ARG otherwise); batches take it with the diagonal
+                                    preconditioner or none */
   double ict_factor;             /* IC_t: drop tolerance = ict_factor x H_max (Sec. III-B uses 1e-3); >= 0,
                                     0 keeps every entry of the pattern */
   int32_t ict_level;             /* IC_t: fill bound, the level-of-fill pattern kept (0, 1 or 2) */

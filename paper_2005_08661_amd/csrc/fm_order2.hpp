@@ -122,11 +122,11 @@ struct Cm {
 // +-2 neighbours of f and z and the neighbour codes; g and D go to their
 // colour-major elements in three-colour IC(0) plans (and D to its voxel-order
 // copy, which the direction pass reads).
-template <typename T, int LMAX>
+template <typename T, int LMAX, bool BATCH = false>
 __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
   constexpr int V = Vk<T, FM_V_GRAD2>::v;
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<T> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
   const T *__restrict__ fin = a.Fp;
   const T *__restrict__ zp = a.Zp;
@@ -213,11 +213,11 @@ __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
 
 // Diagonal (P = diag H with diag(C^T C) of the second-order operator) or
 // identity preconditioner (as k_diag).
-template <typename T>
+template <typename T, bool BATCH = false>
 __global__ __launch_bounds__(kNT) void k_diag2(IterArgs<T> a0, const T *__restrict__ gsrc, int identity) {
   constexpr int V = Vpt<T>::v;
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<T> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
   const T *__restrict__ gg = gsrc ? gsrc : a.Gc;
   const T *__restrict__ gp = a.Gp;
@@ -286,11 +286,11 @@ __global__ __launch_bounds__(kNT) void k_diag2(IterArgs<T> a0, const T *__restri
 // centre voxel) A = sum (Cz)(Cf) = z^T C^T C f and B = sum (Cz)^2; d0 = sum z^2 D.
 // In three-colour IC(0) plans p and D are the voxel-order copies that the
 // preconditioner and gradient passes write beside the colour-major arrays.
-template <typename T>
+template <typename T, bool BATCH = false>
 __global__ __launch_bounds__(kNT) void k_dir2(IterArgs<T> a0) {
   constexpr int V = Vk<T, FM_V_DIR2>::v;
-  const VolView vw = vol_view<false>(a0);
-  const VArgs<T> a = at_volume<false>(a0, vw);
+  const VolView vw = vol_view<BATCH>(a0);
+  const VArgs<T> a = at_volume<BATCH>(a0, vw);
   const Geo g = a.geo;
   const T *__restrict__ zp = a.Zp;
   T *__restrict__ zo = a.Zc;
