@@ -497,3 +497,35 @@ def test_batch_matches_oracle_and_single(prec, precond):
             np.testing.assert_array_equal(tb[v][:-1, 3], ref["trace"][:-1, O.TR["restart"]])
         else:
             assert e_or < 0.05 and e_s < 0.01
+
+
+@pytest.mark.parametrize("vname", sorted(EDGE))
+def test_adjoint_and_batch_degenerate_shapes(vname):
+    """The second-order adjoint and a batched solve on one z-line, one plane and a slab two voxels
+    thick (rows of C only along the axes with three voxels): adjoint against the oracle's within
+    1e-7 relative (F64, diagonal preconditioner), batch identical to the single-volume solve and
+    within 1e-3 Hz RMS of the oracle."""
+    vol = EDGE[vname]()
+    say("order-2 degenerate %s %s" % (vname, vol.shape))
+    rng = np.random.default_rng(41)
+    dldf = rng.standard_normal(vol.shape) * vol.mask
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, precond=fmap.DIAG, niter=400)) as plan:
+        f = plan.solve(y, s, m)
+        out = plan.adjoint(torch.from_numpy(dldf).cuda(), want_v=True, rtol=1e-12, maxit=5000)
+        torch.cuda.synchronize()
+    f = f.cpu().numpy()
+    pb = O.problem_for(vol, O.NATURAL, O.DIAG)
+    vo, dbo, dzo, _ = O.adjoint(pb, O.combine(vol.y, vol.sens), vol.mask, f, dldf, maxit=5000, rtol=1e-12)
+    assert rel(out["v"].cpu().numpy(), vo) < 1e-7
+    assert abs(out["dbeta"] - dbo) <= 1e-7 * max(abs(dbo), 1e-300)
+    vols = [vol, EDGE[vname]()]
+    prms = [fmap.params_for(v, precision=fmap.F64, precond=fmap.DIAG) for v in vols]
+    dev = [fmap.to_device(v) for v in vols]
+    with fmap.Batch(prms) as b:
+        fb = [o.cpu().numpy() for o in b.solve([d[0] for d in dev], [d[1] for d in dev], [d[2] for d in dev])]
+    fs, _ = fmap.solve_volume(vol, fmap.F64, fmap.NATURAL, precond=fmap.DIAG)
+    ref = O.run_volume(vol, O.NATURAL, O.DIAG)
+    msk = vol.mask.astype(bool)
+    assert rms(fb[0] - fs, msk) < 1e-9 and rms(fb[1] - fs, msk) < 1e-9
+    assert rms(fb[0] - ref["f"], msk) < 1e-3
