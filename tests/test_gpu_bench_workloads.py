@@ -1,0 +1,80 @@
+"""Parity of the workloads bench.py times beside the headline, at their sizes and in the launch
+configurations it times them in, against the FP64 oracle (Sec. III Algorithm):
+
+  - the headline problem on the paper-rule mask (reading R13: 350 896 unknowns of 128x128x64),
+    MIX, red-black IC(0), the plan's default schedule (resident), 100 iterations;
+  - natural-order IC(0) (the paper's own ordering; the pipelined wavefront sweeps) at
+    128x128x64, 8 coils, MIX, 100 iterations;
+  - second-order differences with IC(0) in three-colour order at 128x128x64, MIX, the first 5
+    iterations (the oracle's general IC(0) takes about 6 s per iteration at this size).
+
+Bars (those of the headline): <= 0.01 Hz RMS, no basin flips (differences above
+1/(2 min |t_m - t_n|)), identical restart decisions, cost trace to 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2005_08661_amd import fmap, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    torch.cuda.set_device(0)
+    fmap.lib()
+
+
+def check(vol, f, tr, ref, label):
+    m = vol.mask.astype(bool)
+    te = np.asarray(vol.te, dtype=np.float64)
+    thr = 1.0 / (2.0 * min(abs(te[a] - te[b]) for a in range(len(te)) for b in range(a + 1, len(te))))
+    d = (f - ref["f"])[m]
+    e, mx, nfl = float(np.sqrt(np.mean(d ** 2))), float(np.abs(d).max()), int(np.count_nonzero(np.abs(d) > thr))
+    nres = int(np.count_nonzero(tr[:-1, fmap.TRACE_COLS["restart"]] != ref["trace"][:-1, O.TR["restart"]]))
+    say("  %s: rms %.3e Hz, max %.3e Hz, flips %d, restart mismatches %d" % (label, e, mx, nfl, nres))
+    assert e <= 0.01 and nfl == 0 and nres == 0
+    np.testing.assert_allclose(tr[:, 0], ref["trace"][:, O.TR["cost"]], rtol=1e-6)
+
+
+def gpu_solve(vol, **kw):
+    y, s, m = fmap.to_device(vol)
+    with fmap.Plan(fmap.params_for(vol, precision=fmap.MIX, **kw)) as plan:
+        sched = plan.schedule()
+        f = plan.solve(y, s, m).cpu().numpy()
+        tr = plan.trace()
+    return f, tr, sched
+
+
+def test_paper_mask_headline_matches_oracle():
+    vol = synth.mid_fieldmap(mask="paper")
+    say("paper-rule mask 128x128x64: %d unknowns, MIX, 100 iterations" % int(vol.mask.sum()))
+    f, tr, sched = gpu_solve(vol, ordering=fmap.REDBLACK)
+    assert sched == fmap.SCHED_RESIDENT
+    ref = O.run_volume(vol, O.REDBLACK)
+    check(vol, f, tr, ref, "paper mask, resident, vs oracle")
+
+
+def test_natural_order_full_size_matches_oracle():
+    vol = synth.mid_fieldmap()
+    say("natural-order IC(0) 128x128x64, MIX, 100 iterations")
+    f, tr, _ = gpu_solve(vol, ordering=fmap.NATURAL)
+    ref = O.run_volume(vol, O.NATURAL)
+    check(vol, f, tr, ref, "natural order vs oracle")
+
+
+def test_second_order_full_size_first_iterations_match_oracle():
+    vol = synth.mid_fieldmap()
+    vol.reg_order = 2
+    say("second-order IC(0), three-colour order, 128x128x64, MIX, 5 iterations")
+    f, tr, _ = gpu_solve(vol, ordering=fmap.COLOR3, precond=fmap.IC0, niter=5)
+    ref = O.run_volume(vol, O.COLOR3, O.IC0, niter=5)
+    check(vol, f, tr, ref, "second order vs oracle")
