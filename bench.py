@@ -162,9 +162,9 @@ def host_threads():
 
 def bench_cpu(args, vol, synth, batched_vols, headline):
     """The FP64 oracle on the host (a -O3 -march=native copy compiled here), on 1 thread and on all threads:
-    config 2 (the headline volume) in full on all threads, which also gives the parity of the GPU maps, and a
-    20-iteration sample on 1 thread; config 1 (32x32x16, 1 coil, 50 iterations, natural-order IC(0)) in full on
-    both; config 4 (the 16 uneven volumes) for 3 iterations per volume on both.  The oracle's parallel loops
+    the headline volume in full on all threads, which also gives the parity of the GPU maps, and a
+    20-iteration sample on 1 thread; the small volume (32x32x16, 1 coil, 50 iterations, natural-order IC(0)) in
+    full on both; the 16 uneven volumes for 3 iterations per volume on both.  The oracle's parallel loops
     are those over independent voxels; its sums stay sequential, so every thread count gives the same bits."""
     import tempfile
 
@@ -188,24 +188,24 @@ def bench_cpu(args, vol, synth, batched_vols, headline):
     out = {"affinity_cpus": affinity, "threads_all": nall, "build": "gcc -O3 -march=native -fopenmp "
                                                                       "-ffp-contract=off"}
     nmask = int(vol.mask.sum())
-    # config 2: full solve on all threads (the parity reference), 20-iteration sample on one thread
+    # the headline volume: full solve on all threads (the parity reference), 20-iteration sample on one thread
     ref, t_all = run(vol, nall, vol.niter)
     _, t_one = run(vol, 1, 20)
-    out["config2"] = {"all_threads": {"value": nmask * vol.niter / t_all, "seconds": t_all, "niter": vol.niter},
+    out["headline"] = {"all_threads": {"value": nmask * vol.niter / t_all, "seconds": t_all, "niter": vol.niter},
                       "one_thread": {"value": nmask * 20 / t_one, "seconds": t_one, "niter": 20}}
-    log("cpu config 2: %.3e voxel-iterations/s on %d threads (100 iterations, %.1f s), %.3e on 1 thread "
-        "(20 iterations, %.1f s)" % (out["config2"]["all_threads"]["value"], nall, t_all,
-                                     out["config2"]["one_thread"]["value"], t_one))
-    # config 1
+    log("cpu headline volume: %.3e voxel-iterations/s on %d threads (100 iterations, %.1f s), %.3e on 1 thread "
+        "(20 iterations, %.1f s)" % (out["headline"]["all_threads"]["value"], nall, t_all,
+                                     out["headline"]["one_thread"]["value"], t_one))
+    # the small volume (32x32x16, 1 coil)
     tiny = synth.tiny_fieldmap()
     n1 = int(tiny.mask.sum())
     _, t1a = run(tiny, nall, tiny.niter, O.NATURAL, O.IC0)
     _, t11 = run(tiny, 1, tiny.niter, O.NATURAL, O.IC0)
-    out["config1"] = {"voxels": n1, "niter": tiny.niter, "all_threads": n1 * tiny.niter / t1a,
+    out["small_32x32x16"] = {"voxels": n1, "niter": tiny.niter, "all_threads": n1 * tiny.niter / t1a,
                       "one_thread": n1 * tiny.niter / t11}
-    log("cpu config 1: %.3e (all) / %.3e (1 thread) voxel-iterations/s" % (out["config1"]["all_threads"],
-                                                                        out["config1"]["one_thread"]))
-    # config 4: every volume, 3 iterations
+    log("cpu 32x32x16 volume: %.3e (all) / %.3e (1 thread) voxel-iterations/s" % (out["small_32x32x16"]["all_threads"],
+                                                                        out["small_32x32x16"]["one_thread"]))
+    # the 16 uneven volumes: every volume, 3 iterations
     vols4 = batched_vols if batched_vols is not None else synth.batched(16)
     n4 = sum(int(v.mask.sum()) for v in vols4)
     rates = {}
@@ -214,8 +214,8 @@ def bench_cpu(args, vol, synth, batched_vols, headline):
         for v in vols4:
             t += run(v, nt, 3, O.REDBLACK, O.IC0)[1]
         rates[name] = n4 * 3 / t
-    out["config4"] = dict(voxels=n4, niter=3, **rates)
-    log("cpu config 4: %.3e (all) / %.3e (1 thread) voxel-iterations/s" % (rates["all_threads"],
+    out["batch16"] = dict(voxels=n4, niter=3, **rates)
+    log("cpu 16 uneven volumes: %.3e (all) / %.3e (1 thread) voxel-iterations/s" % (rates["all_threads"],
                                                                         rates["one_thread"]))
     O.set_threads(nall)
     # parity of the GPU maps against the oracle's full run (Sec. III Algorithm, same fixed iteration counts)
@@ -234,11 +234,11 @@ def bench_cpu(args, vol, synth, batched_vols, headline):
     if "mix" in headline and "f64" in headline:
         par["mix_vs_f64"] = map_diff(headline["mix"][0], headline["f64"][0], m, thr)
         log("parity MIX vs F64: rms %.3e Hz" % par["mix_vs_f64"]["rms_hz"])
-    cpu = {"value": out["config2"]["all_threads"]["value"], "unit": "voxel-iterations/s", "cores": nall,
+    cpu = {"value": out["headline"]["all_threads"]["value"], "unit": "voxel-iterations/s", "cores": nall,
            "kind": "oracle",
-           "sample": "config 2 as the GPU step (%dx%dx%d, 8 coils, coil combination, eq. (w0) start, %d NCG "
+           "sample": "the headline problem as the GPU step (%dx%dx%d, 8 coils, coil combination, eq. (w0) start, %d NCG "
                      "iterations, FP64 C, %d threads, %.1f s); one thread: %.3e voxel-iterations/s on 20 "
-                     "iterations" % (vol.shape + (vol.niter, nall, t_all, out["config2"]["one_thread"]["value"])),
+                     "iterations" % (vol.shape + (vol.niter, nall, t_all, out["headline"]["one_thread"]["value"])),
            "detail": out}
     return cpu, par
 
