@@ -556,6 +556,34 @@ def bench_large(args, fmap, synth, torch, prec):
     return res
 
 
+def bench_ict(args, fmap, synth, torch, prec):
+    """The headline volume (128x128x64, 8 coils) preconditioned by IC with a drop tolerance (IC_t, natural
+    order, fill bounded to the level-1 pattern, tolerance 1e-3 x H_max): the factor and both triangular
+    solves are formed every iteration, one launch per level of the schedule (699 levels each way)."""
+    log("ict: generating 128x128x64")
+    vol = synth.mid_fieldmap()
+    niter = 10
+    y, s, m = fmap.to_device(vol)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = torch.zeros(vol.shape, dtype=torch.float64, device="cuda")
+    with fmap.Plan(fmap.params_for(vol, precision=prec, ordering=fmap.NATURAL, precond=fmap.ICT, niter=niter)) as plan:
+        plan.solve(y, s, m, out=out)
+        torch.cuda.synchronize()
+        ms_solve = time_solve(plan, fmap, y, s, m, out, 1, torch)
+        ev0.record(stream)
+        plan.iterate(niter, out=out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_loop = ev0.elapsed_time(ev1)
+        plan.status()
+        n = plan.mask_count()
+    res = {"grid": list(vol.shape), "voxels": n, "niter": niter, "ms_per_solve": ms_solve, "loop_ms": ms_loop,
+           "ms_per_iteration": ms_loop / niter, "loop_voxel_iterations_per_s": n * niter / (ms_loop * 1e-3)}
+    log("ict: solve %.2f ms, %.3f ms per iteration" % (ms_solve, res["ms_per_iteration"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -566,9 +594,9 @@ def main():
     ap.add_argument("--precond", choices=["ic0", "diag", "none"], default="ic0")
     ap.add_argument("--mask", choices=["full", "paper"], default="full")
     ap.add_argument("--shape", default="128,128,64")
-    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2", "large", "copy"],
+    ap.add_argument("--workload", choices=["fieldmap", "batched", "waterfat", "order2", "large", "ict", "copy"],
                     default="fieldmap",
-                    help="fieldmap: the headline line (default); batched / waterfat / order2 / large: only that "
+                    help="fieldmap: the headline line (default); batched / waterfat / order2 / large / ict: only that "
                          "workload; copy: a plain 1 GiB device copy (the calibration of the traffic counters)")
     ap.add_argument("--kernel-iters", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -614,6 +642,11 @@ def main():
             value, ms = res["ic0_color3"]["value"], res["ic0_color3"]["ms_per_solve"]
             wl = "field map 128x128x64, 8 coils, 3 echoes, second-order finite differences, 100 NCG iterations, " \
                  "IC(0) in three-colour order, %s" % args.precision.upper()
+        elif args.workload == "ict":
+            res = bench_ict(args, fmap, synth, torch, prec)
+            value, ms = res["loop_voxel_iterations_per_s"], res["ms_per_solve"]
+            wl = "field map 128x128x64 (%d unknowns), 8 coils, 3 echoes, %d NCG iterations, IC_t (natural order, " \
+                 "level-1 fill, 1e-3 H_max), %s" % (res["voxels"], res["niter"], args.precision.upper())
         elif args.workload == "large":
             res = bench_large(args, fmap, synth, torch, prec)
             value, ms = res["loop_voxel_iterations_per_s"], res["ms_per_solve"]
