@@ -134,17 +134,23 @@ static int row2(const fmo_problem *pb, const uint8_t *mask, int64_t j, int a) {
 
 /* Colours of the elimination order (natural order: one). */
 static int ncolours(const fmo_problem *pb) {
-  return pb->ordering == FMO_ORDER_REDBLACK ? 2 : (pb->ordering == FMO_ORDER_COLOR3 ? 3 : 1);
+  return (pb->ordering == FMO_ORDER_REDBLACK || pb->ordering == FMO_ORDER_BLOCKRB)
+             ? 2
+             : (pb->ordering == FMO_ORDER_COLOR3 ? 3 : 1);
 }
 
-/* Position of voxel j in the elimination order: colour (x+y+z) mod ncolours
- * first, natural index within a colour. */
+/* Position of voxel j in the elimination order: its colour first ((x+y+z)
+ * mod ncolours, or the tile colour of block red-black), then the natural
+ * index (natural order inside a tile: a tile's voxels keep their relative
+ * natural order, and tiles of one colour are not coupled). */
 static int64_t rank_of(const fmo_problem *pb, int64_t j) {
   const int nc = ncolours(pb);
   if (nc == 1) return j;
   const int64_t nz = pb->nz, ny = pb->ny;
   const int64_t z = j % nz, y = (j / nz) % ny, x = j / (ny * nz);
-  return ((x + y + z) % nc) * nvox(pb) + j;
+  const int64_t colour =
+      pb->ordering == FMO_ORDER_BLOCKRB ? (x / FMO_BLOCK + y / FMO_BLOCK) % 2 : (x + y + z) % nc;
+  return colour * nvox(pb) + j;
 }
 
 /* Voxels in elimination order (in-mask only); returns the count. */
@@ -327,7 +333,7 @@ int fmo_init_fieldmap(int64_t n, int32_t L, const double *zhat, const double *te
 static int check_pb(const fmo_problem *pb) {
   if (!pb || pb->nx < 1 || pb->ny < 1 || pb->nz < 1 || pb->necho < 2 || !pb->te || !pb->gam ||
       !(pb->beta >= 0) || pb->nmls < 1 || pb->niter < 0 || pb->ordering < FMO_ORDER_NATURAL ||
-      pb->ordering > FMO_ORDER_COLOR3)
+      pb->ordering > FMO_ORDER_BLOCKRB)
     return FMO_ERR_ARG;
   return FMO_OK;
 }
@@ -380,6 +386,14 @@ int fmo_laplacian(const fmo_problem *pb, const uint8_t *mask, const double *f, d
   return FMO_OK;
 }
 
+/* Colours that are independent sets of the 7-point stencil (red-black and
+ * three-colour orders), whose voxels a sweep may visit in any order within
+ * the colour; block red-black couples the voxels of a tile, so it sweeps in
+ * elimination order like natural order. */
+static int independent_colours(const fmo_problem *pb) {
+  return ncolours(pb) > 1 && pb->ordering != FMO_ORDER_BLOCKRB;
+}
+
 /* End of the run of colour `colour` that starts at position q0 of the
  * elimination order. */
 static int64_t colour_end(const fmo_problem *pb, const int64_t *order, int64_t q0, int64_t cnt, int colour) {
@@ -410,7 +424,7 @@ int fmo_factor(const fmo_problem *pb, const uint8_t *mask, const double *curv, d
   const int64_t cnt = build_order(pb, mask, order);
   int st = FMO_OK;
   for (int64_t j = 0; j < n; ++j) piv[j] = 0.0;
-  if (ncolours(pb) == 1) {
+  if (!independent_colours(pb)) {
     for (int64_t q = 0; q < cnt; ++q) {
       const int64_t j = order[q];
       piv[j] = pivot_of(pb, mask, curv, piv, j);
@@ -481,7 +495,7 @@ int fmo_apply(const fmo_problem *pb, const uint8_t *mask, const double *piv, con
    * (independent sets of the 7-point stencil), so its voxels may be visited
    * in any order */
   int64_t bound[4] = {0, cnt, cnt, cnt};
-  const int nc = ncolours(pb);
+  const int nc = independent_colours(pb) ? ncolours(pb) : 1;
   for (int colour = 0; colour < nc && nc > 1; ++colour)
     bound[colour + 1] = colour_end(pb, order, bound[colour], cnt, colour);
   /* forward: (P + E) x = g, E = strictly lower part of H (entries -beta) */

@@ -35,10 +35,14 @@ extern "C" {
 
 enum { FMO_OK = 0, FMO_ERR_ARG = 1, FMO_ERR_NOT_PD = 5, FMO_ERR_NONFINITE = 6 };
 /* Elimination orders of IC(0): natural (lexicographic, z fastest), red-black
- * ((x+y+z) mod 2, then natural) and three-colour ((x+y+z) mod 3, then
+ * ((x+y+z) mod 2, then natural), three-colour ((x+y+z) mod 3, then
  * natural; no two voxels of a colour are pattern neighbours of the
- * second-order C^T C, whose neighbours lie 1 or 2 steps along an axis). */
-enum { FMO_ORDER_NATURAL = 0, FMO_ORDER_REDBLACK = 1, FMO_ORDER_COLOR3 = 2 };
+ * second-order C^T C, whose neighbours lie 1 or 2 steps along an axis) and
+ * block red-black (the (x, y) plane cut into tiles of FMO_BLOCK x FMO_BLOCK
+ * whole columns coloured (x/FMO_BLOCK + y/FMO_BLOCK) mod 2, colour 0 first,
+ * natural order inside a tile; tiles of one colour share no face). */
+enum { FMO_ORDER_NATURAL = 0, FMO_ORDER_REDBLACK = 1, FMO_ORDER_COLOR3 = 2, FMO_ORDER_BLOCKRB = 3 };
+enum { FMO_BLOCK = 8 };
 /* IC(0), diag(H), none, or incomplete Cholesky with a drop tolerance (IC_t,
  * natural order; see fmo_ict_factor). */
 enum { FMO_PRECOND_IC0 = 0, FMO_PRECOND_DIAG = 1, FMO_PRECOND_NONE = 2, FMO_PRECOND_ICT = 3 };

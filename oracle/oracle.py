@@ -15,7 +15,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "libfmo.so")
 _lib = None
 
-NATURAL, REDBLACK, COLOR3 = 0, 1, 2
+NATURAL, REDBLACK, COLOR3, BLOCKRB = 0, 1, 2, 3
+BLOCK = 8  # tile edge (whole columns) of the block red-black order
 IC0, DIAG, NONE, ICT = 0, 1, 2, 3
 ICT_MAXOFF = 16
 TR = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)

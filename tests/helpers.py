@@ -44,7 +44,10 @@ def elimination_order(shape, mask, ordering):
     if ordering == 0:
         return idx[m]
     x, y, z = np.unravel_index(idx, shape)
-    col = (x + y + z) & 1
+    if ordering == 3:  # block red-black: tiles of 8 x 8 whole columns, natural order inside a tile
+        col = (x // 8 + y // 8) & 1
+    else:
+        col = (x + y + z) & 1
     return np.concatenate([idx[m & (col == 0)], idx[m & (col == 1)]])
 
 

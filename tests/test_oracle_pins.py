@@ -225,10 +225,11 @@ def test_huber_curvature_is_tight_single_pair():
 # Sec. III-B: IC(0) of H = D + beta C^T C (precon_hess, precon).
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK, O.BLOCKRB])
 def test_ic0_matches_textbook_incomplete_cholesky(ordering):
     rng = np.random.default_rng(6)
-    shape = (4, 5, 3)
+    # block red-black needs several 8 x 8-column tiles: 3 x 2 tiles, two of them partial
+    shape = (18, 10, 2) if ordering == O.BLOCKRB else (4, 5, 3)
     mask = (rng.uniform(size=shape) < 0.85).astype(np.uint8)
     curv = rng.uniform(0, 0.1, shape) * mask
     beta = 0.1
@@ -371,7 +372,7 @@ def _noise_free_constant(shape, beta, L=3, ncoil=2, seed=14, fval=37.5):
     return y, s, te, fval
 
 
-@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK, O.BLOCKRB])
 def test_noise_free_constant_field_is_recovered(ordering):
     shape = (5, 4, 6)
     rng = np.random.default_rng(15)
@@ -407,7 +408,7 @@ def test_converged_point_is_a_newton_fixed_point():
     assert np.linalg.eigvalsh(Hx).min() > 0  # a strict local minimum
 
 
-@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK])
+@pytest.mark.parametrize("ordering", [O.NATURAL, O.REDBLACK, O.BLOCKRB])
 def test_cost_is_monotone_per_outer_and_line_search_step(ordering):
     vol = synth.tiny_fieldmap(mask="paper")
     out = O.run_volume(vol, ordering=ordering, niter=20, want_mls=True)
@@ -487,3 +488,20 @@ def test_diagonal_and_identity_preconditioners():
     out = O.run_volume(vol, precond=O.NONE, niter=1, f0=f0)
     tr = out["trace"]
     assert abs(tr[0, O.TR["ztg"]] + tr[0, O.TR["gnorm2"]]) <= 1e-12 * tr[0, O.TR["gnorm2"]]
+
+
+def test_block_red_black_within_one_tile_is_natural_order():
+    """A volume inside one 8 x 8-column tile has one colour: block red-black is natural order there,
+    pivots and preconditioned residual bit for bit."""
+    rng = np.random.default_rng(61)
+    shape = (8, 7, 5)
+    mask = (rng.uniform(size=shape) < 0.9).astype(np.uint8)
+    curv = rng.uniform(0, 0.1, shape) * mask
+    g = rng.normal(size=shape) * mask
+    out = {}
+    for ordering in (O.NATURAL, O.BLOCKRB):
+        pb = _fm_problem(shape, [0, 1e-3], 0.1, ordering=ordering)
+        piv = O.factor(pb, mask, curv)
+        out[ordering] = (piv, O.apply(pb, mask, piv, g))
+    assert np.array_equal(out[O.NATURAL][0], out[O.BLOCKRB][0])
+    assert np.array_equal(out[O.NATURAL][1], out[O.BLOCKRB][1])
