@@ -67,8 +67,17 @@ typedef enum { FM_PREC_F64 = 0, FM_PREC_MIX = 1 } fm_precision;
  * colour in natural order), or three-colour ((x+y+z) mod 3 = 0, 1, 2, each in
  * natural order; the order for second-order differences, whose 13-point
  * C^T C couples voxels 1 and 2 steps apart and so couples voxels of one
- * red-black colour; built for reg_order 2 with IC(0) only). */
-typedef enum { FM_ORDER_NATURAL = 0, FM_ORDER_REDBLACK = 1, FM_ORDER_COLOR3 = 2 } fm_ordering;
+ * red-black colour; built for reg_order 2 with IC(0) only), or block
+ * red-black (the (x, y) plane cut into tiles of 8 x 8 whole columns coloured
+ * (x/8 + y/8) mod 2, colour 0 first, natural order inside a tile: between
+ * natural and red-black order in quality, two launches per sweep; built for
+ * reg_order 1; fm_adjoint preconditions its CG in natural order there). */
+typedef enum {
+  FM_ORDER_NATURAL = 0,
+  FM_ORDER_REDBLACK = 1,
+  FM_ORDER_COLOR3 = 2,
+  FM_ORDER_BLOCKRB = 3
+} fm_ordering;
 /* Preconditioner: IC(0), diag(H), none, or incomplete Cholesky with a drop
  * tolerance (IC_t, the preconditioner of Sec. III-B and Sec. IV: entries of
  * the factor below ict_factor x H_max, scaled by their column's 1-norm, are

@@ -384,6 +384,23 @@ fm_status enqueue_precond(fm_plan *p, const T *gsrc, hipStream_t s, Recorder *re
     FM_LAUNCH(FM_K_PRECOND_B, (fm::k_ic3_bwd0<T>), dim3(p->sgrid), dim3(fm::kNT), s, pargs(p, p->q++), gsrc);
     FM_LAUNCH_CHECK();
     set_parts(p, 0, 0);
+  } else if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_BLOCKRB) {
+    // block red-black: forward colour 0, colour 1; backward colour 1, colour 0 (a volume of one
+    // tile column and row has no colour-1 tile)
+    const fm::Wavefront &w = p->wf;
+    FM_LAUNCH(FM_K_PRECOND_A, fm::k_icb_fwd<T>, dim3(w.nblk[0]), dim3(64), s, pargs(p, p->q++), w, gsrc, 0);
+    FM_LAUNCH_CHECK();
+    set_parts(p, 0, 0);
+    if (w.nblk[1] > 0) {
+      FM_LAUNCH(FM_K_PRECOND_A, fm::k_icb_fwd<T>, dim3(w.nblk[1]), dim3(64), s, pargs(p, p->q++), w, gsrc, 1);
+      FM_LAUNCH_CHECK();
+      FM_LAUNCH(FM_K_PRECOND_B, fm::k_icb_bwd<T>, dim3(w.nblk[1]), dim3(64), s, pargs(p, p->q++), w, gsrc, 1);
+      FM_LAUNCH_CHECK();
+      set_parts(p, w.nblk[1], 2);
+    }
+    FM_LAUNCH(FM_K_PRECOND_B, fm::k_icb_bwd<T>, dim3(w.nblk[0]), dim3(64), s, pargs(p, p->q++), w, gsrc, 0);
+    FM_LAUNCH_CHECK();
+    set_parts(p, w.nblk[0], 2);
   } else if (p->prm.precond == FM_PRECOND_IC0) {
     if (p->prm.ordering == FM_ORDER_NATURAL) {
       FM_LAUNCH(FM_K_PRECOND_A, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, pargs(p, p->q++), p->wf, gsrc);
@@ -420,6 +437,7 @@ uint64_t launches_per_iteration(const fm_plan *p) {
   uint64_t precond_dir = 2;
   if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_NATURAL) precond_dir = 3;
   if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_COLOR3) precond_dir = 5;
+  if (p->prm.precond == FM_PRECOND_IC0 && p->prm.ordering == FM_ORDER_BLOCKRB) precond_dir = p->wf.nblk[1] > 0 ? 5 : 3;
   return 1 + precond_dir + (uint64_t)(p->prm.nmls - 1);
 }
 
@@ -629,7 +647,8 @@ fm_status validate(const fm_params *p) {
   if (p->nmls < 1) return fail(FM_ERR_ARG, "nmls must be >= 1");
   if (p->model != FM_FIELDMAP && p->model != FM_WATERFAT) return fail(FM_ERR_ARG, "bad model");
   if (p->precision != FM_PREC_F64 && p->precision != FM_PREC_MIX) return fail(FM_ERR_ARG, "bad precision");
-  if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK && p->ordering != FM_ORDER_COLOR3)
+  if (p->ordering != FM_ORDER_NATURAL && p->ordering != FM_ORDER_REDBLACK && p->ordering != FM_ORDER_COLOR3 &&
+      p->ordering != FM_ORDER_BLOCKRB)
     return fail(FM_ERR_ARG, "bad ordering");
   if (p->precond < FM_PRECOND_IC0 || p->precond > FM_PRECOND_ICT) return fail(FM_ERR_ARG, "bad preconditioner");
   if (p->reg_order < 0 || p->reg_order > 2) return fail(FM_ERR_ARG, "reg_order must be 1 or 2");
@@ -990,7 +1009,8 @@ fm_status adj_enqueue_iteration(fm_plan *p, uint64_t &q, int &np, int &nv, int k
     np = p->sgrid;
     nv = 2;
   } else if (p->prm.precond == FM_PRECOND_IC0) {
-    if (p->prm.ordering == FM_ORDER_NATURAL) {
+    // natural-order IC(0) also for block red-black plans (v does not depend on the preconditioner)
+    if (p->prm.ordering == FM_ORDER_NATURAL || p->prm.ordering == FM_ORDER_BLOCKRB) {
       FM_LAUNCH(0, fm::k_ic_fwd_wave<T>, dim3(p->wf.ntiles), dim3(64), s, adj_precond_args<T>(p, q++, np, nv), p->wf, r);
       FM_LAUNCH_CHECK();
       np = 0;
@@ -1214,6 +1234,20 @@ fm_status fm_plan_create(const fm_params *prm, fm_plan **out) {
         hipMemset(cnt, 0, sizeof(uint32_t) * 2 + sizeof(int32_t) * 2 * (size_t)w.ntiles) != hipSuccess)
       return cleanup(fail(FM_ERR_HIP, "wavefront tables upload failed"));
     w.order = (const int2 *)ord;
+    // block red-black: the tiles of each colour (ti + tj) mod 2
+    std::vector<int2> blk[2];
+    for (int ti = 0; ti < w.ntx; ++ti)
+      for (int tj = 0; tj < w.nty; ++tj) blk[(ti + tj) & 1].push_back(make_int2(ti, tj));
+    for (int c = 0; c < 2; ++c) {
+      w.nblk[c] = (int32_t)blk[c].size();
+      w.blk[c] = nullptr;
+      if (blk[c].empty()) continue;
+      void *bp = nullptr;
+      FM_ALLOC(bp, sizeof(int2) * blk[c].size());
+      if (hipMemcpy(bp, blk[c].data(), sizeof(int2) * blk[c].size(), hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(FM_ERR_HIP, "block tables upload failed"));
+      w.blk[c] = (const int2 *)bp;
+    }
     w.ticket_fwd = (uint32_t *)cnt;
     w.ticket_bwd = (uint32_t *)cnt + 1;
     w.prog_fwd = (int32_t *)((uint32_t *)cnt + 2);

@@ -35,6 +35,8 @@ struct Wavefront {
   int32_t ntiles;
   uint32_t *ticket_fwd, *ticket_bwd;
   int32_t *prog_fwd, *prog_bwd;  // [ntiles] steps completed
+  const int2 *blk[2];    // block red-black: the tiles of colour (ti + tj) mod 2 = 0 and 1
+  int32_t nblk[2];
 };
 
 __device__ __forceinline__ int load_prog(const int32_t *p) {
@@ -284,6 +286,202 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
   // per-tile partial sums, indexed by tile so the order is fixed
   store_partials_at<2, 64>(acc, tile.x * w.nty + tile.y, w.ntiles, a.pout);
   put_state(st, a.sout, PK_DOTS, w.ntiles);
+}
+
+// ---------------------------------------------------------------------------
+// IC(0) in block red-black order: the tiles of one colour ((ti + tj) mod 2,
+// colour 0 first) share no face, and inside a tile the order is natural, so
+// one launch sweeps every tile of a colour at once, one wavefront per tile as
+// above, with no waits between tiles.  A voxel's earlier neighbours are its
+// in-tile -x, -y, -z neighbours and, in a colour-1 tile, every neighbour
+// across a tile face (colour 0, factored by the previous launch); its later
+// neighbours are the in-tile +x, +y, +z ones and, in a colour-0 tile, every
+// neighbour across a face.  Forward: colour 0, then colour 1; backward:
+// colour 1 (the first half of the dot products), then colour 0 (the rest).
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_icb_fwd(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc, int colour) {
+  const Geo g = a.geo;
+  const State st = take_state<64, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[a.par & 1];
+  const int2 tile = w.blk[colour][blockIdx.x];
+  const bool second = colour == 1;  // its face neighbours come earlier
+  const int lane = threadIdx.x, la = lane >> 3, lb = lane & 7;
+  const int x = tile.x * kTile + la, y = tile.y * kTile + lb;
+  const bool col_ok = x < g.nx && y < g.ny;
+  const int nz = g.nz;
+  const int64_t jcol = col_ok ? ((int64_t)x * g.ny + y) * nz : 0;
+  // offset of this lane's neighbour across the tile face along x and y (0: none used)
+  const int64_t ox = (second && col_ok) ? (la == 0 && x > 0 ? -g.sx : (la == kTile - 1 && x + 1 < g.nx ? g.sx : 0)) : 0;
+  const int64_t oy = (second && col_ok) ? (lb == 0 && y > 0 ? -g.sy : (lb == kTile - 1 && y + 1 < g.ny ? g.sy : 0)) : 0;
+  const double beta = a.beta, b2 = a.beta * a.beta;
+  const int nsteps = nz + 2 * (kTile - 1);
+  int bad = 0;
+  uint32_t rc[kStepU];
+  double rh[kStepU], rbr[kStepU], rbyr[kStepU];
+  T rg[kStepU], rbx[kStepU], rbyx[kStepU];
+  // the fixed per-step load pattern of the natural sweep (clamped addresses)
+  auto prefetch = [&](int S, int u) {
+    const int z = S - la - lb;
+    const bool ok = col_ok && z >= 0 && z < nz;
+    const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
+    const uint32_t c = a.code[j];
+    rc[u] = ok ? c : 0u;
+    rh[u] = (double)a.D[j] + beta * nb_deg(c);
+    rg[u] = gg[j];
+    rbr[u] = a.ipiv[j + ox];
+    rbx[u] = a.X[j + ox];
+    rbyr[u] = a.ipiv[j + oy];
+    rbyx[u] = a.X[j + oy];
+  };
+#pragma unroll
+  for (int u = 0; u < kStepU; ++u) prefetch(u, u);
+  double r_prev = 0.0, x_prev = 0.0, r_out = 0.0, x_out = 0.0;
+  for (int S0 = 0; S0 < nsteps; S0 += kStepU) {
+#pragma unroll
+    for (int u = 0; u < kStepU; ++u) {
+      const int S = S0 + u;
+      const double rx_l = shfl_up_t(r_out, kTile), xx_l = shfl_up_t(x_out, kTile);
+      const double ry_l = shfl_up_t(r_out, 1), xy_l = shfl_up_t(x_out, 1);
+      const int z = S - la - lb;
+      const uint32_t c = rc[u];
+      double r_new = 0.0, x_new = 0.0;
+      if (col_ok && z >= 0 && z < nz) {
+        if (c & NB_SELF) {
+          double sr = 0.0, sx = 0.0;
+          if (c & NB_XM) {
+            if (la) {
+              sr += rx_l;
+              sx += xx_l;
+            } else if (second) {
+              sr += rbr[u];
+              sx += (double)rbx[u];
+            }
+          }
+          if ((c & NB_XP) && la == kTile - 1 && second) {
+            sr += rbr[u];
+            sx += (double)rbx[u];
+          }
+          if (c & NB_YM) {
+            if (lb) {
+              sr += ry_l;
+              sx += xy_l;
+            } else if (second) {
+              sr += rbyr[u];
+              sx += (double)rbyx[u];
+            }
+          }
+          if ((c & NB_YP) && lb == kTile - 1 && second) {
+            sr += rbyr[u];
+            sx += (double)rbyx[u];
+          }
+          if (c & NB_ZM) {
+            sr += r_prev;
+            sx += x_prev;
+          }
+          const double piv = rh[u] - b2 * sr;
+          double ip = 1.0 / piv;
+          if (!(piv > 0.0)) {
+            bad = 1;
+            ip = 0.0;
+          }
+          r_new = ip;
+          x_new = (double)(T)(((double)rg[u] + beta * sx) * ip);
+        }
+        r_prev = r_new;
+        x_prev = x_new;
+      }
+      // out-of-range lanes store into the padding before voxel 0
+      const int64_t js = (col_ok && z >= 0 && z < nz) ? jcol + z : (int64_t)-1;
+      a.ipiv[js] = r_new;
+      a.X[js] = (T)x_new;
+      r_out = r_new;
+      x_out = x_new;
+      if (S + kStepU < nsteps) prefetch(S + kStepU, u);
+    }
+  }
+  if (bad) set_status(a.status, 5);
+  put_state(st, a.sout, PK_NONE, 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_icb_bwd(IterArgs<T> a, Wavefront w, const T *__restrict__ gsrc, int colour) {
+  const Geo g = a.geo;
+  const State st = take_state<64, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
+  const T *__restrict__ gg = gsrc ? gsrc : a.G[a.par & 1];
+  const T *__restrict__ gp = a.G[(a.par + 1) & 1];
+  const int2 tile = w.blk[colour][blockIdx.x];
+  const bool first = colour == 0;  // its face neighbours come later
+  const int lane = threadIdx.x, la = lane >> 3, lb = lane & 7;
+  const int ra = kTile - 1 - la, rb = kTile - 1 - lb;  // skew of the mirrored sweep
+  const int x = tile.x * kTile + la, y = tile.y * kTile + lb;
+  const bool col_ok = x < g.nx && y < g.ny;
+  const int nz = g.nz;
+  const int64_t jcol = col_ok ? ((int64_t)x * g.ny + y) * nz : 0;
+  const int64_t ox = (first && col_ok) ? (la == 0 && x > 0 ? -g.sx : (la == kTile - 1 && x + 1 < g.nx ? g.sx : 0)) : 0;
+  const int64_t oy = (first && col_ok) ? (lb == 0 && y > 0 ? -g.sy : (lb == kTile - 1 && y + 1 < g.ny ? g.sy : 0)) : 0;
+  const double beta = a.beta;
+  const int nsteps = nz + 2 * (kTile - 1);
+  uint32_t rc[kStepU];
+  double rip[kStepU];
+  T rx[kStepU], rg[kStepU], rgp[kStepU], rbx[kStepU], rby[kStepU];
+  auto prefetch = [&](int S, int u) {
+    const int z = nz - 1 - (S - ra - rb);
+    const bool ok = col_ok && z >= 0 && z < nz;
+    const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
+    const uint32_t c = a.code[j];
+    rc[u] = ok ? c : 0u;
+    rip[u] = a.ipiv[j];
+    rx[u] = a.X[j];
+    rg[u] = gg[j];
+    rgp[u] = gp[j];
+    rbx[u] = a.P[j + ox];
+    rby[u] = a.P[j + oy];
+  };
+#pragma unroll
+  for (int u = 0; u < kStepU; ++u) prefetch(u, u);
+  double p_prev = 0.0, p_out = 0.0;
+  double acc[2] = {0.0, 0.0};
+  for (int S0 = 0; S0 < nsteps; S0 += kStepU) {
+#pragma unroll
+    for (int u = 0; u < kStepU; ++u) {
+      const int S = S0 + u;
+      const double px_l = __shfl_down(p_out, (unsigned)kTile, 64);
+      const double py_l = __shfl_down(p_out, 1u, 64);
+      const int z = nz - 1 - (S - ra - rb);
+      const uint32_t c = rc[u];
+      double p_new = 0.0;
+      if (col_ok && z >= 0 && z < nz) {
+        if (c & NB_SELF) {
+          double s = 0.0;
+          if ((c & NB_XM) && la == 0 && first) s += (double)rbx[u];
+          if (c & NB_XP) {
+            if (la < kTile - 1)
+              s += px_l;
+            else if (first)
+              s += (double)rbx[u];
+          }
+          if ((c & NB_YM) && lb == 0 && first) s += (double)rby[u];
+          if (c & NB_YP) {
+            if (lb < kTile - 1)
+              s += py_l;
+            else if (first)
+              s += (double)rby[u];
+          }
+          if (c & NB_ZP) s += p_prev;
+          p_new = (double)(T)((double)rx[u] + beta * s * rip[u]);
+          acc[0] += (double)rg[u] * p_new;
+          acc[1] += (double)rgp[u] * p_new;
+        }
+        p_prev = p_new;
+      }
+      a.P[(col_ok && z >= 0 && z < nz) ? jcol + z : (int64_t)-1] = (T)p_new;
+      p_out = p_new;
+      if (S + kStepU < nsteps) prefetch(S + kStepU, u);
+    }
+  }
+  store_partials_at<2, 64>(acc, (int)blockIdx.x, (int)gridDim.x, a.pout);
+  put_state(st, a.sout, first ? PK_DOTS : PK_DOTS_A, (int)gridDim.x);
 }
 
 }  // namespace fm

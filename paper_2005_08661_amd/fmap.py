@@ -19,7 +19,7 @@ FM_MAX_ECHO = 16
 FM_MAX_PEAK = 16
 FIELDMAP, WATERFAT = 0, 1
 F64, MIX = 0, 1
-NATURAL, REDBLACK, COLOR3 = 0, 1, 2
+NATURAL, REDBLACK, COLOR3, BLOCKRB = 0, 1, 2, 3
 IC0, DIAG, NONE, ICT = 0, 1, 2, 3
 ICT_MAXOFF = 11
 TRACE_COLS = dict(cost=0, gtp=1, mu=2, restart=3, alpha=4, ztg=5, B=6, gnorm2=7)

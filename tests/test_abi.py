@@ -99,6 +99,7 @@ def header_enums():
 def test_binding_constants_match_the_header():
     e = header_enums()
     pairs = {"FM_ORDER_NATURAL": fmap.NATURAL, "FM_ORDER_REDBLACK": fmap.REDBLACK, "FM_ORDER_COLOR3": fmap.COLOR3,
+             "FM_ORDER_BLOCKRB": fmap.BLOCKRB,
              "FM_PREC_F64": fmap.F64, "FM_PREC_MIX": fmap.MIX, "FM_FIELDMAP": fmap.FIELDMAP,
              "FM_WATERFAT": fmap.WATERFAT, "FM_SCHED_AUTO": fmap.SCHED_AUTO, "FM_SCHED_STREAM": fmap.SCHED_STREAM,
              "FM_SCHED_RESIDENT": fmap.SCHED_RESIDENT}
