@@ -327,11 +327,12 @@ def bench_batched(args, fmap, synth, torch, prec):
 def bench_convergence(args, fmap, vol, y, s, m, torch, prec, ms_iter_rb):
     """Iterations and time to reach a relative cost gap (Psi_i - Psi*) / (Psi_0 - Psi*) of 1e-3 and
     1e-4 for each preconditioner on the benchmark volume, Psi* = the least cost of the 400-iteration F64
-    solves (IC(0) in natural and red-black order, IC_t with the level-1 pattern and the tolerance
-    1e-3 x H_max in natural order, diag(H), none).  Time = iterations x the measured time of one
+    solves (IC(0) in natural, red-black and block red-black order, IC_t with the level-1 pattern and the
+    tolerance 1e-3 x H_max in natural order, diag(H), none).  Time = iterations x the measured time of one
     iteration of that preconditioner."""
     log("convergence: 400-iteration traces per preconditioner")
     runs = {"ic0_natural": (fmap.NATURAL, fmap.IC0), "ic0_redblack": (fmap.REDBLACK, fmap.IC0),
+            "ic0_blockrb": (fmap.BLOCKRB, fmap.IC0),
             "ict_natural": (fmap.NATURAL, fmap.ICT), "diag": (fmap.NATURAL, fmap.DIAG),
             "none": (fmap.NATURAL, fmap.NONE)}
     traces, ms_iter = {}, {}

@@ -5,6 +5,8 @@ configurations it times them in, against the FP64 oracle (Sec. III Algorithm):
     MIX, red-black IC(0), the plan's default schedule (resident), 100 iterations;
   - natural-order IC(0) (the paper's own ordering; the pipelined wavefront sweeps) at
     128x128x64, 8 coils, MIX, 100 iterations;
+  - block red-black IC(0) (one wavefront per 8x8-column tile, a launch per colour) at the same
+    size, MIX, 100 iterations;
   - second-order differences with IC(0) in three-colour order at 128x128x64, MIX, the first 5
     iterations (the oracle's general IC(0) takes about 6 s per iteration at this size).
 
@@ -69,6 +71,14 @@ def test_natural_order_full_size_matches_oracle():
     f, tr, _ = gpu_solve(vol, ordering=fmap.NATURAL)
     ref = O.run_volume(vol, O.NATURAL)
     check(vol, f, tr, ref, "natural order vs oracle")
+
+
+def test_block_red_black_full_size_matches_oracle():
+    vol = synth.mid_fieldmap()
+    say("block red-black IC(0) 128x128x64, MIX, 100 iterations")
+    f, tr, _ = gpu_solve(vol, ordering=fmap.BLOCKRB)
+    ref = O.run_volume(vol, O.BLOCKRB)
+    check(vol, f, tr, ref, "block red-black vs oracle")
 
 
 def test_second_order_full_size_first_iterations_match_oracle():
