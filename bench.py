@@ -41,7 +41,7 @@ def bytes_per_voxel(kclass, precision, L, ordering, precond):
         return 1 + 2 * L * t + 2 * t
     if kclass == "dir":        # read code, p, z_prev, f, D; write z
         return 1 + 5 * t
-    if precond == "ic0" and ordering == "natural":
+    if precond == "ic0" and ordering in ("natural", "blockrb"):  # block red-black: same arrays, one tile at a time
         if kclass == "precond_a":  # read code, D, g; write 1/P (8), x
             return 1 + 3 * t + 8
         if kclass == "precond_b":  # read code, x, 1/P (8), g, g_prev; write p
@@ -93,6 +93,8 @@ def kernel_symbol(kclass, ordering, precond, nz):
             return "k_diag"
         if ordering == "natural":
             return "k_ic_fwd_wave" if kclass == "precond_a" else "k_ic_bwd_wave"
+        if ordering == "blockrb":
+            return "k_icb_fwd" if kclass == "precond_a" else "k_icb_bwd"
         pair = "_pair" if nz % 2 == 0 else ""  # pair-mapped passes when every column length is even
         return ("k_rb_black" if kclass == "precond_a" else "k_rb_red_dir") + pair
     return KERNEL_SYMBOL[kclass]
@@ -176,7 +178,7 @@ def bench_cpu(args, vol, synth, batched_vols, headline):
     nall = host_threads()
     affinity = len(os.sched_getaffinity(0))
     log("cpu baseline: oracle -O3 -march=native, 1 and %d threads (%d CPUs in the affinity mask)" % (nall, affinity))
-    order = O.NATURAL if args.ordering == "natural" else O.REDBLACK
+    order = {"natural": O.NATURAL, "redblack": O.REDBLACK, "blockrb": O.BLOCKRB}[args.ordering]
     pc = {"ic0": O.IC0, "diag": O.DIAG, "none": O.NONE}[args.precond]
 
     def run(v, nt, niter, ordering=order, precond=pc):
@@ -591,7 +593,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["mix", "f64"], default="mix")
-    ap.add_argument("--ordering", choices=["natural", "redblack"], default="redblack")
+    ap.add_argument("--ordering", choices=["natural", "redblack", "blockrb"], default="redblack")
     ap.add_argument("--precond", choices=["ic0", "diag", "none"], default="ic0")
     ap.add_argument("--mask", choices=["full", "paper"], default="full")
     ap.add_argument("--shape", default="128,128,64")
@@ -667,7 +669,7 @@ def main():
     log("generating %s volume (%s mask)" % (shape, args.mask))
     vol = synth.mid_fieldmap(mask=args.mask, shape=shape)
     prec = fmap.MIX if args.precision == "mix" else fmap.F64
-    order = fmap.NATURAL if args.ordering == "natural" else fmap.REDBLACK
+    order = {"natural": fmap.NATURAL, "redblack": fmap.REDBLACK, "blockrb": fmap.BLOCKRB}[args.ordering]
     pc = {"ic0": fmap.IC0, "diag": fmap.DIAG, "none": fmap.NONE}[args.precond]
     y, s, m = fmap.to_device(vol)
     plan = fmap.Plan(fmap.params_for(vol, precision=prec, ordering=order, precond=pc))
