@@ -71,7 +71,8 @@ typedef enum { FM_PREC_F64 = 0, FM_PREC_MIX = 1 } fm_precision;
  * red-black (the (x, y) plane cut into tiles of 8 x 8 whole columns coloured
  * (x/8 + y/8) mod 2, colour 0 first, natural order inside a tile: between
  * natural and red-black order in quality, two launches per sweep; built for
- * reg_order 1; fm_adjoint preconditions its CG in natural order there). */
+ * reg_order 1 and ny * nz * 80 below 2^30, FM_ERR_SHAPE otherwise; fm_adjoint
+ * preconditions its CG in natural order there). */
 typedef enum {
   FM_ORDER_NATURAL = 0,
   FM_ORDER_REDBLACK = 1,

@@ -654,6 +654,8 @@ fm_status validate(const fm_params *p) {
   if (p->reg_order < 0 || p->reg_order > 2) return fail(FM_ERR_ARG, "reg_order must be 1 or 2");
   if (p->reg_order == 2 && p->precond == FM_PRECOND_IC0 && p->ordering != FM_ORDER_COLOR3)
     return fail(FM_ERR_ARG, "IC(0) with second-order differences is built in three-colour order (FM_ORDER_COLOR3)");
+  if (p->ordering == FM_ORDER_BLOCKRB && (int64_t)p->ny * p->nz * 80 >= ((int64_t)1 << 30))
+    return fail(FM_ERR_SHAPE, "block red-black order needs ny * nz * 80 below 2^30 (its per-tile views use 32-bit offsets)");
   if (p->ordering == FM_ORDER_COLOR3 && (p->reg_order != 2 || p->precond != FM_PRECOND_IC0))
     return fail(FM_ERR_ARG, "three-colour order is built for IC(0) with second-order differences only");
   if (p->precond == FM_PRECOND_ICT) {

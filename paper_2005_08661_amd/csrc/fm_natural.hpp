@@ -111,19 +111,20 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
   int bad = 0;
   // ring of prefetched inputs, slot = step % kStepU
   uint32_t rc[kStepU];
-  double rh[kStepU], rbr[kStepU], rbyr[kStepU];
+  double rbr[kStepU], rbyr[kStepU];
+  T rd[kStepU];
   T rg[kStepU], rbx[kStepU], rbyx[kStepU];
   // Every lane issues the same loads at every step (addresses clamped into the
   // arrays, values masked afterwards), so the number of memory operations per
   // step is fixed and the compiler can wait for exactly the slot it consumes
-  // instead of draining every outstanding load.
+  // instead of draining every outstanding load.  The ring holds the loaded
+  // values only: anything computed from them at prefetch time would make the
+  // wavefront wait for the load it has just issued.
   auto prefetch = [&](int S, int u) {
     const int z = S - la - lb;
-    const bool ok = col_ok && z >= 0 && z < nz;
     const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
-    const uint32_t c = a.code[j];
-    rc[u] = ok ? c : 0u;
-    rh[u] = (double)a.D[j] + beta * nb_deg(c);
+    rc[u] = a.code[j];
+    rd[u] = a.D[j];
     rg[u] = gg[j];
     const int64_t jx = (col_ok && la == 0 && x > 0) ? j - g.sx : j;  // tile boundary: the -x neighbour column
     const int64_t jy = (col_ok && lb == 0 && y > 0) ? j - g.sy : j;
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
             sr += r_prev;
             sx += x_prev;
           }
-          const double piv = rh[u] - b2 * sr;
+          const double piv = ((double)rd[u] + beta * nb_deg(c)) - b2 * sr;
           double ip = 1.0 / piv;
           if (!(piv > 0.0)) {
             bad = 1;
@@ -234,10 +235,8 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
   // same fixed per-step load pattern as the forward sweep
   auto prefetch = [&](int S, int u) {
     const int z = nz - 1 - (S - ra - rb);
-    const bool ok = col_ok && z >= 0 && z < nz;
     const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
-    const uint32_t c = a.code[j];
-    rc[u] = ok ? c : 0u;
+    rc[u] = a.code[j];
     rip[u] = ld_coh(a.ipiv + j);
     rx[u] = ld_coh(a.X + j);
     rg[u] = gg[j];
@@ -299,9 +298,69 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
 // neighbour across a face.  Forward: colour 0, then colour 1; backward:
 // colour 1 (the first half of the dot products), then colour 0 (the rest).
 
+// Per-tile views of the per-voxel arrays for the block sweeps: x-planes
+// [q0, q1) of the volume (the tile's planes and one more on each side, all
+// that a tile reads or writes) as a raw buffer with 32-bit byte offsets.  The
+// hardware's range check reads 0 for an offset at or past the view's end and
+// drops a store there; lanes without a voxel, face reads where there is no
+// neighbour across the face, and stores of steps outside the column address
+// the element one past the view (kPast below) and so need no masking.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_view(const void *base, uint32_t nbytes) {
+  // descriptor word 3 of an untyped buffer on gfx9-family GPUs
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)nbytes, 0x00020000);
+}
+__device__ __forceinline__ uint32_t view_u8(__amdgpu_buffer_rsrc_t r, uint32_t e) {
+  return __builtin_amdgcn_raw_buffer_load_b8(r, e, 0, 0);
+}
+__device__ __forceinline__ float view_ld(__amdgpu_buffer_rsrc_t r, uint32_t e, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, e * 4u, 0, 0));
+}
+__device__ __forceinline__ double view_ld(__amdgpu_buffer_rsrc_t r, uint32_t e, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, e * 8u, 0, 0));
+}
+__device__ __forceinline__ void view_st(__amdgpu_buffer_rsrc_t r, uint32_t e, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, e * 4u, 0, 0);
+}
+__device__ __forceinline__ void view_st(__amdgpu_buffer_rsrc_t r, uint32_t e, double v) {
+  using B64 = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0u, 0, 0));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(B64, v), r, e * 8u, 0, 0);
+}
+
+// The views and lane geometry of one tile (both sweeps).  Element indices are
+// relative to plane q0; the host keeps ny * nz * 80 (10 planes of 8-byte
+// elements) below 2^30, so no offset computed here wraps.
+struct TileView {
+  int la, lb;
+  bool col_ok;
+  uint32_t past;    // one past the view: reads 0, stores dropped
+  uint32_t e0;      // this lane's column at z = 0 (past for a lane outside the volume)
+  uint32_t dx, dy;  // offset to the neighbour across an x / y tile face, or one that lands past the view
+  int64_t jq;       // voxel index of the view's first element
+  uint32_t nq;      // elements in the view
+};
+
+__device__ __forceinline__ TileView tile_view(const Geo &g, int2 tile, bool faces) {
+  TileView v;
+  v.la = (int)threadIdx.x >> 3;
+  v.lb = (int)threadIdx.x & 7;
+  const int x = tile.x * kTile + v.la, y = tile.y * kTile + v.lb;
+  v.col_ok = x < g.nx && y < g.ny;
+  const int q0 = max(0, tile.x * kTile - 1), q1 = min(g.nx, tile.x * kTile + kTile + 1);
+  v.jq = (int64_t)q0 * g.sx;
+  v.nq = (uint32_t)((int64_t)(q1 - q0) * g.sx);
+  v.past = v.nq;
+  v.e0 = v.col_ok ? (uint32_t)((int64_t)(x - q0) * g.sx + (int64_t)y * g.sy) : v.past;
+  // e0 + z + far >= past for every z >= 0: a face read with no neighbour reads 0
+  const uint32_t far = v.nq;
+  const bool fx = faces && v.col_ok && ((v.la == 0 && x > 0) || (v.la == kTile - 1 && x + 1 < g.nx));
+  const bool fy = faces && v.col_ok && ((v.lb == 0 && y > 0) || (v.lb == kTile - 1 && y + 1 < g.ny));
+  v.dx = fx ? (uint32_t)(v.la == 0 ? -g.sx : g.sx) : far;
+  v.dy = fy ? (uint32_t)(v.lb == 0 ? -g.sy : g.sy) : far;
+  return v;
+}
+
 // Prefetch distance of the block sweeps, in steps.  With one wavefront per CU
-// there is no occupancy to lose: 16 measured 2.7% faster than 4 and 1.3% than
-// 8; 32 needs every VGPR in FP64 and was 8% slower.
+// there is no occupancy to lose: 16 measured faster than 8, 12 and 24.
 constexpr int kStepB = 16;
 
 template <typename T>
@@ -309,35 +368,28 @@ __global__ __launch_bounds__(64) void k_icb_fwd(IterArgs<T> a, Wavefront w, cons
   const Geo g = a.geo;
   const State st = take_state<64, 4>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
   const T *__restrict__ gg = gsrc ? gsrc : a.G[a.par & 1];
-  const int2 tile = w.blk[colour][blockIdx.x];
-  const bool second = colour == 1;  // its face neighbours come earlier
-  const int lane = threadIdx.x, la = lane >> 3, lb = lane & 7;
-  const int x = tile.x * kTile + la, y = tile.y * kTile + lb;
-  const bool col_ok = x < g.nx && y < g.ny;
-  const int nz = g.nz;
-  const int64_t jcol = col_ok ? ((int64_t)x * g.ny + y) * nz : 0;
-  // offset of this lane's neighbour across the tile face along x and y (0: none used)
-  const int64_t ox = (second && col_ok) ? (la == 0 && x > 0 ? -g.sx : (la == kTile - 1 && x + 1 < g.nx ? g.sx : 0)) : 0;
-  const int64_t oy = (second && col_ok) ? (lb == 0 && y > 0 ? -g.sy : (lb == kTile - 1 && y + 1 < g.ny ? g.sy : 0)) : 0;
+  // a colour-1 tile's neighbours across its faces come earlier (colour 0)
+  const TileView v = tile_view(g, w.blk[colour][blockIdx.x], colour == 1);
+  const int la = v.la, lb = v.lb, nz = g.nz;
+  const auto vcode = plane_view(a.code + v.jq, v.nq), vd = plane_view(a.D + v.jq, v.nq * (uint32_t)sizeof(T));
+  const auto vg = plane_view(gg + v.jq, v.nq * (uint32_t)sizeof(T));
+  const auto vip = plane_view(a.ipiv + v.jq, v.nq * 8u), vx = plane_view(a.X + v.jq, v.nq * (uint32_t)sizeof(T));
   const double beta = a.beta, b2 = a.beta * a.beta;
   const int nsteps = nz + 2 * (kTile - 1);
-  int bad = 0;
+  bool bad = false;
   uint32_t rc[kStepB];
-  double rh[kStepB], rbr[kStepB], rbyr[kStepB];
-  T rg[kStepB], rbx[kStepB], rbyx[kStepB];
-  // the fixed per-step load pattern of the natural sweep (clamped addresses)
+  double rbr[kStepB], rbyr[kStepB];
+  T rd[kStepB], rg[kStepB], rbx[kStepB], rbyx[kStepB];
+  // raw loads only (z clamped into the column; the step masks what is outside it)
   auto prefetch = [&](int S, int u) {
-    const int z = S - la - lb;
-    const bool ok = col_ok && z >= 0 && z < nz;
-    const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
-    const uint32_t c = a.code[j];
-    rc[u] = ok ? c : 0u;
-    rh[u] = (double)a.D[j] + beta * nb_deg(c);
-    rg[u] = gg[j];
-    rbr[u] = a.ipiv[j + ox];
-    rbx[u] = a.X[j + ox];
-    rbyr[u] = a.ipiv[j + oy];
-    rbyx[u] = a.X[j + oy];
+    const uint32_t e = v.e0 + (uint32_t)min(max(S - la - lb, 0), nz - 1);
+    rc[u] = view_u8(vcode, e);
+    rd[u] = view_ld(vd, e, T());
+    rg[u] = view_ld(vg, e, T());
+    rbr[u] = view_ld(vip, e + v.dx, double());
+    rbx[u] = view_ld(vx, e + v.dx, T());
+    rbyr[u] = view_ld(vip, e + v.dy, double());
+    rbyx[u] = view_ld(vx, e + v.dy, T());
   };
 #pragma unroll
   for (int u = 0; u < kStepB; ++u) prefetch(u, u);
@@ -349,57 +401,33 @@ __global__ __launch_bounds__(64) void k_icb_fwd(IterArgs<T> a, Wavefront w, cons
       const double rx_l = shfl_up_t(r_out, kTile), xx_l = shfl_up_t(x_out, kTile);
       const double ry_l = shfl_up_t(r_out, 1), xy_l = shfl_up_t(x_out, 1);
       const int z = S - la - lb;
-      const uint32_t c = rc[u];
-      double r_new = 0.0, x_new = 0.0;
-      if (col_ok && z >= 0 && z < nz) {
-        if (c & NB_SELF) {
-          double sr = 0.0, sx = 0.0;
-          if (c & NB_XM) {
-            if (la) {
-              sr += rx_l;
-              sx += xx_l;
-            } else if (second) {
-              sr += rbr[u];
-              sx += (double)rbx[u];
-            }
-          }
-          if ((c & NB_XP) && la == kTile - 1 && second) {
-            sr += rbr[u];
-            sx += (double)rbx[u];
-          }
-          if (c & NB_YM) {
-            if (lb) {
-              sr += ry_l;
-              sx += xy_l;
-            } else if (second) {
-              sr += rbyr[u];
-              sx += (double)rbyx[u];
-            }
-          }
-          if ((c & NB_YP) && lb == kTile - 1 && second) {
-            sr += rbyr[u];
-            sx += (double)rbyx[u];
-          }
-          if (c & NB_ZM) {
-            sr += r_prev;
-            sx += x_prev;
-          }
-          const double piv = rh[u] - b2 * sr;
-          double ip = 1.0 / piv;
-          if (!(piv > 0.0)) {
-            bad = 1;
-            ip = 0.0;
-          }
-          r_new = ip;
-          x_new = (double)(T)(((double)rg[u] + beta * sx) * ip);
-        }
-        r_prev = r_new;
-        x_prev = x_new;
-      }
-      // out-of-range lanes store into the padding before voxel 0
-      const int64_t js = (col_ok && z >= 0 && z < nz) ? jcol + z : (int64_t)-1;
-      a.ipiv[js] = r_new;
-      a.X[js] = (T)x_new;
+      const bool inr = v.col_ok && z >= 0 && z < nz;
+      const uint32_t c = inr ? rc[u] : 0u;
+      const bool self = (c & NB_SELF) != 0;
+      // earlier neighbours in the order -x, +x, -y, +y, -z, each term 0 where
+      // there is none: a voxel outside the mask holds 0 in 1/P and x (its lane
+      // stores 0) and a face read with no neighbour reads 0
+      double sr = 0.0, sx = 0.0;
+      sr += la ? rx_l : rbr[u];
+      sx += la ? xx_l : (double)rbx[u];
+      sr += la == kTile - 1 ? rbr[u] : 0.0;
+      sx += la == kTile - 1 ? (double)rbx[u] : 0.0;
+      sr += lb ? ry_l : rbyr[u];
+      sx += lb ? xy_l : (double)rbyx[u];
+      sr += lb == kTile - 1 ? rbyr[u] : 0.0;
+      sx += lb == kTile - 1 ? (double)rbyx[u] : 0.0;
+      sr += r_prev;
+      sx += x_prev;
+      const double piv = ((double)rd[u] + beta * nb_deg(c)) - b2 * sr;
+      const bool pos = piv > 0.0;
+      bad |= self && !pos;
+      const double r_new = (self && pos) ? 1.0 / piv : 0.0;
+      const double x_new = self ? (double)(T)(((double)rg[u] + beta * sx) * r_new) : 0.0;
+      r_prev = r_new;
+      x_prev = x_new;
+      const uint32_t es = inr ? v.e0 + (uint32_t)z : v.past;
+      view_st(vip, es, r_new);
+      view_st(vx, es, (T)x_new);
       r_out = r_new;
       x_out = x_new;
       if (S + kStepB < nsteps) prefetch(S + kStepB, u);
@@ -415,33 +443,28 @@ __global__ __launch_bounds__(64) void k_icb_bwd(IterArgs<T> a, Wavefront w, cons
   const State st = take_state<64, 2>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status);
   const T *__restrict__ gg = gsrc ? gsrc : a.G[a.par & 1];
   const T *__restrict__ gp = a.G[(a.par + 1) & 1];
-  const int2 tile = w.blk[colour][blockIdx.x];
-  const bool first = colour == 0;  // its face neighbours come later
-  const int lane = threadIdx.x, la = lane >> 3, lb = lane & 7;
+  const bool first = colour == 0;  // its neighbours across the faces come later
+  const TileView v = tile_view(g, w.blk[colour][blockIdx.x], first);
+  const int la = v.la, lb = v.lb, nz = g.nz;
   const int ra = kTile - 1 - la, rb = kTile - 1 - lb;  // skew of the mirrored sweep
-  const int x = tile.x * kTile + la, y = tile.y * kTile + lb;
-  const bool col_ok = x < g.nx && y < g.ny;
-  const int nz = g.nz;
-  const int64_t jcol = col_ok ? ((int64_t)x * g.ny + y) * nz : 0;
-  const int64_t ox = (first && col_ok) ? (la == 0 && x > 0 ? -g.sx : (la == kTile - 1 && x + 1 < g.nx ? g.sx : 0)) : 0;
-  const int64_t oy = (first && col_ok) ? (lb == 0 && y > 0 ? -g.sy : (lb == kTile - 1 && y + 1 < g.ny ? g.sy : 0)) : 0;
+  const uint32_t nt = v.nq * (uint32_t)sizeof(T);
+  const auto vcode = plane_view(a.code + v.jq, v.nq), vip = plane_view(a.ipiv + v.jq, v.nq * 8u);
+  const auto vx = plane_view(a.X + v.jq, nt), vg = plane_view(gg + v.jq, nt), vgp = plane_view(gp + v.jq, nt);
+  const auto vp = plane_view(a.P + v.jq, nt);
   const double beta = a.beta;
   const int nsteps = nz + 2 * (kTile - 1);
   uint32_t rc[kStepB];
   double rip[kStepB];
   T rx[kStepB], rg[kStepB], rgp[kStepB], rbx[kStepB], rby[kStepB];
   auto prefetch = [&](int S, int u) {
-    const int z = nz - 1 - (S - ra - rb);
-    const bool ok = col_ok && z >= 0 && z < nz;
-    const int64_t j = jcol + (z < 0 ? 0 : (z >= nz ? nz - 1 : z));
-    const uint32_t c = a.code[j];
-    rc[u] = ok ? c : 0u;
-    rip[u] = a.ipiv[j];
-    rx[u] = a.X[j];
-    rg[u] = gg[j];
-    rgp[u] = gp[j];
-    rbx[u] = a.P[j + ox];
-    rby[u] = a.P[j + oy];
+    const uint32_t e = v.e0 + (uint32_t)min(max(nz - 1 - (S - ra - rb), 0), nz - 1);
+    rc[u] = view_u8(vcode, e);
+    rip[u] = view_ld(vip, e, double());
+    rx[u] = view_ld(vx, e, T());
+    rg[u] = view_ld(vg, e, T());
+    rgp[u] = view_ld(vgp, e, T());
+    rbx[u] = view_ld(vp, e + v.dx, T());
+    rby[u] = view_ld(vp, e + v.dy, T());
   };
 #pragma unroll
   for (int u = 0; u < kStepB; ++u) prefetch(u, u);
@@ -454,33 +477,22 @@ __global__ __launch_bounds__(64) void k_icb_bwd(IterArgs<T> a, Wavefront w, cons
       const double px_l = __shfl_down(p_out, (unsigned)kTile, 64);
       const double py_l = __shfl_down(p_out, 1u, 64);
       const int z = nz - 1 - (S - ra - rb);
-      const uint32_t c = rc[u];
-      double p_new = 0.0;
-      if (col_ok && z >= 0 && z < nz) {
-        if (c & NB_SELF) {
-          double s = 0.0;
-          if ((c & NB_XM) && la == 0 && first) s += (double)rbx[u];
-          if (c & NB_XP) {
-            if (la < kTile - 1)
-              s += px_l;
-            else if (first)
-              s += (double)rbx[u];
-          }
-          if ((c & NB_YM) && lb == 0 && first) s += (double)rby[u];
-          if (c & NB_YP) {
-            if (lb < kTile - 1)
-              s += py_l;
-            else if (first)
-              s += (double)rby[u];
-          }
-          if (c & NB_ZP) s += p_prev;
-          p_new = (double)(T)((double)rx[u] + beta * s * rip[u]);
-          acc[0] += (double)rg[u] * p_new;
-          acc[1] += (double)rgp[u] * p_new;
-        }
-        p_prev = p_new;
-      }
-      a.P[(col_ok && z >= 0 && z < nz) ? jcol + z : (int64_t)-1] = (T)p_new;
+      const bool inr = v.col_ok && z >= 0 && z < nz;
+      const uint32_t c = inr ? rc[u] : 0u;
+      const bool self = (c & NB_SELF) != 0;
+      // later neighbours in the order -x, +x, -y, +y, +z (p is 0 outside the
+      // mask, a face read with no neighbour reads 0)
+      double s = 0.0;
+      s += la == 0 ? (double)rbx[u] : 0.0;
+      s += la < kTile - 1 ? px_l : (double)rbx[u];
+      s += lb == 0 ? (double)rby[u] : 0.0;
+      s += lb < kTile - 1 ? py_l : (double)rby[u];
+      s += p_prev;
+      const double p_new = self ? (double)(T)((double)rx[u] + beta * s * rip[u]) : 0.0;
+      acc[0] += (self ? (double)rg[u] : 0.0) * p_new;
+      acc[1] += (self ? (double)rgp[u] : 0.0) * p_new;
+      p_prev = p_new;
+      view_st(vp, inr ? v.e0 + (uint32_t)z : v.past, (T)p_new);
       p_out = p_new;
       if (S + kStepB < nsteps) prefetch(S + kStepB, u);
     }

@@ -116,3 +116,19 @@ def test_adjoint_of_a_block_red_black_plan():
     rel = float(np.linalg.norm(v - vo) / np.linalg.norm(vo))
     say("  adjoint rel v %.2e, dbeta %.2e" % (rel, abs(out["dbeta"] - dbo) / abs(dbo)))
     assert rel < 1e-7 and abs(out["dbeta"] - dbo) <= 1e-7 * abs(dbo)
+
+
+def test_planes_too_large_for_the_tile_views_are_refused():
+    """The block sweeps address each tile's planes with 32-bit offsets: a plan whose ny * nz * 80
+    reaches 2^30 is refused with FM_ERR_SHAPE before any allocation; one just below is accepted."""
+    vol = VOLUMES["one_tile"]()
+    big = fmap.make_params((1, 4096, 4096), vol.ncoil, vol.te, vol.beta, niter=2, precision=fmap.MIX,
+                           ordering=fmap.BLOCKRB, precond=fmap.IC0)
+    with pytest.raises(fmap.FmapError) as ei:
+        fmap.Plan(big)
+    assert ei.value.status == 2
+    ok = fmap.make_params((1, 2048, 6000), vol.ncoil, vol.te, vol.beta, niter=2, precision=fmap.MIX,
+                          ordering=fmap.BLOCKRB, precond=fmap.IC0)
+    assert 2048 * 6000 * 80 < (1 << 30)
+    with fmap.Plan(ok):
+        pass
