@@ -399,23 +399,27 @@ __global__ __launch_bounds__(64) void k_icb_fwd(IterArgs<T> a, Wavefront w, cons
     for (int u = 0; u < kStepB; ++u) {
       const int S = S0 + u;
       const double rx_l = shfl_up_t(r_out, kTile), xx_l = shfl_up_t(x_out, kTile);
-      const double ry_l = shfl_up_t(r_out, 1), xy_l = shfl_up_t(x_out, 1);
+      // lane t-1 is in the same DPP row for every lane with lb > 0
+      const double ry_l = dpp_d<0x111>(r_out), xy_l = dpp_d<0x111>(x_out);  // row_shr:1
       const int z = S - la - lb;
       const bool inr = v.col_ok && z >= 0 && z < nz;
       const uint32_t c = inr ? rc[u] : 0u;
       const bool self = (c & NB_SELF) != 0;
       // earlier neighbours in the order -x, +x, -y, +y, -z, each term 0 where
       // there is none: a voxel outside the mask holds 0 in 1/P and x (its lane
-      // stores 0) and a face read with no neighbour reads 0
+      // stores 0) and a face read with no neighbour reads 0.  A lane's one x
+      // face is its -x neighbour (la = 0, in-tile term 0) or its +x one
+      // (la = 7), so adding it after the in-tile term keeps that order; the
+      // same for y.
       double sr = 0.0, sx = 0.0;
-      sr += la ? rx_l : rbr[u];
-      sx += la ? xx_l : (double)rbx[u];
-      sr += la == kTile - 1 ? rbr[u] : 0.0;
-      sx += la == kTile - 1 ? (double)rbx[u] : 0.0;
-      sr += lb ? ry_l : rbyr[u];
-      sx += lb ? xy_l : (double)rbyx[u];
-      sr += lb == kTile - 1 ? rbyr[u] : 0.0;
-      sx += lb == kTile - 1 ? (double)rbyx[u] : 0.0;
+      sr += la ? rx_l : 0.0;
+      sx += la ? xx_l : 0.0;
+      sr += rbr[u];
+      sx += (double)rbx[u];
+      sr += lb ? ry_l : 0.0;
+      sx += lb ? xy_l : 0.0;
+      sr += rbyr[u];
+      sx += (double)rbyx[u];
       sr += r_prev;
       sx += x_prev;
       const double piv = ((double)rd[u] + beta * nb_deg(c)) - b2 * sr;
@@ -475,18 +479,21 @@ __global__ __launch_bounds__(64) void k_icb_bwd(IterArgs<T> a, Wavefront w, cons
     for (int u = 0; u < kStepB; ++u) {
       const int S = S0 + u;
       const double px_l = __shfl_down(p_out, (unsigned)kTile, 64);
-      const double py_l = __shfl_down(p_out, 1u, 64);
+      // lane t+1 is in the same DPP row for every lane with lb < 7
+      const double py_l = dpp_d<0x101>(p_out);  // row_shl:1
       const int z = nz - 1 - (S - ra - rb);
       const bool inr = v.col_ok && z >= 0 && z < nz;
       const uint32_t c = inr ? rc[u] : 0u;
       const bool self = (c & NB_SELF) != 0;
       // later neighbours in the order -x, +x, -y, +y, +z (p is 0 outside the
       // mask, a face read with no neighbour reads 0)
+      // (a lane's one x face, -x at la = 0 or +x at la = 7, added before the
+      // in-tile +x term keeps that order; the same for y)
       double s = 0.0;
-      s += la == 0 ? (double)rbx[u] : 0.0;
-      s += la < kTile - 1 ? px_l : (double)rbx[u];
-      s += lb == 0 ? (double)rby[u] : 0.0;
-      s += lb < kTile - 1 ? py_l : (double)rby[u];
+      s += (double)rbx[u];
+      s += la < kTile - 1 ? px_l : 0.0;
+      s += (double)rby[u];
+      s += lb < kTile - 1 ? py_l : 0.0;
       s += p_prev;
       const double p_new = self ? (double)(T)((double)rx[u] + beta * s * rip[u]) : 0.0;
       acc[0] += (self ? (double)rg[u] : 0.0) * p_new;
