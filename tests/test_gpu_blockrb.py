@@ -132,3 +132,18 @@ def test_planes_too_large_for_the_tile_views_are_refused():
     assert 2048 * 6000 * 80 < (1 << 30)
     with fmap.Plan(ok):
         pass
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 9), (17, 1, 3), (1, 19, 2), (9, 9, 1), (8, 8, 1), (16, 3, 4)])
+def test_thin_volumes_match_oracle(shape):
+    """Volumes one voxel thick along one or two axes, and tiles with a single plane (nz = 1): the
+    sweeps' z skew, tile faces at the volume edge and one-column tiles, F64 against the oracle."""
+    vol = vol_of(shape, 5 + sum(shape), mask="full")
+    say("block red-black thin volume %s" % (shape,))
+    f, tr = fmap.solve_volume(vol, precision=fmap.F64, ordering=fmap.BLOCKRB)
+    ref = O.run_volume(vol, ordering=O.BLOCKRB)
+    msk = vol.mask.astype(bool)
+    err = rms(f - ref["f"], msk)
+    say("  rms vs oracle %.3e Hz" % err)
+    assert err < 1e-6
+    np.testing.assert_allclose(tr[:, 0], ref["trace"][:, O.TR["cost"]], rtol=1e-9)

@@ -35,7 +35,7 @@ def rms(a, m):
 
 
 ORDERS = {"natural": (fmap.NATURAL, fmap.IC0, O.NATURAL, O.IC0), "redblack": (fmap.REDBLACK, fmap.IC0, O.REDBLACK, O.IC0),
-          "diag": (fmap.NATURAL, fmap.DIAG, O.NATURAL, O.DIAG)}
+          "blockrb": (fmap.BLOCKRB, fmap.IC0, O.BLOCKRB, O.IC0), "diag": (fmap.NATURAL, fmap.DIAG, O.NATURAL, O.DIAG)}
 
 
 def volume(te, beta, niter, seed=960, shape=(13, 9, 7), ncoil=2):
@@ -84,7 +84,7 @@ def test_one_line_search_step(order):
     assert rms(f12 - ref["f"], vol.mask.astype(bool)) < 1e-6
 
 
-@pytest.mark.parametrize("order", ["natural", "redblack"])
+@pytest.mark.parametrize("order", ["natural", "redblack", "blockrb"])
 def test_zero_iterations_returns_the_start(order):
     say("niter = 0")
     vol = volume([0.0, 1.5e-3, 4.0e-3], 0.1, 0, seed=963)
@@ -129,7 +129,7 @@ LARGE = (320, 320, 160)
 TE = [0.0, 2.0e-3, 4.5e-3]
 
 
-@pytest.mark.parametrize("order,prec", [("redblack", "mix"), ("redblack", "f64"), ("natural", "f64")])
+@pytest.mark.parametrize("order,prec", [("redblack", "mix"), ("redblack", "f64"), ("natural", "f64"), ("blockrb", "mix")])
 def test_large_volume_converges_to_constant_field(order, prec):
     """Uniform magnitude, constant 37 Hz field, start at 0 Hz: exact recovery at 16.4 M voxels.
     (Magnitude 10, so that the data curvature is not negligible against beta C^T C: the constant

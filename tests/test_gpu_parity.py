@@ -192,8 +192,9 @@ def test_edge_cases_empty_mask_single_voxel_and_line():
     say("edge: empty mask")
     vol = ragged_volume()
     vol.mask[:] = 0
-    f, tr = fmap.solve_volume(vol, precision=fmap.F64)
-    assert np.all(f == 0) and np.all(np.isfinite(tr))
+    for order in (fmap.NATURAL, fmap.BLOCKRB):
+        f, tr = fmap.solve_volume(vol, precision=fmap.F64, ordering=order)
+        assert np.all(f == 0) and np.all(np.isfinite(tr))
     say("edge: 1x1x1")
     one = synth.fieldmap_volume((1, 1, 1), 1, [0.0, 2e-3], 0.0, 20, 3, 1, 60.0, False, 60.0)
     f, tr = fmap.solve_volume(one, precision=fmap.F64)
@@ -201,13 +202,13 @@ def test_edge_cases_empty_mask_single_voxel_and_line():
     assert abs(f.item() - ref["f"].item()) < 1e-9
     say("edge: 1x1x37 line")
     line = synth.fieldmap_volume((1, 1, 37), 2, [0.0, 1e-3, 3e-3], 0.3, 10, 4, 2, 60.0, False, 30.0)
-    for order in (fmap.NATURAL, fmap.REDBLACK):
+    for order in (fmap.NATURAL, fmap.REDBLACK, fmap.BLOCKRB):
         f, tr = fmap.solve_volume(line, precision=fmap.F64, ordering=order)
         ref = O.run_volume(line, ordering=order)
         assert rms(f - ref["f"], line.mask.astype(bool)) < 1e-9
 
 
-@pytest.mark.parametrize("ordering", ["natural", "redblack"])
+@pytest.mark.parametrize("ordering", ["natural", "redblack", "blockrb"])
 def test_zero_curvature_isolated_voxel_reports_not_pd(ordering):
     say("edge: isolated voxel with zero data -> NOT_PD (%s)" % ordering)
     vol = ragged_volume()
@@ -216,7 +217,7 @@ def test_zero_curvature_isolated_voxel_reports_not_pd(ordering):
     vol.mask[10, 7, 5] = 1  # isolated voxel (a red one: 10 + 7 + 5 is even)
     vol.y[:, :, 10, 7, 5] = 0
     y, s, m = fmap.to_device(vol)
-    order = fmap.NATURAL if ordering == "natural" else fmap.REDBLACK
+    order = {"natural": fmap.NATURAL, "redblack": fmap.REDBLACK, "blockrb": fmap.BLOCKRB}[ordering]
     with fmap.Plan(fmap.params_for(vol, precision=fmap.F64, ordering=order)) as plan:
         plan.solve(y, s, m)
         with pytest.raises(fmap.FmapError) as ei:
