@@ -482,11 +482,22 @@ int tail_nparts(const fm_plan *p) {
 // iteration's gradient pass (or by the final pass).
 template <typename T, int LMAX>
 fm_status enqueue_iteration(fm_plan *p, hipStream_t s, Recorder *rec = nullptr) {
-  // FP32, 2-6 echoes, columns a multiple of 4: the 16-byte-load passes (the gradient
-  // pass with the first-order stencil only; the line-search passes have none)
+  // FP32, 2-6 echoes, columns a multiple of 4: the 16-byte-load passes (gradient
+  // passes of either stencil; the line-search passes have none)
   const int quad = std::is_same<T, float>::value && p->prm.necho <= 6 && p->geo.nz % 4 == 0 ? p->prm.necho : 0;
   if (p->reg2) {
-    FM_LAUNCH(FM_K_GRAD, (fm::k_grad2<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
+    if (quad == 2)
+      FM_LAUNCH(FM_K_GRAD, (fm::k_grad2_q<2>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<float>(p, p->q++));
+    else if (quad == 3)
+      FM_LAUNCH(FM_K_GRAD, (fm::k_grad2_q<3>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<float>(p, p->q++));
+    else if (quad == 4)
+      FM_LAUNCH(FM_K_GRAD, (fm::k_grad2_q<4>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<float>(p, p->q++));
+    else if (quad == 5)
+      FM_LAUNCH(FM_K_GRAD, (fm::k_grad2_q<5>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<float>(p, p->q++));
+    else if (quad == 6)
+      FM_LAUNCH(FM_K_GRAD, (fm::k_grad2_q<6>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<float>(p, p->q++));
+    else
+      FM_LAUNCH(FM_K_GRAD, (fm::k_grad2<T, LMAX>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<T>(p, p->q++));
   } else if (quad == 2) {
     FM_LAUNCH(FM_K_GRAD, (fm::k_grad_q<2, false>), dim3(p->sgrid), dim3(fm::kNT), s, iter_args<float>(p, p->q++));
   } else if (quad == 3) {

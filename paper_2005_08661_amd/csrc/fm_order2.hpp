@@ -211,6 +211,145 @@ __global__ __launch_bounds__(kNT) void k_grad2(IterArgs<T> a0) {
   put_state(st, a.sout, PK_GRAD, vw.nb, vw.leader);
 }
 
+// The iteration's gradient pass of k_grad2 with four consecutive voxels of a
+// column per thread (FP32, NE echoes fixed at compile time, nz a multiple of
+// 4, single volumes): codes in 4-byte loads; f, z, the echo data and the
+// +-1, +-2 neighbours along x and y in 16-byte loads; the z neighbours inside
+// the four from registers and the two below and above in 8-byte loads.  Every
+// value is formed with the expressions k_grad2 uses, so f, g and D are the
+// same bits; only the order of the partial sums differs.
+template <int NE>
+__global__ __launch_bounds__(kNT) void k_grad2_q(IterArgs<float> a0) {
+  const VolView vw = vol_view<false>(a0);
+  const VArgs<float> a = at_volume<false>(a0, vw);
+  const Geo g = a.geo;
+  const int nq = (int)(g.n >> 2), stride = vw.nb * kNT, sx = (int)g.sx, sy = (int)g.sy;
+  const int64_t es = vw.es;
+  const float *__restrict__ fin = a.Fp;
+  const float *__restrict__ zin = a.Zp;
+  const Cm cmv(g);
+  const bool cm = a0.cm != 0;
+  // neighbour slots in the order -x, +x, -y, +y (d = 1 and d = 2 apart)
+  const int off[4] = {-sx, sx, -sy, sy};
+  uint32_t c4, cx[4];
+  float4 f4, z4, f1[4], z1[4], f2[4], z2[4], d4[NE][2];
+  float2 fzm, zzm, fzp, zzp;  // f, z of the two voxels below (j-2, j-1) and above (j+4, j+5)
+  uint32_t czm, czp;          // codes of voxels j-1 and j+4
+  auto load = [&](int q) {
+    const int j = 4 * q;
+    c4 = *reinterpret_cast<const uint32_t *>(a.code + j);
+    f4 = *reinterpret_cast<const float4 *>(fin + j);
+    z4 = *reinterpret_cast<const float4 *>(zin + j);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cx[k] = *reinterpret_cast<const uint32_t *>(a.code + j + off[k]);
+      f1[k] = *reinterpret_cast<const float4 *>(fin + j + off[k]);
+      z1[k] = *reinterpret_cast<const float4 *>(zin + j + off[k]);
+      f2[k] = *reinterpret_cast<const float4 *>(fin + j + 2 * off[k]);
+      z2[k] = *reinterpret_cast<const float4 *>(zin + j + 2 * off[k]);
+    }
+    fzm = *reinterpret_cast<const float2 *>(fin + j - 2);
+    zzm = *reinterpret_cast<const float2 *>(zin + j - 2);
+    fzp = *reinterpret_cast<const float2 *>(fin + j + 4);
+    zzp = *reinterpret_cast<const float2 *>(zin + j + 4);
+    czm = a.code[j - 1];
+    czp = a.code[j + 4];
+#pragma unroll
+    for (int l = 0; l < NE; ++l) {
+      const float4 *d = reinterpret_cast<const float4 *>(a.dat + (size_t)l * (size_t)es + j);
+      d4[l][0] = d[0];
+      d4[l][1] = d[1];
+    }
+  };
+  int q = vw.bl * kNT + (int)threadIdx.x;
+  const State st = take_state<kNT, 3>(a.sin, a.pin, a.nparts_in, a.nvals_in, a.beta, a.trace, a.status, vw.prow,
+                                      vw.leader);
+  const float alpha = (float)st.alpha;
+  const float beta = (float)a.beta;
+  constexpr int NP = NE * (NE - 1) / 2;
+  PairC<float> pc[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) pc[k] = uniform_pair(a.pairs[k]);
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (; q < nq; q += stride) {
+    load(q);
+    keep(c4);
+    keep(f4);
+    keep(z4);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      keep(cx[k]);
+      keep(f1[k]);
+      keep(z1[k]);
+      keep(f2[k]);
+      keep(z2[k]);
+    }
+    const int j = 4 * q;
+    const float fv[4] = {f4.x, f4.y, f4.z, f4.w}, zv[4] = {z4.x, z4.y, z4.z, z4.w};
+    // f and z of column voxels j-2 .. j+5
+    const float fc[8] = {fzm.x, fzm.y, f4.x, f4.y, f4.z, f4.w, fzp.x, fzp.y};
+    const float zc[8] = {zzm.x, zzm.y, z4.x, z4.y, z4.z, z4.w, zzp.x, zzp.y};
+    float fo[4], go[4], dout[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t cv = (c4 >> (8 * i)) & 0xffu;
+      const bool in = cv & NB_SELF;
+      const float fj = fv[i] + alpha * zv[i];
+      float v1[6], v2[6];
+      uint32_t cn[6];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float a1[4] = {f1[k].x, f1[k].y, f1[k].z, f1[k].w}, b1[4] = {z1[k].x, z1[k].y, z1[k].z, z1[k].w};
+        const float a2[4] = {f2[k].x, f2[k].y, f2[k].z, f2[k].w}, b2[4] = {z2[k].x, z2[k].y, z2[k].z, z2[k].w};
+        v1[k] = a1[i] + alpha * b1[i];
+        v2[k] = a2[i] + alpha * b2[i];
+        cn[k] = (cx[k] >> (8 * i)) & 0xffu;
+      }
+      v1[4] = fc[i + 1] + alpha * zc[i + 1];  // z - 1
+      v1[5] = fc[i + 3] + alpha * zc[i + 3];  // z + 1
+      v2[4] = fc[i] + alpha * zc[i];          // z - 2
+      v2[5] = fc[i + 4] + alpha * zc[i + 4];  // z + 2
+      cn[4] = i > 0 ? (c4 >> (8 * (i - 1))) & 0xffu : czm;
+      cn[5] = i < 3 ? (c4 >> (8 * (i + 1))) & 0xffu : czp;
+      const Rows2 R(cv, cn);
+      const float lap = ctc2(R, fj, v1, v2);
+      float rho[NE], tau[NE];
+#pragma unroll
+      for (int l = 0; l < NE; ++l) {
+        const float4 &d = d4[l][i >> 1];
+        rho[l] = (i & 1) ? d.z : d.x;
+        tau[l] = (i & 1) ? d.w : d.y;
+      }
+      float phi, dphi, curv;
+      voxel_terms<float, NE>(rho, tau, NE, pc, fj, phi, dphi, curv);
+      const float gj = dphi + beta * lap;
+      fo[i] = in ? fj : 0.f;
+      go[i] = in ? gj : 0.f;
+      dout[i] = in ? curv : 0.f;
+      acc[0] += in ? (double)phi : 0.0;
+      acc[1] += in ? (double)fj * (double)lap : 0.0;
+      acc[2] += in ? (double)gj * (double)gj : 0.0;
+      acc[3] += in ? (double)zv[i] * (double)gj : 0.0;
+    }
+    *reinterpret_cast<float4 *>(a.Fc + j) = make_float4(fo[0], fo[1], fo[2], fo[3]);
+    if (cm) {
+      // g and D of three-colour IC(0) plans in the colour-major layout, D also in voxel order
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int jw = cmv.of(j + i);
+        a.Gc[jw] = go[i];
+        a.D[jw] = dout[i];
+      }
+      *reinterpret_cast<float4 *>(a0.Dv + j) = make_float4(dout[0], dout[1], dout[2], dout[3]);
+    } else {
+      *reinterpret_cast<float4 *>(a.Gc + j) = make_float4(go[0], go[1], go[2], go[3]);
+      *reinterpret_cast<float4 *>(a.D + j) = make_float4(dout[0], dout[1], dout[2], dout[3]);
+    }
+  }
+  store_partials<4, kNT>(acc, a.pout);
+  put_state(st, a.sout, PK_GRAD, vw.nb, vw.leader);
+}
+
 // Diagonal (P = diag H with diag(C^T C) of the second-order operator) or
 // identity preconditioner (as k_diag).
 template <typename T, bool BATCH = false>
