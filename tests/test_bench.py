@@ -125,3 +125,18 @@ def test_roofline_limiter_from_measured_traffic(bench):
     assert e["limiter"].startswith("latency")
     e = bench.roofline_entry(kinfo, "resident", 25e9)
     assert e["limiter"] == "hbm bandwidth"
+
+
+def test_pass_model_of_the_block_red_black_sweeps(bench):
+    """Block red-black sweeps move the arrays of the natural-order sweeps (one tile at a time): forward
+    code, D, g in and 1/P (8 bytes), x out; backward code, x, 1/P, g, g_prev in and p out.  The profile
+    names the block kernels."""
+    for prec, t in (("mix", 4), ("f64", 8)):
+        assert bench.bytes_per_voxel("precond_a", prec, 3, "blockrb", "ic0") == 1 + 3 * t + 8
+        assert bench.bytes_per_voxel("precond_b", prec, 3, "blockrb", "ic0") == 1 + 4 * t + 8
+        for kc in ("precond_a", "precond_b"):
+            assert (bench.bytes_per_voxel(kc, prec, 3, "blockrb", "ic0")
+                    == bench.bytes_per_voxel(kc, prec, 3, "natural", "ic0"))
+    assert bench.kernel_symbol("precond_a", "blockrb", "ic0", 64) == "k_icb_fwd"
+    assert bench.kernel_symbol("precond_b", "blockrb", "ic0", 64) == "k_icb_bwd"
+    assert bench.kernel_symbol("precond_a", "natural", "ic0", 64) == "k_ic_fwd_wave"
