@@ -190,9 +190,11 @@ __global__ __launch_bounds__(64) void k_ic_fwd_wave(IterArgs<T> a, Wavefront w, 
       }
       r_out = r_new;
       x_out = x_new;
+      // publish the group before its last prefetch, so the wait for the
+      // stores does not also wait for a load issued just before it
+      if (u == kStepU - 1) publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);
       if (S + kStepU < nsteps) prefetch(S + kStepU, u);
     }
-    publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);
   }
   if (bad) set_status(a.status, 5);
   put_state(st, a.sout, PK_NONE, 0);
@@ -278,9 +280,9 @@ __global__ __launch_bounds__(64) void k_ic_bwd_wave(IterArgs<T> a, Wavefront w, 
       }
       st_coh(a.P + (col_ok && z >= 0 && z < nz ? jcol + z : (int64_t)-1), (T)p_new);  // see the forward sweep
       p_out = p_new;
+      if (u == kStepU - 1) publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);  // as forward
       if (S + kStepU < nsteps) prefetch(S + kStepU, u);
     }
-    publish_prog(my_prog, S0 + kStepU < nsteps ? S0 + kStepU : nsteps);
   }
   // per-tile partial sums, indexed by tile so the order is fixed
   store_partials_at<2, 64>(acc, tile.x * w.nty + tile.y, w.ntiles, a.pout);
